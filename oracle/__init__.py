@@ -1,0 +1,266 @@
+"""CPU ORACLE -- TEST INFRASTRUCTURE ONLY.
+
+Only ``tests/``, ``__graft_entry__.smoke()`` and the CPU-baseline leg of
+``bench.py`` may import this package.  The GPU product path never calls it.
+
+The LTL^T factorization, the Pfaffian from the factors and the solve are plain
+C (``ltlt_oracle.c``: the unblocked definition, FP64, no FMA contraction).  The
+remaining references are written here from their definitions:
+
+* ``pfaffian_bruteforce`` -- exact Pfaffian by expansion along the first row,
+  Pf(A) = sum_{j>=1} (-1)^{j+1} a_{0j} Pf(A with rows/cols 0,j removed)
+  (0-based j), in Python integers / fractions, for n <= 10;
+* ``skr2k`` -- C := beta C + alpha (A B^T - B A^T) on the strict lower triangle,
+  with one library matrix product per term;
+* ``reconstruct`` / ``recon_residual`` -- || P A P^T - L T L^T ||_F / (n ||A||_F);
+* ``backward_error`` -- max_j ||b_j - A x_j||_inf / (||A||_inf ||x_j||_inf + ||b_j||_inf).
+
+What pins the oracle (the tests under tests/test_oracle_*.py): a hand-derived
+4x4 example (tests/golden/worked_4x4.txt), brute-force Pfaffians for n <= 10,
+Pf(A)^2 = det(A) against LAPACK's LU determinant, closed forms for block
+diagonal / congruent / off-diagonal block matrices, scaling and transposition
+identities, the factor invariants (|L| <= 1, ipiv[j] >= j) and the
+reconstruction residual.
+"""
+from __future__ import annotations
+
+import ctypes
+import math
+import os
+import subprocess
+import threading
+from fractions import Fraction
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "ltlt_oracle.c")
+_LIB = os.path.join(_HERE, "liboracle.so")
+_lib = None
+_lock = threading.Lock()
+
+ENONFINITE = -103
+
+
+def build(force: bool = True) -> str:
+    if force or not os.path.exists(_LIB):
+        tmp = _LIB + ".tmp"
+        subprocess.check_call(["gcc", "-O2", "-fPIC", "-shared", "-pthread", "-ffp-contract=off",
+                               "-fno-fast-math", "-std=gnu11", "-o", tmp, _SRC, "-lm"])
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+def _load():
+    global _lib
+    with _lock:
+        if _lib is None:
+            if not os.path.exists(_LIB):
+                build(force=False)
+            lib = ctypes.CDLL(_LIB)
+            i64, dp = ctypes.c_int64, ctypes.POINTER(ctypes.c_double)
+            ip = ctypes.POINTER(ctypes.c_int32)
+            lib.oracle_ltlt.restype = ctypes.c_int
+            lib.oracle_ltlt.argtypes = [i64, dp, i64, ip, dp, dp, i64, ctypes.c_int]
+            lib.oracle_logpf.restype = None
+            lib.oracle_logpf.argtypes = [i64, ip, dp, dp, ctypes.POINTER(ctypes.c_int)]
+            lib.oracle_solve.restype = ctypes.c_int
+            lib.oracle_solve.argtypes = [i64, i64, dp, i64, ip, dp, dp, i64]
+            _lib = lib
+    return _lib
+
+
+def _dp(a):
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+
+
+def _ip(a):
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))
+
+
+class Factors:
+    """Result of ``ltlt``: factored array (L below the subdiagonal), ipiv, T, info, gaps."""
+
+    def __init__(self, LT, ipiv, T, info, gap):
+        self.LT, self.ipiv, self.T, self.info, self.gap = LT, ipiv, T, info, gap
+
+
+def ltlt(A: np.ndarray, nthreads: int = 1, nsteps: int = -1, want_gap: bool = True,
+         inplace: bool = False) -> Factors:
+    """Unblocked partially pivoted LTL^T of the strict lower triangle of A (FP64)."""
+    n = A.shape[0]
+    assert A.shape == (n, n)
+    LT = A if (inplace and A.flags.f_contiguous and A.dtype == np.float64) else np.array(A, dtype=np.float64, order="F")
+    ipiv = np.zeros(max(n, 1), dtype=np.int32)
+    T = np.zeros(max(n - 1, 1), dtype=np.float64)
+    gap = np.ones(max(n, 1), dtype=np.float64) if want_gap else None
+    lda = max(LT.strides[1] // 8, 1) if n > 0 else 1
+    info = _load().oracle_ltlt(n, _dp(LT), lda, _ip(ipiv), _dp(T),
+                               _dp(gap) if gap is not None else None, nsteps, nthreads)
+    return Factors(LT, ipiv[:n], T[:max(n - 1, 0)], int(info), gap[:max(n - 2, 0)] if gap is not None else None)
+
+
+def logpf_from_factors(n: int, ipiv: np.ndarray, T: np.ndarray):
+    """(log|Pf|, sign) from the factors; sign 0 and -inf for a singular matrix."""
+    ipiv = np.ascontiguousarray(ipiv, dtype=np.int32)
+    T = np.ascontiguousarray(T, dtype=np.float64)
+    if T.size == 0:
+        T = np.zeros(1)
+    if ipiv.size == 0:
+        ipiv = np.zeros(1, dtype=np.int32)
+    la = ctypes.c_double(0.0)
+    sg = ctypes.c_int(0)
+    _load().oracle_logpf(n, _ip(ipiv), _dp(T), ctypes.byref(la), ctypes.byref(sg))
+    return float(la.value), int(sg.value)
+
+
+def logpf(A: np.ndarray, nthreads: int = 1):
+    f = ltlt(A, nthreads=nthreads, want_gap=False)
+    if f.info == ENONFINITE:
+        return float("nan"), 0, f.info
+    la, s = logpf_from_factors(A.shape[0], f.ipiv, f.T)
+    return la, s, f.info
+
+
+def solve(LT: np.ndarray, ipiv: np.ndarray, T: np.ndarray, B: np.ndarray):
+    """X = P^T L^{-T} T^{-1} L^{-1} P B with the oracle's factors; returns (X, info)."""
+    n = LT.shape[0]
+    X = np.array(B, dtype=np.float64, order="F")
+    if X.ndim == 1:
+        X = X.reshape(-1, 1, order="F")
+    ipiv = np.ascontiguousarray(ipiv, dtype=np.int32)
+    Tc = np.ascontiguousarray(T, dtype=np.float64)
+    if Tc.size == 0:
+        Tc = np.zeros(1)
+    LTc = np.asfortranarray(LT, dtype=np.float64)
+    info = _load().oracle_solve(n, X.shape[1], _dp(LTc), max(n, 1), _ip(ipiv), _dp(Tc), _dp(X), max(n, 1))
+    return X, int(info)
+
+
+# ----------------------------------------------------------------------------
+# Definitions written out in Python/numpy
+# ----------------------------------------------------------------------------
+
+def pfaffian_bruteforce(A) -> Fraction:
+    """Exact Pfaffian by expansion along the first row (n <= 10).
+
+    ``A`` may hold Python ints, Fractions or floats (converted exactly to
+    Fractions); the strict upper triangle A[i][j], i < j, is used.
+    """
+    n = len(A)
+    assert n <= 12
+    M = [[Fraction(A[i][j]) for j in range(n)] for i in range(n)]
+
+    def pf(idx):
+        m = len(idx)
+        if m == 0:
+            return Fraction(1)
+        if m % 2 == 1:
+            return Fraction(0)
+        i0 = idx[0]
+        total = Fraction(0)
+        for t in range(1, m):
+            a = M[i0][idx[t]]
+            if a == 0:
+                continue
+            rest = idx[1:t] + idx[t + 1:]
+            term = a * pf(rest)
+            total += term if (t % 2 == 1) else -term
+        return total
+
+    return pf(list(range(n)))
+
+
+def full_from_lower(A: np.ndarray) -> np.ndarray:
+    """Skew matrix from the strict lower triangle of A."""
+    Lw = np.tril(np.asarray(A, dtype=np.float64), -1)
+    return Lw - Lw.T
+
+
+def reconstruct(LT: np.ndarray, ipiv: np.ndarray, T: np.ndarray):
+    """(L, Tm, perm) with P A P^T = L Tm L^T and (P A P^T)[i,j] = A[perm[i], perm[j]]."""
+    n = LT.shape[0]
+    L = np.eye(n)
+    for j in range(1, n):
+        L[j + 1:, j] = LT[j + 1:, j - 1]
+    Tm = np.zeros((n, n))
+    for k in range(n - 1):
+        Tm[k + 1, k] = T[k]
+        Tm[k, k + 1] = -T[k]
+    perm = np.arange(n)
+    for j in range(1, n):
+        p = int(ipiv[j])
+        perm[[j, p]] = perm[[p, j]]
+    return L, Tm, perm
+
+
+def recon_residual(A0: np.ndarray, LT: np.ndarray, ipiv: np.ndarray, T: np.ndarray) -> float:
+    """|| P A P^T - L T L^T ||_F / (n ||A||_F) for the skew matrix given by tril(A0, -1)."""
+    n = A0.shape[0]
+    if n == 0:
+        return 0.0
+    S = full_from_lower(A0)
+    L, Tm, perm = reconstruct(LT, ipiv, T)
+    PAP = S[np.ix_(perm, perm)]
+    R = PAP - L @ Tm @ L.T
+    nrm = np.linalg.norm(S)
+    return float(np.linalg.norm(R) / (n * nrm)) if nrm > 0 else float(np.linalg.norm(R))
+
+
+def skr2k(alpha: float, A: np.ndarray, B: np.ndarray, beta: float, C: np.ndarray) -> np.ndarray:
+    """Strict lower triangle of beta C + alpha (A B^T - B A^T); the rest of C is returned unchanged."""
+    A = np.asarray(A, dtype=np.float64)
+    B = np.asarray(B, dtype=np.float64)
+    upd = A @ B.T - B @ A.T
+    out = np.array(C, dtype=np.float64, order="F")
+    low = np.tril(np.ones(out.shape, dtype=bool), -1)
+    out[low] = (beta * out + alpha * upd)[low]
+    return out
+
+
+def skr2k_error_bound(alpha: float, A: np.ndarray, B: np.ndarray, beta: float, C: np.ndarray,
+                      u: float = 2.0 ** -53) -> np.ndarray:
+    """Entrywise bound on |computed - exact| for skr2k in working precision u.
+
+    Any summation order of the 2k products plus the scaling obeys
+    |err| <= gamma_{2k+2} (|beta||C| + |alpha| (|A||B|^T + |B||A|^T)),
+    gamma_m = m u / (1 - m u).
+    """
+    k = A.shape[1]
+    m = 2 * k + 2
+    g = m * u / (1 - m * u)
+    aA, aB = np.abs(A), np.abs(B)
+    return g * (abs(beta) * np.abs(C) + abs(alpha) * (aA @ aB.T + aB @ aA.T))
+
+
+def backward_error(A0: np.ndarray, X: np.ndarray, B: np.ndarray) -> float:
+    """max_j ||b_j - A x_j||_inf / (||A||_inf ||x_j||_inf + ||b_j||_inf), A skew from tril(A0,-1)."""
+    S = full_from_lower(A0)
+    R = B - S @ X
+    anrm = np.abs(S).sum(axis=1).max() if S.size else 0.0
+    num = np.abs(R).max(axis=0)
+    den = anrm * np.abs(X).max(axis=0) + np.abs(B).max(axis=0)
+    return float((num / den).max()) if num.size else 0.0
+
+
+def gflops_nominal(n: int, seconds: float) -> float:
+    """GFLOP/s on the nominal n^3/3 flop count of the paired factorization."""
+    return (n ** 3 / 3.0) / seconds / 1e9
+
+
+def nominal_flops_steps(n: int, k0: int, k1: int) -> float:
+    """Nominal flops of elimination steps k0..k1-1: sum of (n-k-1)^2 (n^3/3 in total)."""
+    return float(sum((n - k - 1) ** 2 for k in range(k0, k1)))
+
+
+def logdet_lu(A_full: np.ndarray):
+    """(sign, log|det|) by LAPACK's partially pivoted LU (numpy.linalg.slogdet)."""
+    s, ld = np.linalg.slogdet(A_full)
+    return float(s), float(ld)
+
+
+def isclose_log(a: float, b: float) -> float:
+    """Relative error used for log|Pf|: |a-b| / max(1, |b|)."""
+    if math.isinf(a) and math.isinf(b) and (a > 0) == (b > 0):
+        return 0.0
+    return abs(a - b) / max(1.0, abs(b))
