@@ -1,0 +1,197 @@
+/*
+ * skf -- skew-symmetric LTL^T factorization and Pfaffians on AMD MI355X (gfx950).
+ *
+ * Plain C ABI.  Every array argument is a DEVICE pointer owned by the caller
+ * unless the comment says "host".  Streams are passed as `void*` holding a
+ * hipStream_t (NULL = the default stream).  The library never frees caller
+ * memory and allocates no device memory on these paths: scratch space is the
+ * caller's `work` buffer, whose size the matching *_workspace query returns.
+ *
+ * Mathematics (standard, no particular paper passage: the method is Gaussian
+ * congruence elimination with partial pivoting in the manner of Parlett and
+ * Reid, 1970, specialised to skew-symmetric matrices):
+ *   P A P^T = L T L^T, L unit lower triangular with L[:,0] = e_0, T skew
+ *   tridiagonal (T(k+1,k) = T[k], T(k,k+1) = -T[k]); Pf(A) = det(P) Pf(T),
+ *   Pf(T) = (-1)^{n/2} prod_{k even} T[k]; 2*log|Pf(A)| = log|det(A)|.
+ *
+ * Storage conventions shared by all entry points (column-major, 0-based):
+ *   - A is n x n with leading dimension lda >= max(1,n); ONLY the strict lower
+ *     triangle is read.  The diagonal and the strict upper triangle are never
+ *     read or written.
+ *   - On exit from a factorization, L[i,j] (i > j >= 1) is stored at A[i, j-1],
+ *     the subdiagonal A[k+1,k] holds T[k], and T[k] is also written to T[].
+ *   - ipiv[0] = 0; ipiv[j] = p >= j means rows/columns j and p were interchanged
+ *     at elimination step j-1 (P is the product of these interchanges, in order).
+ *   - Pivoting chooses the largest |entry| of the current column below the
+ *     subdiagonal; ties go to the lowest row index; an all-zero column gives no
+ *     interchange and a zero multiplier column.
+ *
+ * Status codes: entry points return 0 once the work is enqueued, or a negative
+ * code for an argument / device error detected on the host before any launch
+ * (-i = the i-th argument, 1-based, is invalid; SKF_E* below).  Numerical
+ * outcomes are reported through `dinfo` (a device int) when it is non-NULL, in
+ * which case the call is asynchronous on `stream`.  When `dinfo` is NULL the
+ * call synchronizes `stream` and returns the numerical outcome instead:
+ *   0            success
+ *   k+1 > 0      the first even step k with T[k] == 0: A is exactly singular
+ *                (Pf = 0); the factorization itself is complete
+ *   SKF_ENONFINITE  a pivot column held a NaN or an infinity; the outputs are
+ *                partial and must not be used
+ *   SKF_ETIMEOUT the persistent kernel's co-residency wait gave up (the device
+ *                could not run all of its workgroups at once); outputs invalid
+ */
+#ifndef SKF_H
+#define SKF_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int64_t skf_int;
+
+#define SKF_PREC_F64 0          /* FP64 everywhere */
+#define SKF_PREC_F32_TRAILING 1 /* FP32-MFMA trailing skr2k; FP64 panel, pivots, T and storage */
+
+#define SKF_OK 0
+#define SKF_ENOMEM (-100)
+#define SKF_EDEVICE (-101)
+#define SKF_ENOTIMPL (-102)
+#define SKF_ENONFINITE (-103)
+#define SKF_EWORK (-104)
+#define SKF_ETIMEOUT (-105)
+
+/* Library version string (static storage). */
+const char* skf_version(void);
+
+/* Last HIP error text seen by the library on this thread (static storage). */
+const char* skf_last_error(void);
+
+/*
+ * Device workspace (bytes) needed by skf_ltlt / skf_logpf / skf_pfaffian for an
+ * n x n matrix in precision `prec`.  The buffer must be 256-byte aligned and is
+ * not preserved between calls.  Blocked path: one n x n FP64 ping-pong copy of
+ * the trailing matrix plus O(n * nb) panel buffers.
+ */
+size_t skf_ltlt_workspace(skf_int n, int prec);
+
+/*
+ * Blocked, partially pivoted LTL^T of the skew matrix held in the strict lower
+ * triangle of A (right-looking; panels of nb paired elimination steps with the
+ * pivot search on the device, trailing skew rank-2k updates on the matrix cores).
+ *   n      order (>= 0)
+ *   A      device, lda x n, overwritten by L and T as described above
+ *   ipiv   device int32[n] (n >= 1), output
+ *   T      device double[max(n-1,1)], output
+ *   prec   SKF_PREC_F64 or SKF_PREC_F32_TRAILING
+ *   work   device workspace of at least skf_ltlt_workspace(n, prec) bytes
+ *   dinfo  device int or NULL (see status codes)
+ */
+int skf_ltlt(skf_int n, double* A, skf_int lda, int32_t* ipiv, double* T, int prec,
+             void* work, size_t lwork, int* dinfo, void* stream);
+
+/*
+ * log|Pf(A)| and sign(Pf(A)) from factors produced by skf_ltlt:
+ * log|Pf| = sum_{k even} log|T[k]| (fixed summation order), sign =
+ * (-1)^{s + n/2} prod_{k even} sgn T[k], s = #{j : ipiv[j] != j}.
+ * Odd n or a zero even T[k]: *sign = 0 and *logabs = -inf.  n = 0: Pf = 1.
+ * logabs, sign: device scalars.  Asynchronous; never fails numerically.
+ */
+int skf_logpf_from_factors(skf_int n, const int32_t* ipiv, const double* T, double* logabs,
+                           int* sign, void* stream);
+
+/* Device workspace (bytes) for skf_logpf / skf_pfaffian (the factorization's
+ * workspace plus room for ipiv and T). */
+size_t skf_logpf_workspace(skf_int n, int prec);
+
+/* Factor (destroying A) and reduce to log|Pf| and sign; outputs are device scalars. */
+int skf_logpf(skf_int n, double* A, skf_int lda, double* logabs, int* sign, int prec, void* work,
+              size_t lwork, int* dinfo, void* stream);
+
+/* As skf_logpf but returns Pf itself (device double; may overflow to +-inf or underflow to 0). */
+int skf_pfaffian(skf_int n, double* A, skf_int lda, double* pf, int prec, void* work, size_t lwork,
+                 int* dinfo, void* stream);
+
+/*
+ * Skew-symmetric rank-2k update of the strict lower triangle of C (n x n):
+ *   C := beta C + alpha (A B^T - B A^T),  A, B: n x k (lda, ldb >= n).
+ * The diagonal and upper triangle of C are not referenced.  beta == 0 does not
+ * read C.  FP64 matrix-core (MFMA) tiles.
+ */
+int skf_skr2k(skf_int n, skf_int k, double alpha, const double* A, skf_int lda, const double* B,
+              skf_int ldb, double beta, double* C, skf_int ldc, void* stream);
+
+/* The same update with A and B rounded to FP32, FP32 MFMA products and FP32
+ * accumulation over k, added to the FP64 C in FP64. */
+int skf_skr2k_f32(skf_int n, skf_int k, double alpha, const double* A, skf_int lda, const double* B,
+                  skf_int ldb, double beta, double* C, skf_int ldc, void* stream);
+
+/* Device workspace (bytes) for skf_solve with nrhs right-hand sides. */
+size_t skf_solve_workspace(skf_int n, skf_int nrhs);
+
+/*
+ * Solve A X = B with the factors of skf_ltlt: X = P^T L^{-T} T^{-1} L^{-1} P B,
+ * in place over B (n x nrhs, ldb >= n).  T is solved through its 2x2 block
+ * structure (two independent recurrences dividing by the even T[k]).
+ * Numerical outcome (dinfo / return): 0, or k+1 for the first even k with
+ * T[k] == 0, or n for odd n (T, hence A, is singular).
+ */
+int skf_solve(skf_int n, skf_int nrhs, const double* LT, skf_int lda, const int32_t* ipiv,
+              const double* T, double* B, skf_int ldb, void* work, size_t lwork, int* dinfo,
+              void* stream);
+
+/* Device workspace (bytes) for skf_solve_refine. */
+size_t skf_refine_workspace(skf_int n, skf_int nrhs);
+
+/*
+ * Iterative refinement (synchronous): X_0 = solve(B); repeat R = B - A0 X in
+ * FP64 (A0 = the ORIGINAL matrix, strict lower triangle read), D = solve(R),
+ * X += D, until the componentwise-normwise backward error
+ *   eta = max_j ||b_j - A0 x_j||_inf / (||A0||_inf ||x_j||_inf + ||b_j||_inf)
+ * is <= tol or maxit corrections were applied.  Factors may come from either
+ * precision.  iters, berr: host outputs (iters = corrections applied).
+ * Returns the numerical outcome as skf_solve does; 1 if tol was not reached.
+ */
+int skf_solve_refine(skf_int n, skf_int nrhs, const double* A0, skf_int lda0, const double* LT,
+                     skf_int lda, const int32_t* ipiv, const double* T, const double* B,
+                     skf_int ldb, double* X, skf_int ldx, double tol, int maxit, int* iters,
+                     double* berr, void* work, size_t lwork, void* stream);
+
+/* Device workspace (bytes) for the batched calls over `batch` matrices of
+ * orders n_host[0..batch) (host array). */
+size_t skf_batched_workspace(skf_int batch, const skf_int* n_host);
+
+/*
+ * Batched LTL^T + Pfaffian: `batch` independent skew matrices factored by ONE
+ * persistent launch (largest first from a device work queue).
+ *   n_host, lda_host  host arrays [batch]: orders and leading dimensions
+ *   A                 device array [batch] of device pointers (overwritten by L, T)
+ *   ipiv, T           device arrays [batch] of device pointers, or NULL to skip
+ *                     (T[b] needs max(n-1,1) doubles, ipiv[b] n ints)
+ *   logabs, sign, info  device arrays [batch]: log|Pf|, sign, per-matrix outcome
+ * Asynchronous on `stream`.
+ */
+int skf_ltlt_batched(skf_int batch, const skf_int* n_host, double* const* A, const skf_int* lda_host,
+                     int32_t* const* ipiv, double* const* T, double* logabs, int* sign, int* info,
+                     void* work, size_t lwork, void* stream);
+
+/* log|Pf| and sign of every matrix of the batch (A overwritten). */
+int skf_logpf_batched(skf_int batch, const skf_int* n_host, double* const* A, const skf_int* lda_host,
+                      double* logabs, int* sign, int* info, void* work, size_t lwork, void* stream);
+
+/*
+ * Batched solves with factors from skf_ltlt_batched: B[b] (n_b x nrhs_host[b],
+ * ldb_host[b]) overwritten by X[b].  Pointer arrays are device arrays.
+ */
+int skf_solve_batched(skf_int batch, const skf_int* n_host, double* const* LT, const skf_int* lda_host,
+                      int32_t* const* ipiv, double* const* T, const skf_int* nrhs_host,
+                      double* const* B, const skf_int* ldb_host, int* info, void* work, size_t lwork,
+                      void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SKF_H */

@@ -1,0 +1,140 @@
+// Host driver of the blocked, right-looking skew LTL^T.
+//
+// For each panel P of nb paired elimination steps (k0 = P*nb):
+//   1. panel kernel on the panel-start matrix buf[P%2] (persistent grid, one
+//      pivot search per step on the device; emits L, l', w, T, ipiv, the
+//      panel's permutation and the next panel's first column);
+//   2. trailing update buf[P%2] -> buf[(P+1)%2] through that permutation
+//      (skew rank-nb on the matrix cores, FP64 or FP32);
+//   3. the panel's L columns parked in the workspace copy W.
+// buf[0] is the caller's A, buf[1] the workspace W.  At the end the later
+// panels' permutations are composed and L is copied into A in final row order.
+// The host only enqueues; nothing waits on the device inside the loop.
+#include <algorithm>
+
+#include "skf_internal.h"
+
+namespace skf {
+
+static constexpr int kSlotsNB128 = 64;
+static constexpr int kSlotsNB64 = 128;
+
+int ltlt_plan_nb(int64_t n) {
+  const int cus = device_info().num_cus;
+  // nb = 128 needs every panel row in one of <= num_cus workgroups of 64 slots
+  if (n - 1 <= (int64_t)kSlotsNB128 * cus) return 128;
+  if (n - 1 <= (int64_t)kSlotsNB64 * cus) return 64;
+  return -1;
+}
+
+int ltlt_panel_grid(int64_t m, int nb, int* G, int* S) {
+  const int smax = (nb == 128) ? kSlotsNB128 : kSlotsNB64;
+  const int cus = device_info().num_cus;
+  int64_t g = (m + smax - 1) / smax;
+  if (g < 1) g = 1;
+  if (g > cus) return SKF_ENOTIMPL;
+  int64_t s = (m + g - 1) / g;
+  *G = (int)g;
+  *S = (int)std::max<int64_t>(s, 1);
+  return 0;
+}
+
+static int64_t npanels_of(int64_t n, int nb) { return n >= 2 ? (n - 1 + nb - 1) / nb : 0; }
+
+static size_t carve(LtltWork* w, char* base, int64_t n, int nb) {
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    size_t o = off;
+    off = align_up(off + bytes, 256);
+    return base ? (void*)(base + o) : nullptr;
+  };
+  const int64_t np = npanels_of(n, nb);
+  const int gmax = std::max(1, device_info().num_cus);
+  w->W = (double*)take(sizeof(double) * (size_t)n * n);
+  w->Lbuf = (double*)take(sizeof(double) * (size_t)n * nb);
+  w->Lp = (double*)take(sizeof(double) * (size_t)n * (nb / 2));
+  w->Wp = (double*)take(sizeof(double) * (size_t)n * (nb / 2));
+  w->cnext = (double*)take(sizeof(double) * (size_t)n);
+  w->pis = (int32_t*)take(sizeof(int32_t) * (size_t)std::max<int64_t>(np, 1) * n);
+  w->sigma = (int32_t*)take(sizeof(int32_t) * (size_t)std::max<int64_t>(np, 1) * n);
+  w->rec = (uint64_t*)take(sizeof(uint64_t) * panel_record_words(gmax));
+  w->status = (int*)take(256);
+  w->bytes = off;
+  return off;
+}
+
+size_t ltlt_workspace_bytes(int64_t n, int prec) {
+  (void)prec;
+  const int nb = ltlt_plan_nb(n);
+  if (nb < 0) return 0;
+  LtltWork w;
+  return carve(&w, nullptr, n, nb);
+}
+
+LtltWork ltlt_carve(void* work, int64_t n, int prec) {
+  (void)prec;
+  LtltWork w{};
+  const int nb = ltlt_plan_nb(n);
+  carve(&w, (char*)work, n, nb);
+  return w;
+}
+
+int run_ltlt(int64_t n, double* A, int64_t lda, int32_t* ipiv, double* T, int prec, void* work,
+             size_t lwork, int* dinfo_dev, hipStream_t s) {
+  if (n == 0) return dinfo_dev ? launch_fill_i32(dinfo_dev, 1, 0, s) : 0;
+  const int nb = ltlt_plan_nb(n);
+  if (nb < 0) return SKF_ENOTIMPL;
+  LtltWork w = ltlt_carve(work, n, prec);
+  if (lwork < w.bytes) return SKF_EWORK;
+  const int gmax = std::max(1, device_info().num_cus);
+  int rc;
+  if ((rc = launch_fill_i32(w.status, 1, 0, s))) return rc;
+  if ((rc = launch_fill_i32(ipiv, 1, 0, s))) return rc;  // ipiv[0] = 0
+  if (n == 1) {
+    if (dinfo_dev) return launch_ltlt_info(n, T, w.status, dinfo_dev, s);
+    return 0;
+  }
+  if ((rc = launch_fill_u64(w.rec, panel_record_words(gmax), 0, s))) return rc;
+
+  const int64_t np = npanels_of(n, nb);
+  double* buf[2] = {A, w.W};
+  const int64_t ldb[2] = {lda, n};
+  for (int64_t P = 0; P < np; ++P) {
+    const int64_t k0 = P * nb;
+    const int nsteps = (int)std::min<int64_t>(nb, n - 1 - k0);
+    const int64_t m = n - k0 - 1;
+    PanelParams pp{};
+    pp.n = n;
+    pp.k0 = k0;
+    pp.nsteps = nsteps;
+    pp.nb = nb;
+    if ((rc = ltlt_panel_grid(m, nb, &pp.G, &pp.S))) return rc;
+    pp.src = buf[P % 2];
+    pp.ld = ldb[P % 2];
+    pp.Lbuf = w.Lbuf;
+    pp.Lp = w.Lp;
+    pp.Wp = w.Wp;
+    pp.pi = w.pis + P * n;
+    pp.cnext = w.cnext;
+    pp.T = T;
+    pp.ipiv = ipiv;
+    pp.rec = w.rec;
+    pp.status = w.status;
+    pp.tag_base = (uint32_t)k0;
+    if ((rc = launch_panel(pp, s))) return rc;
+    const int64_t lo = k0 + nsteps;
+    if (n - lo >= 2 && nsteps % 2 == 0) {
+      rc = launch_skr2k_perm(n, lo, nsteps / 2, buf[P % 2], ldb[P % 2], buf[(P + 1) % 2],
+                             ldb[(P + 1) % 2], pp.pi, w.Lp, w.Wp, n, w.cnext,
+                             prec == SKF_PREC_F32_TRAILING, s);
+      if (rc) return rc;
+    }
+    if ((rc = launch_copy_panel_L(n, k0, nsteps, w.Lbuf, w.W, n, s))) return rc;
+  }
+  if ((rc = launch_compose_sigma(n, (int)np, w.pis, w.sigma, s))) return rc;
+  if ((rc = launch_final_L(n, nb, (int)np, w.W, n, w.sigma, A, lda, s))) return rc;
+  if (dinfo_dev) return launch_ltlt_info(n, T, w.status, dinfo_dev, s);
+  return 0;
+}
+
+}  // namespace skf

@@ -1,0 +1,127 @@
+// Internal declarations shared by the HIP translation units of libskf.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+#include "../../include/skf.h"
+
+namespace skf {
+
+typedef double d4 __attribute__((ext_vector_type(4)));
+typedef float f4 __attribute__((ext_vector_type(4)));
+
+constexpr int kWave = 64;
+
+// Records the last HIP error for skf_last_error(); returns SKF_EDEVICE if err != success.
+int note_error(hipError_t err, const char* where);
+
+#define SKF_CHECK_LAUNCH(where)                              \
+  do {                                                       \
+    hipError_t e_ = hipGetLastError();                       \
+    if (e_ != hipSuccess) return ::skf::note_error(e_, where); \
+  } while (0)
+
+#define SKF_CHECK(call, where)                                  \
+  do {                                                          \
+    hipError_t e_ = (call);                                     \
+    if (e_ != hipSuccess) return ::skf::note_error(e_, where);  \
+  } while (0)
+
+struct DeviceInfo {
+  int device;
+  int num_cus;
+  size_t lds_per_block;
+};
+// Properties of the current device (cached per device).
+const DeviceInfo& device_info();
+
+inline size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
+
+// ---------------------------------------------------------------------------
+// skr2k (trailing update) launchers
+// ---------------------------------------------------------------------------
+
+// Plain in-place update of the strict lower triangle of C (n x n):
+//   C := beta C + alpha (X Y^T - Y X^T), X, Y: n x k.
+int launch_skr2k_f64(int64_t n, int64_t k, double alpha, const double* X, int64_t ldx,
+                     const double* Y, int64_t ldy, double beta, double* C, int64_t ldc,
+                     hipStream_t s);
+int launch_skr2k_f32(int64_t n, int64_t k, double alpha, const double* X, int64_t ldx,
+                     const double* Y, int64_t ldy, double beta, double* C, int64_t ldc,
+                     hipStream_t s);
+
+// Trailing update of the blocked factorization, out of place and through the
+// panel's row/column permutation pi (current index -> row index in src):
+//   for lo <= j < i < n:
+//     dst[i,j] = (j == lo) ? cnext[i]
+//              : S(pi[i], pi[j]) + sum_q (Lp[i,q] Wp[j,q] - Wp[i,q] Lp[j,q]),
+//   where S(a,b) = src[a,b] if a > b else -src[b,a] (strict lower storage).
+// Lp, Wp: n x npairs (ld = ldp, rows indexed by the current index).
+int launch_skr2k_perm(int64_t n, int64_t lo, int64_t npairs, const double* src, int64_t ld_src,
+                      double* dst, int64_t ld_dst, const int32_t* pi, const double* Lp,
+                      const double* Wp, int64_t ldp, const double* cnext, bool f32, hipStream_t s);
+
+// ---------------------------------------------------------------------------
+// Blocked factorization pieces
+// ---------------------------------------------------------------------------
+struct PanelParams {
+  int64_t n;
+  int64_t k0;        // first step of the panel
+  int nsteps;        // elimination steps in this panel (<= nb)
+  int nb;            // panel width (even)
+  int G;             // workgroups of the persistent panel kernel
+  int S;             // rows (slots) per workgroup
+  const double* src; // current trailing matrix (strict lower storage)
+  int64_t ld;
+  double* Lbuf;      // n x nb: L columns of the panel, current order at panel end
+  double* Lp;        // n x nb/2: l' of each pair
+  double* Wp;        // n x nb/2: w of each pair
+  int32_t* pi;       // n: panel permutation (current index -> src row)
+  double* cnext;     // n: first column of the next panel
+  double* T;         // global T output
+  int32_t* ipiv;     // global ipiv output
+  uint64_t* rec;     // sync records: 2 x G x kRecWords
+  int* status;       // device status word (0 ok)
+  uint32_t tag_base; // tag of step k is tag_base + (k - k0) + 1
+};
+
+int launch_panel(const PanelParams& p, hipStream_t s);
+size_t panel_record_words(int G);
+
+// Workspace layout of the blocked path.
+struct LtltWork {
+  double* W;       // n x n ping-pong copy (ld n)
+  double* Lbuf;    // n x nb
+  double* Lp;      // n x nb/2
+  double* Wp;      // n x nb/2
+  double* cnext;   // n
+  int32_t* pis;    // npanels x n: per-panel permutations
+  int32_t* sigma;  // npanels x n: composed later permutations
+  uint64_t* rec;   // sync records
+  int* status;     // 1 int (+ padding)
+  size_t bytes;
+};
+
+int ltlt_plan_nb(int64_t n);
+int ltlt_panel_grid(int64_t n, int nb, int* G, int* S);
+size_t ltlt_workspace_bytes(int64_t n, int prec);
+LtltWork ltlt_carve(void* work, int64_t n, int prec);
+
+int run_ltlt(int64_t n, double* A, int64_t lda, int32_t* ipiv, double* T, int prec, void* work,
+             size_t lwork, int* dinfo_dev, hipStream_t s);
+
+// Helpers (ltlt_aux.hip)
+int launch_fill_u64(uint64_t* p, size_t count, uint64_t v, hipStream_t s);
+int launch_fill_i32(int32_t* p, size_t count, int32_t v, hipStream_t s);
+int launch_copy_panel_L(int64_t n, int64_t k0, int nsteps, const double* Lbuf, double* W, int64_t ldw,
+                        hipStream_t s);
+int launch_compose_sigma(int64_t n, int npanels, const int32_t* pis, int32_t* sigma, hipStream_t s);
+int launch_final_L(int64_t n, int nb, int npanels, const double* W, int64_t ldw, const int32_t* sigma,
+                   double* A, int64_t lda, hipStream_t s);
+int launch_ltlt_info(int64_t n, const double* T, const int* status, int* dinfo, hipStream_t s);
+int launch_logpf(int64_t n, const int32_t* ipiv, const double* T, double* logabs, int* sign,
+                 double* pf, hipStream_t s);
+
+}  // namespace skf

@@ -1,0 +1,241 @@
+"""Thin Python binding of libskf (ctypes).  Argument marshalling only: every step
+of the computation runs in the HIP kernels of ``libskf.so``.
+
+Matrices are PyTorch CUDA tensors in column-major layout: ``A.stride(0) == 1``
+and ``A.stride(1) = lda >= n`` (see :func:`colmajor`).  PyTorch supplies device
+memory and streams; nothing here computes.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import threading
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libskf.so")
+
+PREC_F64 = 0
+PREC_F32_TRAILING = 1
+
+OK = 0
+ENOMEM = -100
+EDEVICE = -101
+ENOTIMPL = -102
+ENONFINITE = -103
+EWORK = -104
+ETIMEOUT = -105
+
+# Every symbol declared in include/skf.h (checked by the CPU test suite).
+EXPORTS = [
+    "skf_version", "skf_last_error", "skf_ltlt_workspace", "skf_ltlt", "skf_logpf_from_factors",
+    "skf_logpf_workspace", "skf_logpf", "skf_pfaffian", "skf_skr2k", "skf_skr2k_f32",
+    "skf_solve_workspace", "skf_solve", "skf_refine_workspace", "skf_solve_refine",
+    "skf_batched_workspace", "skf_ltlt_batched", "skf_logpf_batched", "skf_solve_batched",
+]
+
+_lib = None
+_lock = threading.Lock()
+
+
+class SkfError(RuntimeError):
+    def __init__(self, code: int, where: str):
+        msg = f"{where} failed with status {code}"
+        try:
+            le = _load().skf_last_error().decode()
+            if le:
+                msg += f" ({le})"
+        except Exception:  # pragma: no cover - message decoration only
+            pass
+        super().__init__(msg)
+        self.code = code
+
+
+def _load():
+    global _lib
+    with _lock:
+        if _lib is None:
+            if not os.path.exists(LIB_PATH):
+                raise RuntimeError(f"{LIB_PATH} is missing: build it first (paper_2408_05238_amd.build.build())")
+            lib = ctypes.CDLL(LIB_PATH)
+            i64, vp, sz, d = ctypes.c_int64, ctypes.c_void_p, ctypes.c_size_t, ctypes.c_double
+            ci = ctypes.c_int
+            sig = {
+                "skf_version": (ctypes.c_char_p, []),
+                "skf_last_error": (ctypes.c_char_p, []),
+                "skf_ltlt_workspace": (sz, [i64, ci]),
+                "skf_ltlt": (ci, [i64, vp, i64, vp, vp, ci, vp, sz, vp, vp]),
+                "skf_logpf_from_factors": (ci, [i64, vp, vp, vp, vp, vp]),
+                "skf_logpf_workspace": (sz, [i64, ci]),
+                "skf_logpf": (ci, [i64, vp, i64, vp, vp, ci, vp, sz, vp, vp]),
+                "skf_pfaffian": (ci, [i64, vp, i64, vp, ci, vp, sz, vp, vp]),
+                "skf_skr2k": (ci, [i64, i64, d, vp, i64, vp, i64, d, vp, i64, vp]),
+                "skf_skr2k_f32": (ci, [i64, i64, d, vp, i64, vp, i64, d, vp, i64, vp]),
+                "skf_solve_workspace": (sz, [i64, i64]),
+                "skf_solve": (ci, [i64, i64, vp, i64, vp, vp, vp, i64, vp, sz, vp, vp]),
+                "skf_refine_workspace": (sz, [i64, i64]),
+                "skf_solve_refine": (ci, [i64, i64, vp, i64, vp, i64, vp, vp, vp, i64, vp, i64, d, ci,
+                                          ctypes.POINTER(ci), ctypes.POINTER(d), vp, sz, vp]),
+                "skf_batched_workspace": (sz, [i64, vp]),
+                "skf_ltlt_batched": (ci, [i64, vp, vp, vp, vp, vp, vp, vp, vp, vp, sz, vp]),
+                "skf_logpf_batched": (ci, [i64, vp, vp, vp, vp, vp, vp, vp, sz, vp]),
+                "skf_solve_batched": (ci, [i64, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, sz, vp]),
+            }
+            for name, (res, args) in sig.items():
+                if hasattr(lib, name):
+                    f = getattr(lib, name)
+                    f.restype = res
+                    f.argtypes = args
+            _lib = lib
+    return _lib
+
+
+def lib():
+    return _load()
+
+
+def version() -> str:
+    return _load().skf_version().decode()
+
+
+# ----------------------------------------------------------------------------
+# torch helpers (memory and streams only)
+# ----------------------------------------------------------------------------
+
+def _torch():
+    import torch
+    return torch
+
+
+def colmajor(n_rows: int, n_cols: int, device="cuda", dtype=None, ld: int | None = None):
+    """Empty column-major tensor (stride(0) == 1, stride(1) == ld)."""
+    torch = _torch()
+    dtype = dtype or torch.float64
+    ld = ld or max(n_rows, 1)
+    buf = torch.empty((max(n_cols, 1), ld), device=device, dtype=dtype)
+    return buf.t()[:n_rows, :n_cols]
+
+
+def to_device_colmajor(a, device="cuda"):
+    """Copy a numpy array (any order) into a new column-major device tensor."""
+    import numpy as np
+    torch = _torch()
+    a = np.asfortranarray(a)
+    t = colmajor(a.shape[0], a.shape[1] if a.ndim > 1 else 1, device=device,
+                 dtype=torch.from_numpy(np.zeros(1, a.dtype)).dtype)
+    t.copy_(torch.from_numpy(a.reshape(t.shape, order="F")))
+    return t
+
+
+def _ld(A) -> int:
+    if A.dim() != 2 or (A.shape[0] > 1 and A.stride(0) != 1):
+        raise ValueError("expected a column-major 2-D tensor (stride(0) == 1)")
+    return max(A.stride(1), A.shape[0], 1)
+
+
+def _stream(stream):
+    torch = _torch()
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr()) if t is not None else ctypes.c_void_p(0)
+
+
+def workspace(nbytes: int, device="cuda"):
+    torch = _torch()
+    return torch.empty(max(int(nbytes), 256), dtype=torch.uint8, device=device)
+
+
+# Numerical outcomes a synchronous call returns instead of raising.
+NUMERICAL = (ENONFINITE, ETIMEOUT)
+
+
+def _check(rc: int, where: str):
+    if rc < 0 and rc not in NUMERICAL:
+        raise SkfError(rc, where)
+    return rc
+
+
+# ----------------------------------------------------------------------------
+# Entry points (names follow the C ABI)
+# ----------------------------------------------------------------------------
+
+def ltlt_workspace(n: int, prec: int = PREC_F64) -> int:
+    return int(_load().skf_ltlt_workspace(n, prec))
+
+
+def ltlt(A, ipiv=None, T=None, prec: int = PREC_F64, work=None, dinfo=None, stream=None):
+    """Factor A (column-major, strict lower triangle read) in place.
+
+    Returns (ipiv, T, info); info is an int when ``dinfo`` is None (the call then
+    synchronizes the stream), else the device tensor ``dinfo``.
+    """
+    torch = _torch()
+    n = A.shape[0]
+    lda = _ld(A)
+    dev = A.device
+    if ipiv is None:
+        ipiv = torch.empty(max(n, 1), dtype=torch.int32, device=dev)
+    if T is None:
+        T = torch.empty(max(n - 1, 1), dtype=torch.float64, device=dev)
+    if work is None:
+        work = workspace(ltlt_workspace(n, prec), dev)
+    rc = _load().skf_ltlt(n, _ptr(A), lda, _ptr(ipiv), _ptr(T), prec, _ptr(work), work.numel(),
+                          _ptr(dinfo), _stream(stream))
+    _check(rc, "skf_ltlt")
+    return ipiv[:n], T[:max(n - 1, 0)], (rc if dinfo is None else dinfo)
+
+
+def logpf_from_factors(n: int, ipiv, T, stream=None):
+    torch = _torch()
+    dev = ipiv.device
+    la = torch.empty(1, dtype=torch.float64, device=dev)
+    sg = torch.empty(1, dtype=torch.int32, device=dev)
+    Tp = T if T.numel() > 0 else torch.zeros(1, dtype=torch.float64, device=dev)
+    rc = _load().skf_logpf_from_factors(n, _ptr(ipiv), _ptr(Tp), _ptr(la), _ptr(sg), _stream(stream))
+    _check(rc, "skf_logpf_from_factors")
+    return la, sg
+
+
+def logpf_workspace(n: int, prec: int = PREC_F64) -> int:
+    return int(_load().skf_logpf_workspace(n, prec))
+
+
+def logpf(A, prec: int = PREC_F64, work=None, dinfo=None, stream=None):
+    """(logabs, sign, info) of the Pfaffian; A is destroyed.  logabs/sign are device tensors."""
+    torch = _torch()
+    n = A.shape[0]
+    lda = _ld(A)
+    dev = A.device
+    la = torch.empty(1, dtype=torch.float64, device=dev)
+    sg = torch.empty(1, dtype=torch.int32, device=dev)
+    if work is None:
+        work = workspace(logpf_workspace(n, prec), dev)
+    rc = _load().skf_logpf(n, _ptr(A), lda, _ptr(la), _ptr(sg), prec, _ptr(work), work.numel(),
+                           _ptr(dinfo), _stream(stream))
+    _check(rc, "skf_logpf")
+    return la, sg, (rc if dinfo is None else dinfo)
+
+
+def pfaffian(A, prec: int = PREC_F64, work=None, dinfo=None, stream=None):
+    torch = _torch()
+    n = A.shape[0]
+    lda = _ld(A)
+    pf = torch.empty(1, dtype=torch.float64, device=A.device)
+    if work is None:
+        work = workspace(logpf_workspace(n, prec), A.device)
+    rc = _load().skf_pfaffian(n, _ptr(A), lda, _ptr(pf), prec, _ptr(work), work.numel(), _ptr(dinfo),
+                              _stream(stream))
+    _check(rc, "skf_pfaffian")
+    return pf, (rc if dinfo is None else dinfo)
+
+
+def skr2k(alpha: float, A, B, beta: float, C, f32: bool = False, stream=None):
+    """C := beta C + alpha (A B^T - B A^T) on the strict lower triangle of C (in place)."""
+    n, k = A.shape
+    fn = _load().skf_skr2k_f32 if f32 else _load().skf_skr2k
+    rc = fn(n, k, float(alpha), _ptr(A), _ld(A) if k > 0 else max(n, 1), _ptr(B),
+            _ld(B) if k > 0 else max(n, 1), float(beta), _ptr(C), _ld(C), _stream(stream))
+    _check(rc, "skf_skr2k")
+    return C

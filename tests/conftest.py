@@ -25,3 +25,9 @@ def gen():
     from paper_2408_05238_amd import inputs
     inputs._load()
     return inputs
+
+
+try:  # import torch during collection so the first GPU test's timeout excludes it
+    import torch  # noqa: F401
+except Exception:  # pragma: no cover
+    pass
