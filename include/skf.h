@@ -190,6 +190,19 @@ int skf_solve_batched(skf_int batch, const skf_int* n_host, double* const* LT, c
                       double* const* B, const skf_int* ldb_host, int* info, void* work, size_t lwork,
                       void* stream);
 
+/*
+ * Kernel timing for benchmarks.  While enabled, every launch of the blocked
+ * factorization's panel kernel (class 0) and trailing skew rank-2k update
+ * (class 1) is bracketed by HIP events recorded on the launch's own stream,
+ * together with the launch's algorithmic flop count (class 1: 2 * K * m(m-1)/2
+ * with K = 2 * pairs, m the trailing order).  skf_profile_read synchronizes the
+ * recorded events and returns, per class, total milliseconds, total flops and
+ * the number of launches (arrays of length 2, host memory); reset != 0 clears
+ * the record.  Not thread-safe against concurrent factorizations.
+ */
+int skf_profile_enable(int on);
+int skf_profile_read(double* ms, double* flops, int64_t* launches, int reset);
+
 #ifdef __cplusplus
 }
 #endif

@@ -2,6 +2,7 @@
 // stream-ordered launches.  See include/skf.h for the contract of each call.
 #include <mutex>
 #include <stdio.h>
+#include <vector>
 #include <string.h>
 
 #include "skf_internal.h"
@@ -48,6 +49,65 @@ static int finish_sync(int rc, int* dinfo_internal, hipStream_t s) {
   SKF_CHECK(hipStreamSynchronize(s), "sync");
   return h;
 }
+
+// ---------------------------------------------------------------------------
+// Kernel timing hooks
+// ---------------------------------------------------------------------------
+namespace {
+struct ProfRec {
+  hipEvent_t a, b;
+  int cls;
+  double flops;
+};
+struct Profiler {
+  std::mutex mu;
+  bool on = false;
+  std::vector<ProfRec> recs;
+  std::vector<hipEvent_t> pool;
+  hipEvent_t pending = nullptr;
+  hipEvent_t get() {
+    if (!pool.empty()) {
+      hipEvent_t e = pool.back();
+      pool.pop_back();
+      return e;
+    }
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    return e;
+  }
+};
+Profiler& prof() {
+  static Profiler p;
+  return p;
+}
+}  // namespace
+
+void prof_begin(hipStream_t s) {
+  Profiler& p = prof();
+  std::lock_guard<std::mutex> lk(p.mu);
+  if (!p.on) return;
+  p.pending = p.get();
+  if (p.pending) (void)hipEventRecord(p.pending, s);
+}
+
+void prof_end(hipStream_t s, int cls, double flops) {
+  Profiler& p = prof();
+  std::lock_guard<std::mutex> lk(p.mu);
+  if (!p.on || !p.pending) return;
+  hipEvent_t b = p.get();
+  if (!b) return;
+  (void)hipEventRecord(b, s);
+  p.recs.push_back(ProfRec{p.pending, b, cls, flops});
+  p.pending = nullptr;
+}
+
+size_t solve_workspace_bytes(int64_t n, int64_t nrhs);
+int run_solve(int64_t n, int64_t nrhs, const double* LT, int64_t lda, const int32_t* ipiv, const double* T,
+              double* B, int64_t ldb, void* work, size_t lwork, int* dinfo, hipStream_t s);
+size_t refine_workspace_bytes(int64_t n, int64_t nrhs);
+int run_refine(int64_t n, int64_t nrhs, const double* A0, int64_t lda0, const double* LT, int64_t lda,
+               const int32_t* ipiv, const double* T, const double* B, int64_t ldb, double* X, int64_t ldx,
+               double tol, int maxit, int* iters, double* berr, void* work, size_t lwork, hipStream_t s);
 
 }  // namespace skf
 
@@ -180,9 +240,94 @@ int skf_skr2k_f32(skf_int n, skf_int k, double alpha, const double* A, skf_int l
   return launch_skr2k_f32(n, k, alpha, A, lda, B, ldb, beta, C, ldc, (hipStream_t)stream);
 }
 
-}  // extern "C"
+size_t skf_solve_workspace(skf_int n, skf_int nrhs) {
+  if (n < 0 || nrhs < 0) return 0;
+  return solve_workspace_bytes(n, nrhs) + 256;
+}
 
-// ---------------------------------------------------------------------------
-// Entry points whose kernels live in later translation units are declared in
-// skf.h; until a unit provides them these definitions report SKF_ENOTIMPL.
-// ---------------------------------------------------------------------------
+int skf_solve(skf_int n, skf_int nrhs, const double* LT, skf_int lda, const int32_t* ipiv, const double* T,
+              double* B, skf_int ldb, void* work, size_t lwork, int* dinfo, void* stream) {
+  if (n < 0) return -1;
+  if (nrhs < 0) return -2;
+  if (n > 0 && !LT) return -3;
+  if (lda < (n > 1 ? n : 1)) return -4;
+  if (n > 0 && !ipiv) return -5;
+  if (n > 1 && !T) return -6;
+  if (n > 0 && nrhs > 0 && !B) return -7;
+  if (ldb < (n > 1 ? n : 1)) return -8;
+  if (!work || ((uintptr_t)work & 255)) return -9;
+  if (lwork < skf_solve_workspace(n, nrhs)) return SKF_EWORK;
+  hipStream_t s = (hipStream_t)stream;
+  const size_t core = solve_workspace_bytes(n, nrhs);
+  int* dinfo_int = (int*)((char*)work + core);
+  int rc = run_solve(n, nrhs, LT, lda, ipiv, T, B, ldb, work, core, dinfo ? dinfo : dinfo_int, s);
+  if (dinfo) return rc;
+  return finish_sync(rc, dinfo_int, s);
+}
+
+size_t skf_refine_workspace(skf_int n, skf_int nrhs) {
+  if (n < 0 || nrhs < 0) return 0;
+  return refine_workspace_bytes(n, nrhs);
+}
+
+int skf_solve_refine(skf_int n, skf_int nrhs, const double* A0, skf_int lda0, const double* LT, skf_int lda,
+                     const int32_t* ipiv, const double* T, const double* B, skf_int ldb, double* X, skf_int ldx,
+                     double tol, int maxit, int* iters, double* berr, void* work, size_t lwork, void* stream) {
+  if (n < 0) return -1;
+  if (nrhs < 0) return -2;
+  if (n > 0 && !A0) return -3;
+  if (lda0 < (n > 1 ? n : 1)) return -4;
+  if (n > 0 && !LT) return -5;
+  if (lda < (n > 1 ? n : 1)) return -6;
+  if (n > 0 && !ipiv) return -7;
+  if (n > 1 && !T) return -8;
+  if (n > 0 && nrhs > 0 && !B) return -9;
+  if (ldb < (n > 1 ? n : 1)) return -10;
+  if (n > 0 && nrhs > 0 && !X) return -11;
+  if (ldx < (n > 1 ? n : 1)) return -12;
+  if (!(tol >= 0.0)) return -13;
+  if (maxit < 0) return -14;
+  if (!work || ((uintptr_t)work & 255)) return -17;
+  if (lwork < skf_refine_workspace(n, nrhs)) return SKF_EWORK;
+  return run_refine(n, nrhs, A0, lda0, LT, lda, ipiv, T, B, ldb, X, ldx, tol, maxit, iters, berr, work, lwork,
+                    (hipStream_t)stream);
+}
+
+int skf_profile_enable(int on) {
+  Profiler& p = prof();
+  std::lock_guard<std::mutex> lk(p.mu);
+  p.on = on != 0;
+  return 0;
+}
+
+int skf_profile_read(double* ms, double* flops, int64_t* launches, int reset) {
+  Profiler& p = prof();
+  std::lock_guard<std::mutex> lk(p.mu);
+  double t[2] = {0, 0}, f[2] = {0, 0};
+  int64_t c[2] = {0, 0};
+  for (const ProfRec& r : p.recs) {
+    SKF_CHECK(hipEventSynchronize(r.b), "profile sync");
+    float e = 0.f;
+    SKF_CHECK(hipEventElapsedTime(&e, r.a, r.b), "profile elapsed");
+    if (r.cls >= 0 && r.cls < 2) {
+      t[r.cls] += e;
+      f[r.cls] += r.flops;
+      c[r.cls] += 1;
+    }
+  }
+  for (int i = 0; i < 2; ++i) {
+    if (ms) ms[i] = t[i];
+    if (flops) flops[i] = f[i];
+    if (launches) launches[i] = c[i];
+  }
+  if (reset) {
+    for (const ProfRec& r : p.recs) {
+      p.pool.push_back(r.a);
+      p.pool.push_back(r.b);
+    }
+    p.recs.clear();
+  }
+  return 0;
+}
+
+}  // extern "C"

@@ -58,6 +58,7 @@ static size_t carve(LtltWork* w, char* base, int64_t n, int nb) {
   w->pis = (int32_t*)take(sizeof(int32_t) * (size_t)std::max<int64_t>(np, 1) * n);
   w->sigma = (int32_t*)take(sizeof(int32_t) * (size_t)std::max<int64_t>(np, 1) * n);
   w->rec = (uint64_t*)take(sizeof(uint64_t) * panel_record_words(gmax));
+  w->mirror = (uint64_t*)take(sizeof(uint64_t) * panel_mirror_words(gmax, nb));
   w->status = (int*)take(256);
   w->bytes = off;
   return off;
@@ -95,6 +96,7 @@ int run_ltlt(int64_t n, double* A, int64_t lda, int32_t* ipiv, double* T, int pr
     return 0;
   }
   if ((rc = launch_fill_u64(w.rec, panel_record_words(gmax), 0, s))) return rc;
+  if ((rc = launch_fill_u64(w.mirror, panel_mirror_words(gmax, nb), 0, s))) return rc;
 
   const int64_t np = npanels_of(n, nb);
   double* buf[2] = {A, w.W};
@@ -119,15 +121,21 @@ int run_ltlt(int64_t n, double* A, int64_t lda, int32_t* ipiv, double* T, int pr
     pp.T = T;
     pp.ipiv = ipiv;
     pp.rec = w.rec;
+    pp.mirror = w.mirror;
     pp.status = w.status;
     pp.tag_base = (uint32_t)k0;
+    prof_begin(s);
     if ((rc = launch_panel(pp, s))) return rc;
+    prof_end(s, 0, 0.0);
     const int64_t lo = k0 + nsteps;
     if (n - lo >= 2 && nsteps % 2 == 0) {
+      prof_begin(s);
       rc = launch_skr2k_perm(n, lo, nsteps / 2, buf[P % 2], ldb[P % 2], buf[(P + 1) % 2],
                              ldb[(P + 1) % 2], pp.pi, w.Lp, w.Wp, n, w.cnext,
                              prec == SKF_PREC_F32_TRAILING, s);
       if (rc) return rc;
+      const double m = (double)(n - lo);
+      prof_end(s, 1, 2.0 * (double)nsteps * m * (m - 1.0) / 2.0);
     }
     if ((rc = launch_copy_panel_L(n, k0, nsteps, w.Lbuf, w.W, n, s))) return rc;
   }

@@ -15,29 +15,34 @@
 // (column recompute = a skew GEMV pair per row).
 //
 // Interchanges are never applied to memory during the panel.  Every row of the
-// active part lives in a "slot" of one workgroup (LDS), and a slot carries its
-// current index psi and the row of the panel-start matrix it came from (hbm).
-// Interchanging rows/columns r and p only relabels two slots; a needed column x
-// of the current matrix is gathered as S(hbm(i), hbm(x)) with S(a,b) = src[a,b]
-// for a > b and -src[b,a] otherwise (strict lower storage).
+// active part lives in a "slot" of one workgroup (LDS columns; lane s%64 of the
+// control wave holds its scalars) and carries its current index psi and the row
+// of the panel-start matrix it came from (hbm).  Interchanging rows/columns r
+// and p only relabels two slots; a needed column x of the current matrix is
+// gathered as S(hbm(i), hbm(x)) with S(a,b) = src[a,b] for a > b and
+// -src[b,a] otherwise (strict lower storage).
 //
-// Grid synchronisation: once per step every workgroup publishes its best
-// candidate (largest |c|, lowest current index on ties) and that row's pair
-// coefficients as 64-bit words (step tag << 32 | 32 payload bits), written and
-// read with agent-scope relaxed atomics.  A reader accepts a word only when its
-// tag matches, so no fence is needed and a torn record cannot be used; records
-// are double-buffered by step parity.  All waits are bounded: past the limit the
-// workgroup records SKF_ETIMEOUT and leaves, so every wave of the grid ends.
+// One step:
+//   control wave: local arg-max (largest |c|, lowest current index on ties) ->
+//   publish a 6-word record -> read every workgroup's record -> global pivot ->
+//   relabel, scale -> gather the new column and fetch the pivot row's pair
+//   coefficients from its workgroup's coefficient mirror;
+//   barrier; all four waves: partial skew GEMV over the pairs so far; barrier;
+//   control wave: finish the column (on a pair's second step also w, the next
+//   pair's first column and the mirror entries of the pair).
+// Cross-workgroup words are 64-bit (tag << 32 | payload), written and read with
+// agent-scope relaxed atomics; a reader accepts a word only when it carries the
+// expected step's tag, so no fence is needed and a torn record is never used.
+// Records are double-buffered by step parity.  Every wait is bounded: past the
+// limit the workgroup records SKF_ETIMEOUT and leaves, so every wave ends.
 #include "skf_internal.h"
 
 namespace skf {
 
 constexpr int kPanelThreads = 256;
-constexpr int kRecHeader = 8;
-constexpr int kRecStride = 8 + 4 * 64 + 8;  // words per record (nb <= 128)
+constexpr int kRecWords = 8;  // psi, (slot<<24 | hbm), c hi, c lo, l0 hi, l0 lo, -, -
 constexpr uint32_t kNoCand = 0xFFFFFFFFu;
 constexpr uint32_t kNonFinite = 0xFFFFFFFEu;
-constexpr uint32_t kTimeout = 0xFFFFFFFDu;
 
 namespace {
 
@@ -47,10 +52,9 @@ __device__ inline uint64_t ld_word(const uint64_t* p) {
 __device__ inline void st_word(uint64_t* p, uint64_t v) {
   __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
-__device__ inline uint64_t mk(uint32_t tag, uint32_t payload) {
-  return ((uint64_t)tag << 32) | payload;
-}
-__device__ inline uint32_t hi32(double x) { return (uint32_t)(__double_as_longlong(x) >> 32); }
+__device__ inline uint64_t mk(uint32_t tag, uint32_t payload) { return ((uint64_t)tag << 32) | payload; }
+__device__ inline uint32_t tag_of(uint64_t w) { return (uint32_t)(w >> 32); }
+__device__ inline uint32_t hi32(double x) { return (uint32_t)((uint64_t)__double_as_longlong(x) >> 32); }
 __device__ inline uint32_t lo32(double x) { return (uint32_t)(__double_as_longlong(x)); }
 __device__ inline double from32(uint32_t h, uint32_t l) {
   return __longlong_as_double((long long)(((uint64_t)h << 32) | l));
@@ -61,332 +65,389 @@ __device__ inline bool better(double a, uint32_t pa, double b, uint32_t pb) {
   return (a > b) || (a == b && pa < pb);
 }
 
-// Wall-clock limit for one wait (the constant 100 MHz counter): 2 s.
-constexpr uint64_t kWaitTicks = 200000000ull;
-
-template <int NB, int SMAX>
-struct PanelSmem {
-  static constexpr int TPR = kPanelThreads / SMAX;  // threads per slot
-  static constexpr int LWLD = NB + 2;               // interleaved Lp/Wp, padded
-  static constexpr int LELD = NB / 2 + 1;
-  double LW[SMAX * LWLD];
-  double LE[SMAX * LELD];
-  double cur[SMAX];
-  int32_t psi[SMAX];
-  int32_t hbm[SMAX];
-  double coef[NB + 8];       // winner's Lp/Wp (interleaved) for pairs < j
-  double red_v[kPanelThreads / 64];
-  uint32_t red_p[kPanelThreads / 64];
-  int32_t red_s[kPanelThreads / 64];
-  int flag;                  // nonzero: non-finite seen locally
-  uint32_t win_psi, win_hbm;
-  int win_g;
-  double win_c, win_l0;
-  int stop;
-  uint32_t cand_hbm[kPanelThreads];
-  double cand_c[kPanelThreads];
-};
-
-// Block-wide arg-best over (v, p, s) held by every thread; result broadcast.
-template <int NT>
-__device__ inline void block_best(double& v, uint32_t& p, int& s, double* rv, uint32_t* rp,
-                                  int32_t* rs) {
+// Wave-wide arg-best over (v, p, s); every lane ends with the result.
+__device__ inline void wave_best(double& v, uint32_t& p, int& s) {
+#pragma unroll
   for (int off = 32; off >= 1; off >>= 1) {
-    double ov = __shfl_xor(v, off);
-    uint32_t op = __shfl_xor(p, off);
-    int os = __shfl_xor(s, off);
+    const double ov = __shfl_xor(v, off);
+    const uint32_t op = __shfl_xor(p, off);
+    const int os = __shfl_xor(s, off);
     if (better(ov, op, v, p)) {
       v = ov;
       p = op;
       s = os;
     }
   }
-  const int w = threadIdx.x >> 6;
-  if ((threadIdx.x & 63) == 0) {
-    rv[w] = v;
-    rp[w] = p;
-    rs[w] = s;
-  }
-  __syncthreads();
-  v = rv[0];
-  p = rp[0];
-  s = rs[0];
-  for (int i = 1; i < NT / 64; ++i)
-    if (better(rv[i], rp[i], v, p)) {
-      v = rv[i];
-      p = rp[i];
-      s = rs[i];
-    }
-  __syncthreads();
 }
 
-template <int NB, int SMAX>
-__global__ void __launch_bounds__(kPanelThreads) panel_kernel(PanelParams P) {
-  typedef PanelSmem<NB, SMAX> Sm;
-  __shared__ Sm sm;
-  constexpr int TPR = Sm::TPR;
-  constexpr int LWLD = Sm::LWLD;
-  constexpr int LELD = Sm::LELD;
+// Wall-clock limit for one wait (the constant 100 MHz counter): 2 s.
+constexpr uint64_t kWaitTicks = 200000000ull;
 
-  const int tid = threadIdx.x;
+template <int NB, int SPL>
+struct PanelSmem {
+  static constexpr int SMAX = 64 * SPL;  // slots per workgroup
+  double Lp[NB / 2][SMAX];               // l' of each pair, per slot
+  double Wp[NB / 2][SMAX];               // w of each pair, per slot
+  double Le[NB / 2][SMAX];               // l of each pair's first step, per slot
+  double part[4][SMAX];                  // partial GEMV sums of the four waves
+  double coefL[NB / 2], coefW[NB / 2];   // pivot row's l', w of the pairs so far
+  int32_t psi[SMAX], hbm[SMAX];
+  double cur[SMAX];
+  int stop;
+};
+
+template <int NB, int SPL>
+__global__ void __launch_bounds__(kPanelThreads) panel_kernel(PanelParams P) {
+  typedef PanelSmem<NB, SPL> Sm;
+  constexpr int SMAX = Sm::SMAX;
+  constexpr int NP = NB / 2;
+  __shared__ Sm sm;
+
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int g = blockIdx.x;
   if (*P.status != 0) return;  // an earlier panel failed: every workgroup leaves at once
   const int64_t n = P.n, k0 = P.k0, ld = P.ld;
   const double* __restrict__ src = P.src;
   const int64_t rowbase = k0 + 1 + (int64_t)g * P.S;
   const int nslots = (int)max((int64_t)0, min((int64_t)P.S, n - rowbase));
+  const int G = P.G;
+  uint64_t* const my_mirror = P.mirror + (size_t)g * SMAX * NP * 4;
 
-  // ---- panel start: slots, zeroed pair storage, column k0 ----
-  for (int i = tid; i < SMAX * LWLD; i += kPanelThreads) sm.LW[i] = 0.0;
-  for (int i = tid; i < SMAX * LELD; i += kPanelThreads) sm.LE[i] = 0.0;
-  if (tid < SMAX) {
-    const int64_t row = rowbase + tid;
-    const bool v = tid < nslots;
-    sm.psi[tid] = v ? (int32_t)row : INT32_MAX;
-    sm.hbm[tid] = v ? (int32_t)row : 0;
-    sm.cur[tid] = v ? src[row + k0 * ld] : 0.0;
-  }
-  if (tid == 0) {
-    sm.flag = 0;
-    sm.stop = 0;
+  for (int i = tid; i < NP * SMAX; i += kPanelThreads) {
+    (&sm.Lp[0][0])[i] = 0.0;
+    (&sm.Wp[0][0])[i] = 0.0;
+    (&sm.Le[0][0])[i] = 0.0;
   }
   if (g == 0)
     for (int64_t i = tid; i <= k0; i += kPanelThreads) P.pi[i] = (int32_t)i;
-  __syncthreads();
 
-  const int slot = tid / TPR;   // slot handled by this thread in per-slot work
-  const int part = tid % TPR;   // which pairs q = part (mod TPR) it sums
+  // control-wave state of slot s = lane + 64 e
+  int32_t psi[SPL], hbm[SPL];
+  double cur[SPL], gat[SPL];
+  double alpha = 0.0, l0 = 0.0;
+  if (wave == 0) {
+#pragma unroll
+    for (int e = 0; e < SPL; ++e) {
+      const int s = lane + 64 * e;
+      const bool v = s < nslots;
+      psi[e] = v ? (int32_t)(rowbase + s) : INT32_MAX;
+      hbm[e] = v ? (int32_t)(rowbase + s) : 0;
+      cur[e] = v ? src[rowbase + s + k0 * ld] : 0.0;
+      gat[e] = 0.0;
+    }
+    if (lane == 0) sm.stop = 0;
+  }
+  __syncthreads();
 
   for (int si = 0; si < P.nsteps; ++si) {
     const int64_t k = k0 + si;
     const int j = si >> 1;
     const int ph = si & 1;
     const uint32_t tag = P.tag_base + (uint32_t)si + 1u;
-    uint64_t* rec_mine = P.rec + ((size_t)(si & 1) * P.G + g) * kRecStride;
+    uint64_t* const recs = P.rec + (size_t)(si & 1) * G * kRecWords;
 
-    // (A) local candidate over active slots (current index >= k+1)
-    double cv = -1.0;
-    uint32_t cp = kNoCand;
-    int cs = -1;
-    if (tid < SMAX && tid < nslots && sm.psi[tid] >= k + 1) {
-      double c = sm.cur[tid];
-      if (!isfinite(c)) sm.flag = 1;
-      cv = fabs(c);
-      cp = (uint32_t)sm.psi[tid];
-      cs = tid;
-    }
-    block_best<kPanelThreads>(cv, cp, cs, sm.red_v, sm.red_p, sm.red_s);
-    const bool nonfinite = sm.flag != 0;
-
-    // (B) publish: header words + the candidate row's pair coefficients
-    {
-      const int nwords = kRecHeader + 4 * j;
-      for (int w = tid; w < nwords; w += kPanelThreads) {
-        uint32_t pay = 0;
-        if (w == 0) {
-          pay = nonfinite ? kNonFinite : cp;
-        } else if (w == 1) {
-          pay = (cs >= 0) ? (uint32_t)sm.hbm[cs] : 0u;
-        } else if (w == 2 || w == 3) {
-          double c = (cs >= 0) ? sm.cur[cs] : 0.0;
-          pay = (w == 2) ? hi32(c) : lo32(c);
-        } else if (w == 4 || w == 5) {
-          double l0 = (cs >= 0) ? sm.LE[cs * LELD + j] : 0.0;
-          pay = (w == 4) ? hi32(l0) : lo32(l0);
-        } else if (w >= kRecHeader) {
-          const int q = (w - kRecHeader) >> 2, e = (w - kRecHeader) & 3;
-          double x = (cs >= 0) ? sm.LW[cs * LWLD + 2 * q + (e >> 1)] : 0.0;
-          pay = (e & 1) ? lo32(x) : hi32(x);
-        }
-        st_word(rec_mine + w, mk(tag, pay));
-      }
-    }
-
-    // (C) gather every workgroup's candidate; reduce to the global pivot
-    {
-      double v = -1.0;
-      uint32_t p = kNoCand;
-      int s = -1;
-      bool bad = false, tout = false;
-      if (tid < P.G) {
-        const uint64_t* r = P.rec + ((size_t)(si & 1) * P.G + tid) * kRecStride;
-        uint64_t w0, w1, w2, w3;
-        const uint64_t t0 = wall_clock64();
-        for (;;) {
-          w0 = ld_word(r + 0);
-          w1 = ld_word(r + 1);
-          w2 = ld_word(r + 2);
-          w3 = ld_word(r + 3);
-          if ((uint32_t)(w0 >> 32) == tag && (uint32_t)(w1 >> 32) == tag &&
-              (uint32_t)(w2 >> 32) == tag && (uint32_t)(w3 >> 32) == tag)
-            break;
-          if (wall_clock64() - t0 > kWaitTicks) {
-            tout = true;
-            break;
-          }
-          __builtin_amdgcn_s_sleep(1);
-        }
-        if (!tout) {
-          const uint32_t ps = (uint32_t)w0;
-          if (ps == kNonFinite) {
-            bad = true;
-          } else if (ps != kNoCand) {
-            const double c = from32((uint32_t)w2, (uint32_t)w3);
-            v = fabs(c);
-            p = ps;
-            s = tid;
-            sm.cand_hbm[tid] = (uint32_t)w1;
-            sm.cand_c[tid] = c;
-          }
-        }
-      }
-      if (bad) atomicOr(&sm.flag, 2);
-      if (tout) atomicOr(&sm.flag, 4);
-      block_best<kPanelThreads>(v, p, s, sm.red_v, sm.red_p, sm.red_s);
-      if (tid == 0) {
-        sm.win_g = s;
-        sm.win_psi = p;
-        sm.stop = (sm.flag & 6) ? sm.flag : (s < 0 ? 4 : 0);
-      }
-      __syncthreads();
-    }
-    if (sm.stop) break;
-    const int wg = sm.win_g;  // >= 0: rows k+1.. are nonempty for every step of a panel
-    const uint64_t* rec_win = P.rec + ((size_t)(si & 1) * P.G + wg) * kRecStride;
-    const int64_t pidx = sm.win_psi;        // pivot row p
-    const int64_t r = k + 1;
-    const double alpha = sm.cand_c[wg];
-    const int64_t hx = sm.cand_hbm[wg];     // panel-start row of the new row r = column x
-
-    // (D) relabel the two slots; record the step
-    if (tid < nslots && pidx != r) {
-      const int32_t ps = sm.psi[tid];
-      if (ps == (int32_t)r) sm.psi[tid] = (int32_t)pidx;
-      else if (ps == (int32_t)pidx) sm.psi[tid] = (int32_t)r;
-    }
-    if (g == 0 && tid == 0) {
-      P.ipiv[r] = (int32_t)pidx;
-      P.T[k] = alpha;
-    }
-    __syncthreads();
-
-    // (E) multipliers: l = c / alpha below row k+1; alpha itself at row k+1
-    if (tid < nslots) {
-      const int32_t ps = sm.psi[tid];
-      double val;
-      bool wr = true;
-      if (ps >= k + 2) val = (alpha != 0.0) ? sm.cur[tid] / alpha : 0.0;
-      else if (ps == r) val = alpha;
-      else wr = false;
-      if (wr) {
-        if (ph == 0) sm.LE[tid * LELD + j] = val;
-        else sm.LW[tid * LWLD + 2 * j] = val;
-      }
-    }
-
-    // (F) the next needed column x = k+1 of the current matrix (the new row r): gather + pair
-    // corrections.  Step k of a pair yields v (pivot column of step k+1); step k+1 yields w
-    // and, through the pair's extra term, the next pair's first pivot column.
-    const int64_t x = k + 1;
-    double gval = 0.0;
-    bool active = false;
-    if (slot < nslots) {
-      const int64_t ps = sm.psi[slot];
-      active = ps >= x + 1;
-      if (active && part == 0) {
-        const int64_t a = sm.hbm[slot];
-        gval = (a > hx) ? src[a + hx * ld] : -src[hx + a * ld];
-      }
-    }
-    // winner's coefficients (pairs < j) and, in the second step, its l_0
-    {
-      const int nw = 4 * j + 2;
-      for (int w = tid; w < nw; w += kPanelThreads) {
-        const int widx = (w < 2) ? 4 + w : kRecHeader + (w - 2);
-        const uint64_t t0 = wall_clock64();
-        uint64_t word;
-        bool tout = false;
-        for (;;) {
-          word = ld_word(rec_win + widx);
-          if ((uint32_t)(word >> 32) == tag) break;
-          if (wall_clock64() - t0 > kWaitTicks) {
-            tout = true;
-            break;
-          }
-          __builtin_amdgcn_s_sleep(1);
-        }
-        if (tout) atomicOr(&sm.flag, 4);
-        // assemble doubles pairwise in LDS: even word = hi, odd word = lo
-        uint32_t* c32 = reinterpret_cast<uint32_t*>(sm.coef);
-        // coef[0] = l0; coef[1 + 2q] = Lx[q], coef[2 + 2q] = Wx[q]
-        const int d = (w < 2) ? 0 : 1 + ((w - 2) >> 1);
-        const int half = (w & 1) ? 0 : 1;  // little endian: hi word at [2d+1]
-        c32[2 * d + half] = (uint32_t)word;
-      }
-    }
-    __syncthreads();
-    if (sm.flag & 4) {
-      if (tid == 0) sm.stop = 4;
-      __syncthreads();
-      break;
-    }
-    double corr = 0.0;
-    if (active) {
-      const double* lw = &sm.LW[slot * LWLD];
-      for (int q = part; q < j; q += TPR) corr += lw[2 * q] * sm.coef[2 + 2 * q] - lw[2 * q + 1] * sm.coef[1 + 2 * q];
-    }
+    if (wave == 0) {
+      // (A) local candidate over active slots (current index >= k+1)
+      double bv = -1.0;
+      uint32_t bp = kNoCand;
+      int bs = -1;
+      bool nonfin = false;
 #pragma unroll
-    for (int off = 1; off < TPR; off <<= 1) corr += __shfl_xor(corr, off);
-    if (part == 0 && slot < nslots) {
-      if (ph == 0) {
-        if (active) sm.cur[slot] = gval + corr;
-      } else {
-        if (active) {
-          const double w = gval + corr;
-          sm.LW[slot * LWLD + 2 * j + 1] = w;
-          const double l = sm.LE[slot * LELD + j];
-          const double lp = sm.LW[slot * LWLD + 2 * j];
-          sm.cur[slot] = w + alpha * (l - sm.coef[0] * lp);
-        } else {
-          sm.LW[slot * LWLD + 2 * j + 1] = 0.0;
+      for (int e = 0; e < SPL; ++e) {
+        if (lane + 64 * e < nslots && psi[e] >= k + 1) {
+          const double c = cur[e];
+          if (!isfinite(c)) nonfin = true;
+          if (better(fabs(c), (uint32_t)psi[e], bv, bp)) {
+            bv = fabs(c);
+            bp = (uint32_t)psi[e];
+            bs = lane + 64 * e;
+          }
+        }
+      }
+      wave_best(bv, bp, bs);
+      nonfin = __any(nonfin);
+
+      // (B) publish this workgroup's record (the owning lane supplies c and hbm)
+      {
+        const int owner = (bs >= 0) ? (bs & 63) : 0;
+        const int oe = (bs >= 0) ? (bs >> 6) : 0;
+        double cval = 0.0;
+        int32_t h = 0;
+#pragma unroll
+        for (int e = 0; e < SPL; ++e)
+          if (e == oe) {
+            cval = cur[e];
+            h = hbm[e];
+          }
+        cval = __shfl(cval, owner);
+        h = __shfl(h, owner);
+        const double lz = (bs >= 0) ? sm.Le[j][bs] : 0.0;
+        uint32_t pay = 0;
+        if (lane == 0) pay = nonfin ? kNonFinite : bp;
+        else if (lane == 1) pay = ((uint32_t)(bs < 0 ? 0 : bs) << 24) | (uint32_t)h;
+        else if (lane == 2) pay = hi32(cval);
+        else if (lane == 3) pay = lo32(cval);
+        else if (lane == 4) pay = hi32(lz);
+        else if (lane == 5) pay = lo32(lz);
+        if (lane < 6) st_word(recs + (size_t)g * kRecWords + lane, mk(tag, pay));
+      }
+
+      // (C) every workgroup's record (lane t reads records t, t+64, ...) -> global pivot
+      double gv = -1.0;
+      uint32_t gp = kNoCand;
+      int gs = -1;
+      bool bad = false, tout = false;
+      double cc[4];
+      uint32_t ch[4];
+      {
+        // all four words of every record this lane reads, re-issued together
+        // while any is stale, so one poll costs one memory round trip
+        uint64_t w[4][4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          const int rr = lane + 64 * q;
+#pragma unroll
+          for (int t = 0; t < 4; ++t) w[q][t] = (rr < G) ? ld_word(recs + (size_t)rr * kRecWords + t) : mk(tag, 0);
+        }
+        uint64_t t0 = 0;
+        for (int it = 0;; ++it) {
+          bool ok = true;
+#pragma unroll
+          for (int q = 0; q < 4; ++q)
+#pragma unroll
+            for (int t = 0; t < 4; ++t) ok = ok && tag_of(w[q][t]) == tag;
+          if (__all(ok)) break;
+          if ((it & 31) == 0) {
+            const uint64_t now = wall_clock64();
+            if (it == 0) t0 = now;
+            else if (now - t0 > kWaitTicks) {
+              tout = true;
+              break;
+            }
+          }
+#pragma unroll
+          for (int q = 0; q < 4; ++q) {
+            const int rr = lane + 64 * q;
+#pragma unroll
+            for (int t = 0; t < 4; ++t)
+              if (tag_of(w[q][t]) != tag) w[q][t] = ld_word(recs + (size_t)rr * kRecWords + t);
+          }
+        }
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          const int rr = lane + 64 * q;
+          cc[q] = 0.0;
+          ch[q] = 0;
+          if (rr < G && !tout) {
+            const uint32_t ps = (uint32_t)w[q][0];
+            if (ps == kNonFinite) {
+              bad = true;
+            } else if (ps != kNoCand) {
+              const double c = from32((uint32_t)w[q][2], (uint32_t)w[q][3]);
+              cc[q] = c;
+              ch[q] = (uint32_t)w[q][1];
+              if (better(fabs(c), ps, gv, gp)) {
+                gv = fabs(c);
+                gp = ps;
+                gs = rr;
+              }
+            }
+          }
+        }
+      }
+      wave_best(gv, gp, gs);
+      bad = __any(bad);
+      tout = __any(tout);
+      int stop = tout ? 4 : (bad ? 2 : (gs < 0 ? 4 : 0));
+      if (!stop) {
+        const int wl = gs & 63, wq = gs >> 6;
+        double wc = 0.0;
+        uint32_t wh = 0;
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+          if (q == wq) {
+            wc = cc[q];
+            wh = ch[q];
+          }
+        alpha = __shfl(wc, wl);
+        const uint32_t hw = __shfl(wh, wl);
+        const int64_t hx = hw & 0xFFFFFFu;  // panel-start row of the new row r (= column x)
+        const int wslot = (int)(hw >> 24);  // its slot inside workgroup gs
+        const int64_t pidx = gp, r = k + 1;
+
+        // (D) relabel the two slots; record the step
+#pragma unroll
+        for (int e = 0; e < SPL; ++e) {
+          if (lane + 64 * e < nslots && pidx != r) {
+            if (psi[e] == (int32_t)r) psi[e] = (int32_t)pidx;
+            else if (psi[e] == (int32_t)pidx) psi[e] = (int32_t)r;
+          }
+        }
+        if (g == 0 && lane == 0) {
+          P.ipiv[r] = (int32_t)pidx;
+          P.T[k] = alpha;
+        }
+
+        // (F, issued first) gather column x = k+1 below its diagonal
+#pragma unroll
+        for (int e = 0; e < SPL; ++e) {
+          gat[e] = 0.0;
+          if (lane + 64 * e < nslots && psi[e] >= k + 2) {
+            const int64_t a = hbm[e];
+            gat[e] = (a > hx) ? src[a + hx * ld] : -src[hx + a * ld];
+          }
+        }
+        // pivot row's coefficients (pairs q < j) from its workgroup's mirror, and its l0
+        {
+          const uint64_t* wm = P.mirror + ((size_t)gs * SMAX + wslot) * NP * 4;
+          const int nw = 4 * j;
+          uint64_t cw[4];
+#pragma unroll
+          for (int i = 0; i < 4; ++i) {
+            const int t = lane + 64 * i;
+            cw[i] = (t < nw) ? ld_word(wm + t) : 0;
+          }
+          const uint64_t* lwp = recs + (size_t)gs * kRecWords + 4 + (lane & 1);
+          uint64_t lw = (lane < 2) ? ld_word(lwp) : mk(tag, 0);
+          uint64_t t0 = 0;
+          for (int it = 0;; ++it) {
+            bool ok = tag_of(lw) == tag;
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+              const int t = lane + 64 * i;
+              ok = ok && (t >= nw || tag_of(cw[i]) == P.tag_base + 2u * (uint32_t)(t >> 2) + 2u);
+            }
+            if (__all(ok)) break;
+            if ((it & 31) == 0) {
+              const uint64_t now = wall_clock64();
+              if (it == 0) t0 = now;
+              else if (now - t0 > kWaitTicks) {
+                tout = true;
+                break;
+              }
+            }
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+              const int t = lane + 64 * i;
+              if (t < nw && tag_of(cw[i]) != P.tag_base + 2u * (uint32_t)(t >> 2) + 2u) cw[i] = ld_word(wm + t);
+            }
+            if (lane < 2 && tag_of(lw) != tag) lw = ld_word(lwp);
+          }
+#pragma unroll
+          for (int i = 0; i < 4; ++i) {
+            const int t = lane + 64 * i;
+            // words of pair q: L hi, L lo, W hi, W lo in lanes 4q' .. 4q'+3
+            const uint32_t lo = (uint32_t)__shfl_down((unsigned)(uint32_t)cw[i], 1);
+            if (t < nw && (t & 1) == 0) {
+              const double v = from32((uint32_t)cw[i], lo);
+              if ((t & 3) == 0) sm.coefL[t >> 2] = v;
+              else sm.coefW[t >> 2] = v;
+            }
+          }
+          const uint32_t l0lo = (uint32_t)__shfl((unsigned)(uint32_t)lw, 1);
+          const uint32_t l0hi = (uint32_t)__shfl((unsigned)(uint32_t)lw, 0);
+          l0 = from32(l0hi, l0lo);
+          tout = __any(tout);
+          if (tout) stop = 4;
+        }
+
+        // (E) multipliers below row k+1, alpha at row k+1
+#pragma unroll
+        for (int e = 0; e < SPL; ++e) {
+          const int s = lane + 64 * e;
+          if (s < nslots) {
+            double val = 0.0;
+            bool wr = true;
+            if (psi[e] >= k + 2) val = (alpha != 0.0) ? cur[e] / alpha : 0.0;
+            else if (psi[e] == (int32_t)r) val = alpha;
+            else wr = false;
+            if (wr) {
+              if (ph == 0) sm.Le[j][s] = val;
+              else sm.Lp[j][s] = val;
+            }
+          }
+        }
+      }
+      if (lane == 0) sm.stop = stop;
+    }
+    __syncthreads();
+    if (sm.stop) break;
+
+    // partial skew GEMV of every slot with the pivot row over pairs q = wave (mod 4), q < j
+#pragma unroll
+    for (int e = 0; e < SPL; ++e) {
+      const int s = lane + 64 * e;
+      double acc = 0.0;
+      for (int q = wave; q < j; q += 4) acc += sm.Lp[q][s] * sm.coefW[q] - sm.Wp[q][s] * sm.coefL[q];
+      sm.part[wave][s] = acc;
+    }
+    __syncthreads();
+
+    if (wave == 0) {
+#pragma unroll
+      for (int e = 0; e < SPL; ++e) {
+        const int s = lane + 64 * e;
+        if (s < nslots) {
+          const double corr = ((sm.part[0][s] + sm.part[1][s]) + sm.part[2][s]) + sm.part[3][s];
+          const bool act = psi[e] >= k + 2;
+          if (ph == 0) {
+            if (act) cur[e] = gat[e] + corr;
+          } else {
+            const double w = act ? gat[e] + corr : 0.0;
+            sm.Wp[j][s] = w;
+            if (act) cur[e] = w + alpha * (sm.Le[j][s] - l0 * sm.Lp[j][s]);
+            // mirror entries of pair j for this slot (read by other workgroups' later steps)
+            const double lp = sm.Lp[j][s];
+            const uint32_t mt = P.tag_base + 2u * (uint32_t)j + 2u;
+            uint64_t* m = my_mirror + ((size_t)s * NP + j) * 4;
+            st_word(m + 0, mk(mt, hi32(lp)));
+            st_word(m + 1, mk(mt, lo32(lp)));
+            st_word(m + 2, mk(mt, hi32(w)));
+            st_word(m + 3, mk(mt, lo32(w)));
+          }
         }
       }
     }
-    __syncthreads();
   }
 
   // ---- panel end ----
   if (sm.stop) {
-    if (tid == 0) {
-      int code = (sm.stop & 4) ? SKF_ETIMEOUT : SKF_ENONFINITE;
-      atomicMin(P.status, code);
-    }
+    if (tid == 0) atomicMin(P.status, (sm.stop & 4) ? SKF_ETIMEOUT : SKF_ENONFINITE);
     return;
   }
+  if (wave == 0) {
+#pragma unroll
+    for (int e = 0; e < SPL; ++e) {
+      const int s = lane + 64 * e;
+      sm.psi[s] = psi[e];
+      sm.hbm[s] = hbm[e];
+      sm.cur[s] = cur[e];
+    }
+  }
+  __syncthreads();
   const int npairs = P.nsteps / 2;
   const int64_t lo = k0 + P.nsteps;
   for (int idx = tid; idx < nslots * P.nsteps; idx += kPanelThreads) {
-    const int t = idx / P.nsteps, c = idx % P.nsteps;
-    const int64_t ps = sm.psi[t];
-    const double v = (c & 1) ? sm.LW[t * LWLD + (c - 1)] : sm.LE[t * LELD + (c >> 1)];
-    P.Lbuf[ps + (int64_t)c * n] = v;
+    const int c = idx / nslots, s = idx % nslots;
+    const double v = (c & 1) ? sm.Lp[c >> 1][s] : sm.Le[c >> 1][s];
+    P.Lbuf[sm.psi[s] + (int64_t)c * n] = v;
   }
   for (int idx = tid; idx < nslots * npairs; idx += kPanelThreads) {
-    const int t = idx / npairs, q = idx % npairs;
-    const int64_t ps = sm.psi[t];
-    P.Lp[ps + (int64_t)q * n] = sm.LW[t * LWLD + 2 * q];
-    P.Wp[ps + (int64_t)q * n] = sm.LW[t * LWLD + 2 * q + 1];
+    const int q = idx / nslots, s = idx % nslots;
+    const int64_t ps = sm.psi[s];
+    P.Lp[ps + (int64_t)q * n] = sm.Lp[q][s];
+    P.Wp[ps + (int64_t)q * n] = sm.Wp[q][s];
   }
-  if (tid < nslots) {
-    const int64_t ps = sm.psi[tid];
-    P.pi[ps] = sm.hbm[tid];
-    if ((P.nsteps & 1) == 0 && ps >= lo + 1) P.cnext[ps] = sm.cur[tid];
+  for (int s = tid; s < nslots; s += kPanelThreads) {
+    const int64_t ps = sm.psi[s];
+    P.pi[ps] = sm.hbm[s];
+    if ((P.nsteps & 1) == 0 && ps >= lo + 1) P.cnext[ps] = sm.cur[s];
   }
 }
 
-template <int NB, int SMAX>
+template <int NB, int SPL>
 int launch_panel_t(const PanelParams& p, hipStream_t s) {
-  hipLaunchKernelGGL((panel_kernel<NB, SMAX>), dim3(p.G), dim3(kPanelThreads), 0, s, p);
+  hipLaunchKernelGGL((panel_kernel<NB, SPL>), dim3(p.G), dim3(kPanelThreads), 0, s, p);
   SKF_CHECK_LAUNCH("panel");
   return 0;
 }
@@ -394,12 +455,14 @@ int launch_panel_t(const PanelParams& p, hipStream_t s) {
 }  // namespace
 
 int launch_panel(const PanelParams& p, hipStream_t s) {
-  if (p.nb == 128 && p.S <= 64) return launch_panel_t<128, 64>(p, s);
-  if (p.nb == 64 && p.S <= 128) return launch_panel_t<64, 128>(p, s);
-  if (p.nb == 64 && p.S <= 64) return launch_panel_t<64, 64>(p, s);
+  if (p.G > 256 || p.n >= (1 << 24)) return SKF_ENOTIMPL;
+  if (p.nb == 128 && p.S <= 64) return launch_panel_t<128, 1>(p, s);
+  if (p.nb == 64 && p.S <= 128) return launch_panel_t<64, 2>(p, s);
   return SKF_ENOTIMPL;
 }
 
-size_t panel_record_words(int G) { return (size_t)2 * G * kRecStride; }
+size_t panel_record_words(int G) { return (size_t)2 * G * kRecWords; }
+
+size_t panel_mirror_words(int G, int nb) { return (size_t)G * 128 * (nb / 2) * 4; }
 
 }  // namespace skf

@@ -83,12 +83,14 @@ struct PanelParams {
   double* T;         // global T output
   int32_t* ipiv;     // global ipiv output
   uint64_t* rec;     // sync records: 2 x G x kRecWords
+  uint64_t* mirror;  // per-workgroup tagged copy of each slot's pair coefficients
   int* status;       // device status word (0 ok)
   uint32_t tag_base; // tag of step k is tag_base + (k - k0) + 1
 };
 
 int launch_panel(const PanelParams& p, hipStream_t s);
 size_t panel_record_words(int G);
+size_t panel_mirror_words(int G, int nb);
 
 // Workspace layout of the blocked path.
 struct LtltWork {
@@ -100,6 +102,7 @@ struct LtltWork {
   int32_t* pis;    // npanels x n: per-panel permutations
   int32_t* sigma;  // npanels x n: composed later permutations
   uint64_t* rec;   // sync records
+  uint64_t* mirror;  // panel coefficient mirrors
   int* status;     // 1 int (+ padding)
   size_t bytes;
 };
@@ -111,6 +114,10 @@ LtltWork ltlt_carve(void* work, int64_t n, int prec);
 
 int run_ltlt(int64_t n, double* A, int64_t lda, int32_t* ipiv, double* T, int prec, void* work,
              size_t lwork, int* dinfo_dev, hipStream_t s);
+
+// Kernel timing hooks (api.hip): no-ops unless skf_profile_enable(1).
+void prof_begin(hipStream_t s);
+void prof_end(hipStream_t s, int cls, double flops);
 
 // Helpers (ltlt_aux.hip)
 int launch_fill_u64(uint64_t* p, size_t count, uint64_t v, hipStream_t s);

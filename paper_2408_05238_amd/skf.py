@@ -31,6 +31,7 @@ EXPORTS = [
     "skf_logpf_workspace", "skf_logpf", "skf_pfaffian", "skf_skr2k", "skf_skr2k_f32",
     "skf_solve_workspace", "skf_solve", "skf_refine_workspace", "skf_solve_refine",
     "skf_batched_workspace", "skf_ltlt_batched", "skf_logpf_batched", "skf_solve_batched",
+    "skf_profile_enable", "skf_profile_read",
 ]
 
 _lib = None
@@ -79,6 +80,8 @@ def _load():
                 "skf_ltlt_batched": (ci, [i64, vp, vp, vp, vp, vp, vp, vp, vp, vp, sz, vp]),
                 "skf_logpf_batched": (ci, [i64, vp, vp, vp, vp, vp, vp, vp, sz, vp]),
                 "skf_solve_batched": (ci, [i64, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, sz, vp]),
+                "skf_profile_enable": (ci, [ci]),
+                "skf_profile_read": (ci, [vp, vp, vp, ci]),
             }
             for name, (res, args) in sig.items():
                 if hasattr(lib, name):
@@ -239,3 +242,47 @@ def skr2k(alpha: float, A, B, beta: float, C, f32: bool = False, stream=None):
             _ld(B) if k > 0 else max(n, 1), float(beta), _ptr(C), _ld(C), _stream(stream))
     _check(rc, "skf_skr2k")
     return C
+
+
+def solve_workspace(n: int, nrhs: int) -> int:
+    return int(_load().skf_solve_workspace(n, nrhs))
+
+
+def solve(LT, ipiv, T, B, work=None, dinfo=None, stream=None):
+    """X = A^{-1} B with the factors of :func:`ltlt`, in place over B (column-major n x nrhs).
+
+    Returns info (int) when ``dinfo`` is None (synchronous), else ``dinfo``.
+    """
+    torch = _torch()
+    n = LT.shape[0]
+    nrhs = B.shape[1] if B.dim() == 2 else 1
+    if work is None:
+        work = workspace(solve_workspace(n, nrhs), LT.device)
+    Tp = T if T.numel() > 0 else torch.zeros(1, dtype=torch.float64, device=LT.device)
+    rc = _load().skf_solve(n, nrhs, _ptr(LT), _ld(LT), _ptr(ipiv), _ptr(Tp), _ptr(B), _ld(B), _ptr(work),
+                           work.numel(), _ptr(dinfo), _stream(stream))
+    _check(rc, "skf_solve")
+    return rc if dinfo is None else dinfo
+
+
+def refine_workspace(n: int, nrhs: int) -> int:
+    return int(_load().skf_refine_workspace(n, nrhs))
+
+
+def solve_refine(A0, LT, ipiv, T, B, X=None, tol: float = 1e-13, maxit: int = 10, work=None, stream=None):
+    """Iterative refinement; returns (X, status, iters, berr).  A0 is the original matrix."""
+    torch = _torch()
+    n = LT.shape[0]
+    nrhs = B.shape[1]
+    if X is None:
+        X = colmajor(n, nrhs, device=LT.device)
+    if work is None:
+        work = workspace(refine_workspace(n, nrhs), LT.device)
+    it = ctypes.c_int(0)
+    be = ctypes.c_double(0.0)
+    Tp = T if T.numel() > 0 else torch.zeros(1, dtype=torch.float64, device=LT.device)
+    rc = _load().skf_solve_refine(n, nrhs, _ptr(A0), _ld(A0), _ptr(LT), _ld(LT), _ptr(ipiv), _ptr(Tp), _ptr(B),
+                                  _ld(B), _ptr(X), _ld(X), float(tol), int(maxit), ctypes.byref(it),
+                                  ctypes.byref(be), _ptr(work), work.numel(), _stream(stream))
+    _check(rc, "skf_solve_refine")
+    return X, rc, int(it.value), float(be.value)

@@ -1,0 +1,79 @@
+"""GPU parity of the solve and the iterative refinement against the CPU oracle."""
+from __future__ import annotations
+
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def skf():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2408_05238_amd import skf as s
+    s.lib()
+    return s
+
+
+def _host(t):
+    return t.detach().cpu().numpy()
+
+
+@pytest.mark.parametrize("n,nrhs", [(2, 1), (4, 3), (64, 16), (66, 5), (130, 17), (300, 16), (513 - 1, 33)])
+def test_solve_parity(skf, oracle_mod, gen, n, nrhs):
+    A = gen.skew_gaussian(n, 900 + n)
+    B = gen.gaussian(n, nrhs, 901 + n)
+    dA = skf.to_device_colmajor(A)
+    ipiv, T, info = skf.ltlt(dA)
+    assert info == 0
+    dB = skf.to_device_colmajor(B)
+    info = skf.solve(dA, ipiv, T, dB)
+    assert info == 0
+    X = _host(dB)
+    # backward error of the GPU solution with the original matrix
+    assert oracle_mod.backward_error(A, X, B) <= 1e-13
+    # against the oracle's solve with the oracle's factors (same pivots)
+    f = oracle_mod.ltlt(A)
+    Xr, inf2 = oracle_mod.solve(f.LT, f.ipiv, f.T, B)
+    assert inf2 == 0
+    scale = np.abs(Xr).max()
+    assert np.abs(X - Xr).max() <= 1e-9 * scale * max(1.0, n / 64)
+
+
+def test_solve_odd_singular(skf, gen):
+    A = gen.skew_gaussian(7, 3)
+    dA = skf.to_device_colmajor(A)
+    ipiv, T, _ = skf.ltlt(dA)
+    dB = skf.to_device_colmajor(np.ones((7, 2)))
+    assert skf.solve(dA, ipiv, T, dB) == 7
+
+
+def test_solve_zero_pivot_info(skf, gen):
+    n = 20
+    A = gen.skew_gaussian(n, 4)
+    A[:, 0] = 0.0
+    A[0, :] = 0.0
+    dA = skf.to_device_colmajor(A)
+    ipiv, T, info = skf.ltlt(dA)
+    assert info == 1
+    dB = skf.to_device_colmajor(np.ones((n, 1)))
+    assert skf.solve(dA, ipiv, T, dB) == 1
+
+
+@pytest.mark.parametrize("n", [256, 1000])
+def test_refine_fp64_and_fp32(skf, oracle_mod, gen, n):
+    A = gen.skew_gaussian(n, 77 + n)
+    B = gen.gaussian(n, 16, 78 + n)
+    A0 = skf.to_device_colmajor(A)
+    dB = skf.to_device_colmajor(B)
+    for prec in (skf.PREC_F64, skf.PREC_F32_TRAILING):
+        dA = A0.clone() if False else skf.to_device_colmajor(A)
+        ipiv, T, info = skf.ltlt(dA, prec=prec)
+        assert info == 0
+        X, st, iters, berr = skf.solve_refine(A0, dA, ipiv, T, dB, tol=1e-13, maxit=20)
+        assert st == 0, (prec, iters, berr)
+        assert berr <= 1e-13
+        Xh = _host(X)
+        assert oracle_mod.backward_error(A, Xh, B) <= 2e-13
