@@ -160,12 +160,16 @@ int skf_solve_refine(skf_int n, skf_int nrhs, const double* A0, skf_int lda0, co
                      double* berr, void* work, size_t lwork, void* stream);
 
 /* Device workspace (bytes) for the batched calls over `batch` matrices of
- * orders n_host[0..batch) (host array). */
+ * orders n_host[0..batch) (host array; includes room for skf_solve_batched
+ * with up to 16 right-hand sides). */
 size_t skf_batched_workspace(skf_int batch, const skf_int* n_host);
 
 /*
- * Batched LTL^T + Pfaffian: `batch` independent skew matrices factored by ONE
- * persistent launch (largest first from a device work queue).
+ * Batched LTL^T + Pfaffian: `batch` independent skew matrices, each of order
+ * n <= 512, factored by ONE persistent launch: every workgroup takes matrices
+ * from a device work queue (largest first) and factors one at a time in its
+ * storage (paired elimination steps, eager interchanges, delayed rank-32
+ * updates).  A matrix's results do not depend on the rest of the batch.
  *   n_host, lda_host  host arrays [batch]: orders and leading dimensions
  *   A                 device array [batch] of device pointers (overwritten by L, T)
  *   ipiv, T           device arrays [batch] of device pointers, or NULL to skip
@@ -183,7 +187,10 @@ int skf_logpf_batched(skf_int batch, const skf_int* n_host, double* const* A, co
 
 /*
  * Batched solves with factors from skf_ltlt_batched: B[b] (n_b x nrhs_host[b],
- * ldb_host[b]) overwritten by X[b].  Pointer arrays are device arrays.
+ * ldb_host[b]) overwritten by X[b].  Pointer arrays are device arrays (read back
+ * to the host once, synchronously); the solves run in order on `stream` and
+ * share the workspace, which must hold skf_solve_workspace of the largest
+ * (n_b, nrhs_b).  info[b] (device) as for skf_solve.
  */
 int skf_solve_batched(skf_int batch, const skf_int* n_host, double* const* LT, const skf_int* lda_host,
                       int32_t* const* ipiv, double* const* T, const skf_int* nrhs_host,

@@ -1,0 +1,398 @@
+// Batched skew LTL^T + Pfaffian: many independent matrices (n <= 512) in ONE
+// persistent launch.
+//
+// Each 256-thread workgroup takes matrix indices from a device work queue
+// (largest n first, so the long factorizations start early) and factors one
+// matrix at a time in its own storage, with no inter-workgroup communication:
+//   * interchanges are applied eagerly to the matrix (the O(n) row/column
+//     segments of the symmetric interchange, lower storage) and to the LDS rows;
+//   * elimination steps are paired as in the single-matrix path: a pair (k,k+1)
+//     contributes one skew rank-2 term l' w^T - w l'^T to the trailing matrix,
+//     and the next pair's first column is w + alpha' (l - l_0 l');
+//   * updates are delayed over a panel of nb = 32 steps: each new pivot column
+//     is the stored (panel-start) column plus a skew GEMV with the panel's
+//     pairs (kept in LDS), and the trailing matrix receives one rank-32 update
+//     per panel;
+//   * the interchange reads the pivot row/column once and thereby also obtains
+//     the next column, so a step costs one memory round trip plus LDS work.
+// Outputs per matrix: L in place (as skf_ltlt), T, ipiv (optional), log|Pf|,
+// sign and the numerical outcome.
+#include <algorithm>
+#include <numeric>
+#include <vector>
+
+#include "skf_internal.h"
+
+namespace skf {
+namespace {
+
+constexpr int BR = 512;   // largest order handled per workgroup
+constexpr int BNP = 16;   // pairs per panel (nb = 32)
+constexpr int BT = 256;   // threads
+constexpr int RPT = BR / BT;
+
+struct BatchArgs {
+  int64_t batch;
+  const int64_t* order;   // matrix indices, largest first
+  const int64_t* nn;      // order of each matrix
+  const int64_t* lda;
+  double* const* A;
+  int32_t* const* ipiv;   // may be null (then scratch)
+  double* const* T;       // may be null (then scratch)
+  double* logabs;
+  int* sign;
+  int* info;
+  int* queue;             // next position in `order`
+  int32_t* ipiv_scratch;  // gridDim.x x BR
+  double* T_scratch;      // gridDim.x x BR
+};
+
+struct Smem {
+  double2 LW[BNP][BR];  // (l', w) of the panel's pairs, by current row
+  double Le[BR];        // multipliers of the current pair's first step
+  double cur[BR];       // current pivot column
+  double rv[BT / 64];
+  int rp[BT / 64];
+  double sum[BT];
+  int par[BT];
+  int item;
+  int piv;
+  double alpha, l0;
+  int flag;
+};
+
+__device__ inline bool better(double a, int pa, double b, int pb) { return (a > b) || (a == b && pa < pb); }
+
+// block arg-max of (v, p) (larger v, then lower p); result broadcast
+__device__ inline void block_argmax(Smem& sm, double v, int p, double* ov, int* op) {
+  for (int off = 32; off >= 1; off >>= 1) {
+    const double v2 = __shfl_xor(v, off);
+    const int p2 = __shfl_xor(p, off);
+    if (better(v2, p2, v, p)) {
+      v = v2;
+      p = p2;
+    }
+  }
+  const int w = threadIdx.x >> 6;
+  if ((threadIdx.x & 63) == 0) {
+    sm.rv[w] = v;
+    sm.rp[w] = p;
+  }
+  __syncthreads();
+  double bv = sm.rv[0];
+  int bp = sm.rp[0];
+  for (int i = 1; i < BT / 64; ++i)
+    if (better(sm.rv[i], sm.rp[i], bv, bp)) {
+      bv = sm.rv[i];
+      bp = sm.rp[i];
+    }
+  *ov = bv;
+  *op = bp;
+  __syncthreads();
+}
+
+__global__ void __launch_bounds__(BT) batched_kernel(BatchArgs a) {
+  __shared__ Smem sm;
+  const int tid = threadIdx.x;
+  for (;;) {
+    if (tid == 0) sm.item = atomicAdd(a.queue, 1);
+    __syncthreads();
+    const int64_t it = sm.item;
+    __syncthreads();
+    if (it >= a.batch) return;
+    const int64_t b = a.order[it];
+    const int64_t n = a.nn[b], ld = a.lda[b];
+    double* A = a.A[b];
+    int32_t* ipiv = a.ipiv ? a.ipiv[b] : a.ipiv_scratch + (size_t)blockIdx.x * BR;
+    double* Tv = a.T ? a.T[b] : a.T_scratch + (size_t)blockIdx.x * BR;
+    if (ipiv == nullptr) ipiv = a.ipiv_scratch + (size_t)blockIdx.x * BR;
+    if (Tv == nullptr) Tv = a.T_scratch + (size_t)blockIdx.x * BR;
+    int status = 0;
+    if (n >= 1 && tid == 0) ipiv[0] = 0;
+    // column 0
+    for (int r = 0; r < RPT; ++r) {
+      const int i = tid + BT * r;
+      sm.cur[i] = (i >= 1 && i < n) ? A[i] : 0.0;
+    }
+    __syncthreads();
+    for (int64_t k0 = 0; k0 < n - 1 && status == 0; k0 += 2 * BNP) {
+      const int nsteps = (int)min((int64_t)2 * BNP, n - 1 - k0);
+      for (int q = 0; q < BNP; ++q)
+        for (int r = 0; r < RPT; ++r) sm.LW[q][tid + BT * r] = make_double2(0.0, 0.0);
+      for (int r = 0; r < RPT; ++r) sm.Le[tid + BT * r] = 0.0;
+      __syncthreads();
+      for (int si = 0; si < nsteps; ++si) {
+        const int64_t k = k0 + si, rr = k + 1;
+        const int j = si >> 1, ph = si & 1;
+        // pivot over rows >= k+1
+        double bv = -1.0;
+        int bp = INT32_MAX;
+        bool nf = false;
+        for (int r = 0; r < RPT; ++r) {
+          const int i = tid + BT * r;
+          if (i >= rr && i < n) {
+            const double c = sm.cur[i];
+            if (!isfinite(c)) nf = true;
+            if (better(fabs(c), i, bv, bp)) {
+              bv = fabs(c);
+              bp = i;
+            }
+          }
+        }
+        if (tid == 0) sm.flag = 0;
+        __syncthreads();
+        if (nf) sm.flag = 1;
+        double gv;
+        int p;
+        block_argmax(sm, bv, bp, &gv, &p);
+        if (sm.flag) {
+          status = SKF_ENONFINITE;
+          break;
+        }
+        const double alpha = sm.cur[p];
+        // symmetric interchange r <-> p (lower storage) and the new column r below r:
+        //   A[i,r] (i > r) := i < p ? -A[p,i] : (i == p ? -A[p,r] : A[i,p])
+        double newc[RPT];
+        for (int r = 0; r < RPT; ++r) {
+          const int i = tid + BT * r;
+          double v = 0.0;
+          if (i > rr && i < n) {
+            if (p != rr) v = (i < p) ? -A[p + (int64_t)i * ld] : (i == p ? -A[p + rr * ld] : A[i + (int64_t)p * ld]);
+            else v = A[i + rr * ld];
+          }
+          newc[r] = v;
+        }
+        if (p != rr) {
+          // row segments left of r (finished columns of L; column k is carried in cur)
+          for (int64_t c = tid; c < k; c += BT) {
+            const double x = A[rr + c * ld], y = A[p + c * ld];
+            A[rr + c * ld] = y;
+            A[p + c * ld] = x;
+          }
+          // column r below r vs row p / column p (old column r moves there)
+          for (int r = 0; r < RPT; ++r) {
+            const int i = tid + BT * r;
+            if (i > rr && i < n) {
+              const double old = A[i + rr * ld];
+              if (i < p) A[p + (int64_t)i * ld] = -old;
+              else if (i == p) A[p + rr * ld] = -old;  // A[p,r] := -A[p,r]
+              else A[i + (int64_t)p * ld] = old;
+            }
+          }
+        }
+        __syncthreads();
+        for (int r = 0; r < RPT; ++r) {
+          const int i = tid + BT * r;
+          if (i > rr && i < n) A[i + rr * ld] = newc[r];
+        }
+        if (p != rr && tid < BNP + 2) {
+          // LDS rows r and p: pairs, current-pair multipliers, pivot column
+          if (tid < BNP) {
+            const double2 t = sm.LW[tid][rr];
+            sm.LW[tid][rr] = sm.LW[tid][p];
+            sm.LW[tid][p] = t;
+          } else if (tid == BNP) {
+            const double t = sm.Le[rr];
+            sm.Le[rr] = sm.Le[p];
+            sm.Le[p] = t;
+          } else {
+            const double t = sm.cur[rr];
+            sm.cur[rr] = sm.cur[p];
+            sm.cur[p] = t;
+          }
+        }
+        if (tid == 0) {
+          Tv[k] = alpha;
+          ipiv[rr] = (int32_t)p;
+        }
+        __syncthreads();
+        // multipliers; column k of the factored array = (alpha; l)
+        for (int r = 0; r < RPT; ++r) {
+          const int i = tid + BT * r;
+          if (i == rr) {
+            A[i + k * ld] = alpha;
+            if (ph == 0) sm.Le[i] = alpha;
+            else sm.LW[j][i].x = alpha;
+          } else if (i > rr && i < n) {
+            const double l = (alpha != 0.0) ? sm.cur[i] / alpha : 0.0;
+            A[i + k * ld] = l;
+            if (ph == 0) sm.Le[i] = l;
+            else sm.LW[j][i].x = l;
+          }
+        }
+        __syncthreads();
+        // next column x = k+1 below its diagonal: stored value + pair corrections
+        const double l0 = sm.Le[rr];
+        for (int r = 0; r < RPT; ++r) {
+          const int i = tid + BT * r;
+          if (i < n && i > rr) {
+            double corr = 0.0;
+            for (int q = 0; q < j; ++q) {
+              const double2 u = sm.LW[q][i], x = sm.LW[q][rr];
+              corr += u.x * x.y - u.y * x.x;
+            }
+            const double g = A[i + rr * ld] + corr;
+            if (ph == 0) {
+              sm.cur[i] = g;
+            } else {
+              sm.LW[j][i].y = g;
+              sm.cur[i] = g + alpha * (sm.Le[i] - l0 * sm.LW[j][i].x);
+            }
+          } else if (i < n && ph == 1) {
+            sm.LW[j][i].y = 0.0;
+          }
+        }
+        __syncthreads();
+      }
+      if (status) break;
+      // trailing update: A[i,jj] += sum_q (l'_i w_jj - w_i l'_jj) for i > jj > lo
+      const int64_t lo = k0 + nsteps;
+      const int npairs = nsteps / 2;
+      if (nsteps % 2 == 0 && n - lo >= 3) {
+        const int64_t c1 = lo + 1;
+        const int64_t m = n - c1;
+        const int64_t nstrip = (m + 7) / 8;
+        // strips of 8 columns; thread handles (strip, row) items
+        for (int64_t sidx = 0; sidx < nstrip; ++sidx) {
+          const int64_t j0 = c1 + sidx * 8;
+          for (int64_t i = j0 + 1 + tid; i < n; i += BT) {
+            double acc[8];
+#pragma unroll
+            for (int t = 0; t < 8; ++t) acc[t] = 0.0;
+            for (int q = 0; q < npairs; ++q) {
+              const double2 u = sm.LW[q][i];
+#pragma unroll
+              for (int t = 0; t < 8; ++t) {
+                const double2 v = sm.LW[q][min(j0 + t, (int64_t)BR - 1)];
+                acc[t] += u.x * v.y - u.y * v.x;
+              }
+            }
+#pragma unroll
+            for (int t = 0; t < 8; ++t) {
+              const int64_t jj = j0 + t;
+              if (jj < i) A[i + jj * ld] += acc[t];
+            }
+          }
+        }
+      }
+      __syncthreads();
+    }
+    // the last column: T[n-2] was produced by the last step (its pivot search saw one row)
+    // Pfaffian: log|Pf| = sum log|T[k even]|, sign from the swaps and the signs
+    double acc = 0.0;
+    int par = 0;
+    if (status == 0 && n % 2 == 0) {
+      const int64_t np2 = n / 2;
+      const int64_t chunk = (np2 + BT - 1) / BT;
+      for (int64_t q = tid * chunk; q < min(np2, (tid + 1) * chunk); ++q) {
+        const double t = Tv[2 * q];
+        if (t == 0.0) par |= 2;
+        if (t < 0.0) par ^= 1;
+        acc += log(fabs(t));
+      }
+      for (int64_t jj = tid; jj < n; jj += BT)
+        if (ipiv[jj] != (int32_t)jj) par ^= 1;
+    }
+    sm.sum[tid] = acc;
+    sm.par[tid] = par;
+    __syncthreads();
+    for (int s = BT / 2; s > 0; s >>= 1) {
+      if (tid < s) {
+        sm.sum[tid] = sm.sum[tid] + sm.sum[tid + s];
+        sm.par[tid] = (sm.par[tid] ^ (sm.par[tid + s] & 1)) | (sm.par[tid + s] & 2);
+      }
+      __syncthreads();
+    }
+    if (tid == 0) {
+      double la;
+      int sg;
+      int inf = status;
+      if (status != 0) {
+        la = NAN;
+        sg = 0;
+      } else if (n == 0) {
+        la = 0.0;
+        sg = 1;
+      } else if (n % 2 == 1 || (sm.par[0] & 2)) {
+        la = -INFINITY;
+        sg = 0;
+      } else {
+        la = sm.sum[0];
+        sg = (((sm.par[0] & 1) ^ (int)((n / 2) & 1)) != 0) ? -1 : 1;
+      }
+      if (inf == 0) {
+        for (int64_t kk = 0; kk + 1 < n; kk += 2)
+          if (Tv[kk] == 0.0) {
+            inf = (int)(kk + 1);
+            break;
+          }
+      }
+      if (a.logabs) a.logabs[b] = la;
+      if (a.sign) a.sign[b] = sg;
+      if (a.info) a.info[b] = inf;
+    }
+    __syncthreads();
+  }
+}
+
+struct BatchedWork {
+  int64_t* order;
+  int64_t* nn;
+  int64_t* lda;
+  int* queue;
+  int32_t* ipiv_scratch;
+  double* T_scratch;
+  size_t bytes;
+};
+
+int batched_grid() { return 2 * device_info().num_cus; }
+
+BatchedWork batched_carve(void* base, int64_t batch) {
+  BatchedWork w{};
+  size_t off = 0;
+  auto take = [&](size_t b) {
+    size_t o = off;
+    off = align_up(off + b, 256);
+    return base ? (void*)((char*)base + o) : nullptr;
+  };
+  const int64_t bb = std::max<int64_t>(batch, 1);
+  w.order = (int64_t*)take(sizeof(int64_t) * bb);
+  w.nn = (int64_t*)take(sizeof(int64_t) * bb);
+  w.lda = (int64_t*)take(sizeof(int64_t) * bb);
+  w.queue = (int*)take(256);
+  w.ipiv_scratch = (int32_t*)take(sizeof(int32_t) * (size_t)batched_grid() * BR);
+  w.T_scratch = (double*)take(sizeof(double) * (size_t)batched_grid() * BR);
+  w.bytes = off;
+  return w;
+}
+
+}  // namespace
+
+size_t batched_workspace_bytes(int64_t batch) { return batched_carve(nullptr, batch).bytes; }
+
+int batched_max_n() { return BR; }
+
+// Host arrays n_host, lda_host are staged into the workspace (synchronous copy
+// of O(batch) words); everything else is asynchronous on `s`.
+int run_batched(int64_t batch, const int64_t* n_host, double* const* A, const int64_t* lda_host,
+                int32_t* const* ipiv, double* const* T, double* logabs, int* sign, int* info, void* work,
+                size_t lwork, hipStream_t s) {
+  BatchedWork w = batched_carve(work, batch);
+  if (lwork < w.bytes) return SKF_EWORK;
+  if (batch == 0) return 0;
+  std::vector<int64_t> order((size_t)batch);
+  std::iota(order.begin(), order.end(), (int64_t)0);
+  std::stable_sort(order.begin(), order.end(), [&](int64_t x, int64_t y) { return n_host[x] > n_host[y]; });
+  SKF_CHECK(hipMemcpyAsync(w.order, order.data(), sizeof(int64_t) * batch, hipMemcpyHostToDevice, s), "order");
+  SKF_CHECK(hipMemcpyAsync(w.nn, n_host, sizeof(int64_t) * batch, hipMemcpyHostToDevice, s), "n");
+  SKF_CHECK(hipMemcpyAsync(w.lda, lda_host, sizeof(int64_t) * batch, hipMemcpyHostToDevice, s), "lda");
+  SKF_CHECK(hipStreamSynchronize(s), "stage");  // the host vectors go out of scope
+  int rc;
+  if ((rc = launch_fill_i32(w.queue, 1, 0, s))) return rc;
+  BatchArgs args{batch, w.order, w.nn, w.lda, A, ipiv, T, logabs, sign, info, w.queue, w.ipiv_scratch, w.T_scratch};
+  hipLaunchKernelGGL(batched_kernel, dim3((unsigned)batched_grid()), dim3(BT), 0, s, args);
+  SKF_CHECK_LAUNCH("batched");
+  return 0;
+}
+
+}  // namespace skf

@@ -11,31 +11,41 @@
 // panels' permutations are composed and L is copied into A in final row order.
 // The host only enqueues; nothing waits on the device inside the loop.
 #include <algorithm>
+#include <stdlib.h>
 
 #include "skf_internal.h"
 
 namespace skf {
 
-static constexpr int kSlotsNB128 = 64;
-static constexpr int kSlotsNB64 = 128;
+// The panel kernel is one wave per workgroup with 64 row slots; LDS holds three
+// (nb/2) x 64 FP64 arrays per workgroup (96 KB at nb = 128, 48 KB at nb = 64), so
+// a CU hosts one (nb = 128) or three (nb = 64) of them at once.  Every
+// workgroup of a panel launch must be resident together.
+static constexpr int kSlots = 64;
+static constexpr int kMaxPanelG = 512;
+
+static int64_t max_panel_groups(int nb) {
+  const int64_t per_cu = (nb == 128) ? 1 : 3;
+  return std::min<int64_t>(kMaxPanelG, per_cu * device_info().num_cus);
+}
 
 int ltlt_plan_nb(int64_t n) {
-  const int cus = device_info().num_cus;
-  // nb = 128 needs every panel row in one of <= num_cus workgroups of 64 slots
-  if (n - 1 <= (int64_t)kSlotsNB128 * cus) return 128;
-  if (n - 1 <= (int64_t)kSlotsNB64 * cus) return 64;
+  const int64_t g0 = std::max<int64_t>(1, (n - 1 + kSlots - 1) / kSlots);
+  // override for tests and tuning: SKF_NB=64 or 128 (ignored when infeasible)
+  if (const char* e = getenv("SKF_NB")) {
+    const int want = atoi(e);
+    if ((want == 64 || want == 128) && g0 <= max_panel_groups(want)) return want;
+  }
+  if (g0 <= max_panel_groups(128)) return 128;
+  if (g0 <= max_panel_groups(64)) return 64;
   return -1;
 }
 
 int ltlt_panel_grid(int64_t m, int nb, int* G, int* S) {
-  const int smax = (nb == 128) ? kSlotsNB128 : kSlotsNB64;
-  const int cus = device_info().num_cus;
-  int64_t g = (m + smax - 1) / smax;
-  if (g < 1) g = 1;
-  if (g > cus) return SKF_ENOTIMPL;
-  int64_t s = (m + g - 1) / g;
+  const int64_t g = std::max<int64_t>(1, (m + kSlots - 1) / kSlots);
+  if (g > max_panel_groups(nb)) return SKF_ENOTIMPL;
   *G = (int)g;
-  *S = (int)std::max<int64_t>(s, 1);
+  *S = kSlots;
   return 0;
 }
 
@@ -49,7 +59,7 @@ static size_t carve(LtltWork* w, char* base, int64_t n, int nb) {
     return base ? (void*)(base + o) : nullptr;
   };
   const int64_t np = npanels_of(n, nb);
-  const int gmax = std::max(1, device_info().num_cus);
+  const int gmax = (int)std::max<int64_t>(1, (n - 1 + kSlots - 1) / kSlots);  // first (largest) panel
   w->W = (double*)take(sizeof(double) * (size_t)n * n);
   w->Lbuf = (double*)take(sizeof(double) * (size_t)n * nb);
   w->Lp = (double*)take(sizeof(double) * (size_t)n * (nb / 2));
@@ -87,7 +97,7 @@ int run_ltlt(int64_t n, double* A, int64_t lda, int32_t* ipiv, double* T, int pr
   if (nb < 0) return SKF_ENOTIMPL;
   LtltWork w = ltlt_carve(work, n, prec);
   if (lwork < w.bytes) return SKF_EWORK;
-  const int gmax = std::max(1, device_info().num_cus);
+  const int gmax = (int)std::max<int64_t>(1, (n - 1 + kSlots - 1) / kSlots);
   int rc;
   if ((rc = launch_fill_i32(w.status, 1, 0, s))) return rc;
   if ((rc = launch_fill_i32(ipiv, 1, 0, s))) return rc;  // ipiv[0] = 0

@@ -5,7 +5,7 @@
 #include <stddef.h>
 #include <stdint.h>
 
-#include "../../include/skf.h"
+#include "skf.h"
 
 namespace skf {
 

@@ -286,3 +286,70 @@ def solve_refine(A0, LT, ipiv, T, B, X=None, tol: float = 1e-13, maxit: int = 10
                                   ctypes.byref(be), _ptr(work), work.numel(), _stream(stream))
     _check(rc, "skf_solve_refine")
     return X, rc, int(it.value), float(be.value)
+
+
+def batched_workspace(n_list) -> int:
+    import numpy as np
+    arr = np.ascontiguousarray(np.asarray(n_list, dtype=np.int64))
+    return int(_load().skf_batched_workspace(len(arr), arr.ctypes.data_as(ctypes.c_void_p)))
+
+
+def ltlt_batched(mats, with_factors: bool = True, work=None, stream=None):
+    """Factor a list of column-major skew matrices (n <= 512) in one persistent launch.
+
+    Returns (logabs, sign, info, ipivs, Ts) as device tensors (ipivs / Ts are
+    lists, or None when ``with_factors`` is False).  Asynchronous on the stream.
+    """
+    import numpy as np
+    torch = _torch()
+    dev = mats[0].device if mats else torch.device("cuda")
+    B = len(mats)
+    n_h = np.array([m.shape[0] for m in mats], dtype=np.int64)
+    lda_h = np.array([_ld(m) if m.shape[0] > 0 else 1 for m in mats], dtype=np.int64)
+    aptr = torch.tensor([m.data_ptr() for m in mats] or [0], dtype=torch.int64, device=dev)
+    logabs = torch.empty(max(B, 1), dtype=torch.float64, device=dev)
+    sign = torch.empty(max(B, 1), dtype=torch.int32, device=dev)
+    info = torch.empty(max(B, 1), dtype=torch.int32, device=dev)
+    if work is None:
+        work = workspace(batched_workspace(n_h), dev)
+    ipivs = Ts = None
+    if with_factors:
+        ipivs = [torch.empty(max(int(n), 1), dtype=torch.int32, device=dev) for n in n_h]
+        Ts = [torch.empty(max(int(n) - 1, 1), dtype=torch.float64, device=dev) for n in n_h]
+        pp = torch.tensor([t.data_ptr() for t in ipivs] or [0], dtype=torch.int64, device=dev)
+        tp = torch.tensor([t.data_ptr() for t in Ts] or [0], dtype=torch.int64, device=dev)
+        rc = _load().skf_ltlt_batched(B, n_h.ctypes.data_as(ctypes.c_void_p), _ptr(aptr),
+                                      lda_h.ctypes.data_as(ctypes.c_void_p), _ptr(pp), _ptr(tp), _ptr(logabs),
+                                      _ptr(sign), _ptr(info), _ptr(work), work.numel(), _stream(stream))
+        ipivs = [ip[:int(n)] for ip, n in zip(ipivs, n_h)]
+        Ts = [t[:max(int(n) - 1, 0)] for t, n in zip(Ts, n_h)]
+    else:
+        rc = _load().skf_logpf_batched(B, n_h.ctypes.data_as(ctypes.c_void_p), _ptr(aptr),
+                                       lda_h.ctypes.data_as(ctypes.c_void_p), _ptr(logabs), _ptr(sign), _ptr(info),
+                                       _ptr(work), work.numel(), _stream(stream))
+    _check(rc, "skf_ltlt_batched")
+    return logabs[:B], sign[:B], info[:B], ipivs, Ts
+
+
+def logpf_batched_packed(buf, offsets, n_list, work=None, stream=None):
+    """log|Pf| of matrices packed in one device buffer (matrix b at element offset
+    offsets[b], column-major with lda = n_b).  One persistent launch."""
+    import numpy as np
+    torch = _torch()
+    dev = buf.device
+    n_h = np.ascontiguousarray(np.asarray(n_list, dtype=np.int64))
+    lda_h = np.maximum(n_h, 1)
+    B = len(n_h)
+    base = buf.data_ptr()
+    aptr = torch.tensor((base + 8 * np.asarray(offsets, dtype=np.int64)).tolist() or [0], dtype=torch.int64,
+                        device=dev)
+    logabs = torch.empty(max(B, 1), dtype=torch.float64, device=dev)
+    sign = torch.empty(max(B, 1), dtype=torch.int32, device=dev)
+    info = torch.empty(max(B, 1), dtype=torch.int32, device=dev)
+    if work is None:
+        work = workspace(batched_workspace(n_h), dev)
+    rc = _load().skf_logpf_batched(B, n_h.ctypes.data_as(ctypes.c_void_p), _ptr(aptr),
+                                   lda_h.ctypes.data_as(ctypes.c_void_p), _ptr(logabs), _ptr(sign), _ptr(info),
+                                   _ptr(work), work.numel(), _stream(stream))
+    _check(rc, "skf_logpf_batched")
+    return logabs[:B], sign[:B], info[:B], aptr

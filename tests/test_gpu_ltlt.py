@@ -210,3 +210,17 @@ def test_ltlt_repeatable(skf, gen):
     r1 = _factor_gpu(skf, A)
     r2 = _factor_gpu(skf, A)
     assert np.array_equal(r1[0], r2[0]) and np.array_equal(r1[2], r2[2])
+
+
+@pytest.mark.parametrize("n", [300, 777])
+def test_ltlt_parity_nb64(skf, oracle_mod, gen, n, monkeypatch):
+    """The narrower panel (used when the matrix needs more than one CU's worth of slots per CU)."""
+    monkeypatch.setenv("SKF_NB", "64")
+    A = gen.skew_gaussian(n, 6000 + n)
+    ref = oracle_mod.ltlt(A)
+    LT, ipiv, T, info = _factor_gpu(skf, A)
+    assert info == 0 and np.array_equal(ipiv, ref.ipiv)
+    assert oracle_mod.recon_residual(A, LT, ipiv, T) <= RECON_TOL
+    la_g, s_g = oracle_mod.logpf_from_factors(n, ipiv, T)
+    la_r, s_r = oracle_mod.logpf_from_factors(n, ref.ipiv, ref.T)
+    assert s_g == s_r and oracle_mod.isclose_log(la_g, la_r) <= LOGPF_TOL
