@@ -41,6 +41,12 @@ def parse():
     ap.add_argument("--cpu-seconds", type=float, default=12.0, help="target CPU time of the oracle sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--traffic", default=os.path.join(ROOT, "profiles", "skr2k_perm_n16384_traffic.txt"))
+    ap.add_argument("--workload", choices=["ltlt", "mixed", "batched", "serve"], default="ltlt",
+                    help="ltlt: the headline factorization; mixed: FP32-trailing + refinement vs FP64 solves "
+                         "(n=16384, 32768, 16 RHS); batched: 8192 small matrices in one launch; serve: "
+                         "2000-request Poisson trace")
+    ap.add_argument("--sizes", default="16384,32768", help="orders for --workload mixed")
+    ap.add_argument("--count", type=int, default=0, help="matrices (batched) or requests (serve); 0 = default")
     return ap.parse_args()
 
 
@@ -87,12 +93,213 @@ def cpu_baseline(A_host, n: int, target_s: float):
                       f"nominal flops sum_k (n-k-1)^2 = {flops:.3e}, {dt:.2f} s"}
 
 
+def _device():
+    import torch
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    from paper_2408_05238_amd import skf
+    skf.lib()  # raises if libskf.so is missing: there is no fallback path
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    return dev
+
+
+def _line(metric, value, unit, ms_per_step, args, dtype, workload, higher=True, **extra):
+    out = {"metric": metric, "value": value, "unit": unit, "n_gpus": 1, "steps": args.steps,
+           "warmup": args.warmup, "ms_per_step": ms_per_step, "higher_is_better": higher, "scaling": "weak",
+           "vs_baseline": None, "dtype": dtype, "data": "synthetic", "config": {"workload": workload}}
+    out.update(extra)
+    print(json.dumps(out), flush=True)
+
+
+def bench_mixed(args):
+    """FP64 factor + solve against FP32-trailing factor + refined solve, 16 RHS.
+
+    A: seed 5; B: seed 6.  Each step factors a pre-loaded copy and solves.
+    """
+    import numpy as np
+    import torch
+
+    from paper_2408_05238_amd import inputs, skf
+    dev = _device()
+    nrhs = 16
+    rows = []
+    for n in [int(x) for x in args.sizes.split(",") if x]:
+        A = inputs.skew_gaussian(n, 5, inputs.STREAM_A, threads=16)
+        Bh = inputs.gaussian(n, nrhs, 6, inputs.STREAM_B)
+        A0 = skf.to_device_colmajor(A, device=dev)
+        del A
+        B = skf.to_device_colmajor(Bh, device=dev)
+        res = {}
+        for prec_name, prec in (("f64", skf.PREC_F64), ("f32_refine", skf.PREC_F32_TRAILING)):
+            LT = skf.colmajor(n, n, device=dev)
+            ipiv = torch.empty(n, dtype=torch.int32, device=dev)
+            T = torch.empty(n - 1, dtype=torch.float64, device=dev)
+            wl = skf.workspace(skf.ltlt_workspace(n, prec), dev)
+            dinfo = torch.zeros(1, dtype=torch.int32, device=dev)
+            X = skf.colmajor(n, nrhs, device=dev)
+            ws = skf.workspace(max(skf.solve_workspace(n, nrhs), skf.refine_workspace(n, nrhs)), dev)
+            times, tf = [], []
+            for it in range(args.warmup + args.steps):
+                LT.copy_(A0)
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                skf.ltlt(LT, ipiv, T, prec, wl, dinfo)
+                torch.cuda.synchronize()
+                t1 = time.perf_counter()
+                if prec == skf.PREC_F64:
+                    X.copy_(B)
+                    skf.solve(LT, ipiv, T, X, work=ws, dinfo=dinfo)
+                    st, iters = 0, 0
+                else:
+                    _, st, iters, berr = skf.solve_refine(A0, LT, ipiv, T, B, X=X, tol=1e-13, maxit=10, work=ws)
+                torch.cuda.synchronize()
+                t2 = time.perf_counter()
+                if it >= args.warmup:
+                    times.append(t2 - t0)
+                    tf.append(t1 - t0)
+            assert int(dinfo.item()) == 0
+            Xh = X.cpu().numpy()
+            # backward error max_j |b_j - A x_j|_inf / (|A|_inf |x_j|_inf + |b_j|_inf), FP64 on the device
+            F = _full_skew(A0)
+            R = B - torch.matmul(F, X)
+            eta = float((R.abs().amax(0) / (F.abs().sum(1).amax() * X.abs().amax(0)
+                                            + B.abs().amax(0))).amax().item())
+            del F, R
+            la, sg = skf.logpf_from_factors(n, ipiv, T)
+            res[prec_name] = {"ms": round(1e3 * float(np.median(times)), 2),
+                              "factor_ms": round(1e3 * float(np.median(tf)), 2),
+                              "factor_gflops": round(n ** 3 / 3 / float(np.median(tf)) / 1e9, 1),
+                              "iters": iters, "status": st, "backward_error": eta,
+                              "logabs_pf": float(la.item()), "sign": int(sg.item()),
+                              "ipiv": ipiv.cpu().numpy()}
+            del LT, wl, ws, X, Xh
+            torch.cuda.empty_cache()
+        p64, p32 = res["f64"], res["f32_refine"]
+        rows.append({"n": n, "f64": {k: v for k, v in p64.items() if k != "ipiv"},
+                     "f32_refine": {k: v for k, v in p32.items() if k != "ipiv"},
+                     "speedup_total": round(p64["ms"] / p32["ms"], 3),
+                     "speedup_factor": round(p64["factor_ms"] / p32["factor_ms"], 3),
+                     "pivot_mismatches_vs_f64": int((p64["ipiv"] != p32["ipiv"]).sum()),
+                     "logpf_rel_diff_vs_f64": abs(p32["logabs_pf"] - p64["logabs_pf"]) /
+                     max(1.0, abs(p64["logabs_pf"]))})
+        del A0, B
+        torch.cuda.empty_cache()
+    head = rows[0]
+    _line("LTL^T factor + 16-RHS solve, FP32-trailing + refinement vs FP64 (speedup)",
+          head["speedup_total"], "x", head["f32_refine"]["ms"], args, "f64 storage, f32 trailing products",
+          f"skew Gaussian n={','.join(str(r['n']) for r in rows)} (seed 5), B 16 Gaussian columns (seed 6), "
+          f"refine to backward error 1e-13", results=rows)
+
+
+def _full_skew(L):
+    """Full skew matrix from the strict lower triangle of a device matrix (torch)."""
+    import torch
+    low = torch.tril(L, -1)
+    return low - low.T
+
+
+def bench_batched(args):
+    """8192 matrices, even n uniform on [32, 512] (seed 7), log|Pf| and sign in one launch."""
+    import concurrent.futures as cf
+
+    import numpy as np
+    import torch
+
+    from paper_2408_05238_amd import inputs, skf
+    dev = _device()
+    count = args.count or 8192
+    n_list = inputs.even_sizes(count, 32, 512, 7).astype(np.int64)
+    offs = np.zeros(count + 1, dtype=np.int64)
+    offs[1:] = np.cumsum(n_list * n_list)
+    host = torch.empty(int(offs[-1]), dtype=torch.float64).pin_memory()
+    hv = host.numpy()
+
+    def fill(b):
+        n = int(n_list[b])
+        hv[offs[b]:offs[b + 1]] = inputs.batch_matrix(n, 7, b).ravel(order="F")
+    with cf.ThreadPoolExecutor(16) as pool:
+        list(pool.map(fill, range(count)))
+    src = host.to(dev)
+    del host, hv
+    nrun = args.warmup + args.steps
+    copies = [src.clone() for _ in range(nrun)]
+    work = skf.workspace(skf.batched_workspace(n_list), dev)
+    torch.cuda.synchronize()
+    outs = []
+    for i in range(args.warmup):
+        outs.append(skf.logpf_batched_packed(copies[i], offs[:-1], n_list, work=work))
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(args.warmup, nrun):
+        outs.append(skf.logpf_batched_packed(copies[i], offs[:-1], n_list, work=work))
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / args.steps
+    la, sg, info, _ = outs[-1]
+    assert int(info.abs().sum().item()) == 0
+    same = all(torch.equal(o[0], la) and torch.equal(o[1], sg) for o in outs)
+    flops = float((n_list.astype(np.float64) ** 3).sum() / 3)
+    bytes_ = float((n_list * (n_list - 1) // 2).sum() * 8)
+    extra = {"gflops_nominal": round(flops / dt / 1e9, 1), "hbm_gbs_min_bytes": round(bytes_ / dt / 1e9, 1),
+             "runs_bitwise_identical": same, "sum_n3_over_3": flops}
+    if not args.no_cpu_baseline:
+        import oracle
+        t = time.perf_counter()
+        k = 0
+        while time.perf_counter() - t < min(args.cpu_seconds, 10.0) and k < count:
+            n = int(n_list[k])
+            oracle.logpf(inputs.batch_matrix(n, 7, k))
+            k += 1
+        ct = time.perf_counter() - t
+        extra["cpu_baseline"] = {"value": round(k / ct, 1), "unit": "Pf/s", "cores": 1, "kind": "oracle",
+                                 "sample": f"first {k} matrices of the batch, one at a time"}
+    _line("batched Pf/s (8192 skew matrices, even n uniform on [32,512])", round(count / dt, 1), "Pf/s",
+          round(dt * 1e3, 3), args, "f64", f"{count} skew Gaussian matrices, even n uniform on [32,512] (seed 7), "
+          f"log|Pf| and sign in one persistent launch", **extra)
+
+
+def bench_serve(args):
+    """2000-request Poisson trace (seed 8): saturation run, then 0.7 x saturation."""
+    import torch
+
+    from paper_2408_05238_amd import serve
+    dev = _device()
+    count = args.count or 2000
+    ex = serve.GpuExecutor(str(dev))
+    reqs, mids = serve.make_workload(count, rate_hz=0.0, seed=8)
+    serve.materialize(reqs, mids, seed=8, device=dev, threads=16)
+    torch.cuda.synchronize()
+    # warm the code paths (one request of each kind)
+    for r in reqs[:8]:
+        ex.run([r], None)
+    sch = serve.Scheduler(ex, budget_bytes=64 << 30, workers=8)
+    t0 = time.perf_counter()
+    sch.run_trace(reqs, t0=t0)
+    sat = sch.stats(t0)
+    rate = 0.7 * sat["req_per_s"]
+    reqs2, _ = serve.make_workload(count, rate_hz=rate, seed=8)
+    for a, b in zip(reqs2, reqs):
+        a.A, a.B = b.A, b.B
+    sch2 = serve.Scheduler(ex, budget_bytes=64 << 30, workers=8)
+    t0 = time.perf_counter()
+    sch2.run_trace(reqs2, t0=t0)
+    st = sch2.stats(t0)
+    _line("serving p99 latency at 0.7x saturation (2000 Poisson requests)", round(st["p99_ms"], 3), "ms",
+          round(st["mean_ms"], 3), args, "f64 / f32-trailing+refine",
+          f"{count} Poisson requests, n log-uniform on [64,4096] (seed 8), 70% FP64 / 30% FP32+refine, "
+          f"Pf:solve 50:50, 16 RHS, 64 GB budget", higher=False,
+          saturation={k: (round(v, 3) if isinstance(v, float) else v) for k, v in sat.items()},
+          at_rate_hz=round(rate, 2),
+          serving={k: (round(v, 3) if isinstance(v, float) else v) for k, v in st.items()})
+
+
 def main():
     args = parse()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); the factorization is not "
               f"sharded across GPUs in this build.", file=sys.stderr)
         sys.exit(2)
+    if args.workload != "ltlt":
+        return {"mixed": bench_mixed, "batched": bench_batched, "serve": bench_serve}[args.workload](args)
     import numpy as np
     import torch
 

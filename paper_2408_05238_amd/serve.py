@@ -1,0 +1,429 @@
+"""Continuous-batching request loop for Pfaffian and solve jobs on one GPU.
+
+Requests arrive over time; the scheduler admits them as workers, HBM budget and
+compute tokens free up, so work of different requests overlaps on the device
+(one HIP stream per worker):
+
+* HBM budget: every admitted request reserves the bytes it will hold (working
+  copy of A, factorization workspace, right-hand sides, the original matrix for
+  refinement); factors of finished requests stay resident in an LRU cache keyed
+  by (matrix id, precision) and are evicted when an admission needs the room.
+  A request whose factors are resident skips the factorization.
+* compute tokens: a factorization of order n > 512 launches persistent panel
+  kernels of ceil((n-1)/64) workgroups that must be co-resident; the scheduler
+  only runs factorizations whose token sum fits the device's CU count, so two of
+  them can never wait on each other for residency.
+* continuous batching: small Pfaffian requests (n <= 512) waiting together are
+  factored by one persistent batched launch.
+* FIFO with overtaking: a request that does not fit yet does not block smaller
+  ones behind it.
+
+The scheduling core (`Scheduler`) is independent of the GPU: it drives an
+executor object and a clock, so its admission, eviction and accounting logic can
+be exercised with a fake executor and a fake clock.
+"""
+from __future__ import annotations
+
+import collections
+import dataclasses
+import math
+import threading
+import time
+from typing import Callable, Dict, List, Optional
+
+
+@dataclasses.dataclass
+class Request:
+    rid: int
+    kind: str            # "pf" or "solve"
+    n: int
+    prec: str            # "f64" or "f32" (FP32 trailing update + refinement for solves)
+    matrix_id: int
+    arrival: float       # seconds from the start of the trace
+    nrhs: int = 16
+    A: object = None     # client-owned device tensor (column-major), read-only
+    B: object = None     # client-owned right-hand sides for solves
+
+
+@dataclasses.dataclass
+class Result:
+    rid: int
+    arrival: float
+    start: float = 0.0
+    end: float = 0.0
+    logabs: float = float("nan")
+    sign: int = 0
+    info: int = 0
+    X: object = None
+    iters: int = 0
+    berr: float = 0.0
+    cached: bool = False
+    batched: bool = False
+
+    @property
+    def latency(self) -> float:
+        return self.end - self.arrival
+
+
+def percentile(values: List[float], q: float) -> float:
+    """Nearest-rank percentile (q in [0, 100])."""
+    if not values:
+        return float("nan")
+    v = sorted(values)
+    r = max(1, int(math.ceil(q / 100.0 * len(v))))
+    return v[min(r, len(v)) - 1]
+
+
+SMALL_N = 512
+
+
+def factor_bytes(n: int) -> int:
+    """Resident factors: the factored array, ipiv and T."""
+    return 8 * n * n + 4 * n + 8 * n
+
+
+def request_bytes(req: Request, ex, have_factors: bool) -> int:
+    """Device bytes a request holds while it runs (besides cached factors).
+
+    `ex` supplies the library's workspace queries (ltlt_ws, solve_ws, refine_ws).
+    """
+    n = req.n
+    b = 0
+    if not have_factors:
+        b += factor_bytes(n) + ex.ltlt_ws(n, 0 if req.prec == "f64" else 1)
+    if req.kind == "solve":
+        b += 2 * 8 * n * req.nrhs          # right-hand sides and solution
+        if req.prec == "f32":
+            b += ex.refine_ws(n, req.nrhs)
+        else:
+            b += ex.solve_ws(n, req.nrhs)
+    return b
+
+
+def tokens(req: Request, have_factors: bool) -> int:
+    if have_factors or req.n <= SMALL_N:
+        return 0
+    return (req.n - 1 + 63) // 64
+
+
+class FactorCache:
+    """LRU of resident factors under the shared budget.  Entries in use by a
+    running request are pinned and never evicted."""
+
+    def __init__(self):
+        self.entries: "collections.OrderedDict[tuple, tuple]" = collections.OrderedDict()
+        self.pins: Dict[tuple, int] = {}
+        self.bytes = 0
+
+    def get(self, key):
+        if key in self.entries:
+            self.entries.move_to_end(key)
+            return self.entries[key][0]
+        return None
+
+    def put(self, key, value, nbytes):
+        if key in self.entries:
+            self.bytes -= self.entries.pop(key)[1]
+        self.entries[key] = (value, nbytes)
+        self.bytes += nbytes
+
+    def pin(self, key):
+        self.pins[key] = self.pins.get(key, 0) + 1
+
+    def unpin(self, key):
+        self.pins[key] -= 1
+        if not self.pins[key]:
+            del self.pins[key]
+
+    def evict_lru(self, protect=None) -> bool:
+        """Drop the least recently used unpinned entry; False if there is none."""
+        for key in self.entries:
+            if key != protect and key not in self.pins:
+                _, nb = self.entries.pop(key)
+                self.bytes -= nb
+                return True
+        return False
+
+
+class Scheduler:
+    """Admission and dispatch; `executor.run(batch, have)` does the work of one dispatch.
+
+    executor interface:
+      run(reqs: List[Request], factors: Optional[object]) -> (List[Result], new_factors or None)
+      ltlt_ws(n, prec), solve_ws(n, nrhs), refine_ws(n, nrhs) -> bytes
+      num_cus -> int
+    """
+
+    def __init__(self, executor, budget_bytes: int = 64 << 30, workers: int = 8, clock=time.perf_counter,
+                 batch_small: bool = True, max_batch: int = 64):
+        self.ex = executor
+        self.budget = budget_bytes
+        self.workers = workers
+        self.clock = clock
+        self.batch_small = batch_small
+        self.max_batch = max_batch
+        self.cache = FactorCache()
+        self.lock = threading.Condition()
+        self.reserved = 0          # bytes held by running requests
+        self.tokens_used = 0
+        self.high_water = 0
+        self.busy = 0
+        self.queue: List[Request] = []
+        self.results: Dict[int, Result] = {}
+        self.evictions = 0
+        self.rejected = 0
+        self._stop = False
+
+    # -- accounting -----------------------------------------------------------
+    def _need(self, req: Request):
+        have = self.cache.get((req.matrix_id, req.prec)) is not None
+        return request_bytes(req, self.ex, have), tokens(req, have), have
+
+    def _fits(self, nbytes: int, protect=None) -> bool:
+        while self.reserved + self.cache.bytes + nbytes > self.budget:
+            if not self.cache.evict_lru(protect):
+                return False
+            self.evictions += 1
+        return True
+
+    def _pick(self):
+        """Next dispatch (list of requests) that fits, FIFO with overtaking."""
+        for qi, req in enumerate(self.queue):
+            nb, tk, have = self._need(req)
+            if nb > self.budget:
+                self.queue.pop(qi)
+                self.rejected += 1
+                res = Result(req.rid, req.arrival, info=-100)
+                res.start = res.end = self.clock()
+                self.results[req.rid] = res
+                return None
+            if self.tokens_used + tk > self.ex.num_cus:
+                continue
+            if not self._fits(nb, (req.matrix_id, req.prec) if have else None):
+                continue
+            batch = [req]
+            if self.batch_small and req.kind == "pf" and req.n <= SMALL_N and not have:
+                total = nb
+                for other in self.queue[qi + 1:]:
+                    if len(batch) >= self.max_batch:
+                        break
+                    if other.kind == "pf" and other.n <= SMALL_N:
+                        nb2, _, have2 = self._need(other)
+                        if not have2 and self._fits(total + nb2):
+                            batch.append(other)
+                            total += nb2
+                nb = total
+            for r in batch:
+                self.queue.remove(r)
+            if have:
+                self.cache.pin((req.matrix_id, req.prec))
+            self.reserved += nb
+            self.tokens_used += tk
+            self.high_water = max(self.high_water, self.reserved + self.cache.bytes)
+            return batch, nb, tk, have
+        return None
+
+    # -- worker ---------------------------------------------------------------
+    def _worker(self):
+        while True:
+            with self.lock:
+                pick = None
+                while True:
+                    if self._stop and not self.queue:
+                        return
+                    pick = self._pick()
+                    if pick:
+                        break
+                    self.lock.wait(0.005)
+                batch, nb, tk, have = pick
+                self.busy += 1
+                factors = self.cache.get((batch[0].matrix_id, batch[0].prec)) if have else None
+            start = self.clock()
+            results, new_factors = self.ex.run(batch, factors)
+            end = self.clock()
+            with self.lock:
+                for req, res in zip(batch, results):
+                    res.arrival = req.arrival
+                    res.start, res.end = start, end
+                    self.results[req.rid] = res
+                self.reserved -= nb
+                self.tokens_used -= tk
+                self.busy -= 1
+                if have:
+                    self.cache.unpin((batch[0].matrix_id, batch[0].prec))
+                if new_factors is not None:
+                    req = batch[0]
+                    self.cache.put((req.matrix_id, req.prec), new_factors, factor_bytes(req.n))
+                    self.high_water = max(self.high_water, self.reserved + self.cache.bytes)
+                self.lock.notify_all()
+
+    def run_trace(self, requests: List[Request], t0: Optional[float] = None) -> Dict[int, Result]:
+        """Replay `requests` (arrival times relative to t0) through `workers` threads."""
+        self._stop = False
+        reqs = sorted(requests, key=lambda r: r.arrival)
+        t0 = self.clock() if t0 is None else t0
+        for r in reqs:
+            r.arrival = t0 + r.arrival
+        threads = [threading.Thread(target=self._worker, daemon=True) for _ in range(self.workers)]
+        for t in threads:
+            t.start()
+        i = 0
+        while i < len(reqs):
+            now = self.clock()
+            with self.lock:
+                while i < len(reqs) and reqs[i].arrival <= now:
+                    self.queue.append(reqs[i])
+                    i += 1
+                self.lock.notify_all()
+            if i < len(reqs):
+                dt = reqs[i].arrival - self.clock()
+                if dt > 0:
+                    time.sleep(min(dt, 0.001))
+        with self.lock:
+            self._stop = True
+            self.lock.notify_all()
+        for t in threads:
+            t.join()
+        return self.results
+
+    def stats(self, t_begin: float) -> dict:
+        res = [r for r in self.results.values() if r.info != -100]
+        lat = [r.latency for r in res]
+        t_end = max((r.end for r in res), default=t_begin)
+        return {
+            "completed": len(res),
+            "rejected": self.rejected,
+            "p50_ms": percentile(lat, 50) * 1e3,
+            "p99_ms": percentile(lat, 99) * 1e3,
+            "mean_ms": (sum(lat) / len(lat) * 1e3) if lat else float("nan"),
+            "req_per_s": len(res) / max(t_end - t_begin, 1e-9),
+            "hbm_high_water_gb": self.high_water / 2 ** 30,
+            "evictions": self.evictions,
+            "cache_hits": sum(1 for r in res if r.cached),
+            "batched": sum(1 for r in res if r.batched),
+        }
+
+
+# ---------------------------------------------------------------------------
+# GPU executor (HIP library through the binding)
+# ---------------------------------------------------------------------------
+
+class GpuExecutor:
+    """Runs one dispatch on the calling worker thread's own stream."""
+
+    def __init__(self, device="cuda:0"):
+        import torch
+
+        from . import skf
+        self.skf = skf
+        self.torch = torch
+        self.device = torch.device(device)
+        skf.lib()
+        self.num_cus = torch.cuda.get_device_properties(self.device).multi_processor_count
+        self._tls = threading.local()
+
+    def ltlt_ws(self, n: int, prec: int) -> int:
+        return self.skf.ltlt_workspace(n, prec)
+
+    def solve_ws(self, n: int, nrhs: int) -> int:
+        return self.skf.solve_workspace(n, nrhs)
+
+    def refine_ws(self, n: int, nrhs: int) -> int:
+        return self.skf.refine_workspace(n, nrhs)
+
+    def _stream(self):
+        s = getattr(self._tls, "stream", None)
+        if s is None:
+            s = self.torch.cuda.Stream(device=self.device)
+            self._tls.stream = s
+        return s
+
+    def run(self, reqs: List[Request], factors):
+        skf, torch = self.skf, self.torch
+        s = self._stream()
+        with torch.cuda.stream(s):
+            if len(reqs) > 1 or (reqs[0].kind == "pf" and reqs[0].n <= SMALL_N and factors is None):
+                mats = []
+                for r in reqs:
+                    w = skf.colmajor(r.n, r.n, device=self.device)
+                    w.copy_(r.A)
+                    mats.append(w)
+                la, sg, info, _, _ = skf.ltlt_batched(mats, with_factors=False, stream=s)
+                s.synchronize()
+                la, sg, info = la.cpu().tolist(), sg.cpu().tolist(), info.cpu().tolist()
+                out = [Result(r.rid, r.arrival, logabs=la[i], sign=sg[i], info=info[i], batched=len(reqs) > 1)
+                       for i, r in enumerate(reqs)]
+                return out, None
+            r = reqs[0]
+            prec = skf.PREC_F64 if r.prec == "f64" else skf.PREC_F32_TRAILING
+            new = None
+            if factors is None:
+                LT = skf.colmajor(r.n, r.n, device=self.device)
+                LT.copy_(r.A)
+                ipiv = torch.empty(max(r.n, 1), dtype=torch.int32, device=self.device)
+                T = torch.empty(max(r.n - 1, 1), dtype=torch.float64, device=self.device)
+                work = skf.workspace(skf.ltlt_workspace(r.n, prec), self.device)
+                dinfo = torch.zeros(1, dtype=torch.int32, device=self.device)
+                skf.ltlt(LT, ipiv, T, prec, work, dinfo, stream=s)
+                del work
+                factors = new = (LT, ipiv, T, dinfo)
+            LT, ipiv, T, dinfo = factors
+            res = Result(r.rid, r.arrival, cached=new is None)
+            if r.kind == "pf":
+                la, sg = skf.logpf_from_factors(r.n, ipiv[:r.n], T[:max(r.n - 1, 0)], stream=s)
+                s.synchronize()
+                res.logabs, res.sign, res.info = float(la.item()), int(sg.item()), int(dinfo.item())
+            else:
+                if r.prec == "f64":
+                    X = skf.colmajor(r.n, r.nrhs, device=self.device)
+                    X.copy_(r.B)
+                    res.info = skf.solve(LT, ipiv[:r.n], T[:max(r.n - 1, 0)], X, stream=s)
+                    res.X = X
+                else:
+                    X, st, it, be = skf.solve_refine(r.A, LT, ipiv[:r.n], T[:max(r.n - 1, 0)], r.B, stream=s)
+                    res.X, res.info, res.iters, res.berr = X, st, it, be
+                s.synchronize()
+            return [res], new
+
+
+def make_workload(count: int, rate_hz: float, seed: int = 8, nmin: int = 64, nmax: int = 4096,
+                  f32_frac: float = 0.3, solve_frac: float = 0.5, reuse_frac: float = 0.25):
+    """The serving trace: Poisson arrivals at `rate_hz`; n = 2 round(exp(U(ln nmin, ln nmax))/2);
+    70/30 FP64/FP32+refine; Pfaffian:solve 50:50; 25% of requests reuse an earlier matrix."""
+    from . import inputs
+    reqs = []
+    t = 0.0
+    ctr = 0
+    mids = []
+    for i in range(count):
+        u = [inputs.uniform(seed, inputs.STREAM_SERVE, ctr + c) for c in range(6)]
+        ctr += 6
+        t += -math.log(max(u[0], 1e-300)) / rate_hz if rate_hz > 0 else 0.0
+        if mids and u[1] < reuse_frac:
+            mid, n = mids[int(u[2] * len(mids)) % len(mids)]
+        else:
+            n = int(2 * round(math.exp(math.log(nmin) + u[2] * (math.log(nmax) - math.log(nmin))) / 2))
+            n = max(nmin, min(nmax, n))
+            mid = len(mids)
+            mids.append((mid, n))
+        kind = "solve" if u[3] < solve_frac else "pf"
+        prec = "f32" if u[4] < f32_frac else "f64"
+        reqs.append(Request(rid=i, kind=kind, n=n, prec=prec, matrix_id=mid, arrival=t))
+    return reqs, mids
+
+
+def materialize(reqs: List[Request], mids, seed: int = 8, device="cuda:0", threads: int = 8):
+    """Client-side inputs on the device: matrix `mid` is the skew Gaussian matrix of
+    its order from stream STREAM_BATCH0 + mid; a solve's right-hand sides come from
+    stream STREAM_BATCH0 + 1_000_000 + rid (Gaussian, nrhs columns)."""
+    from . import inputs, skf
+    mats = {}
+    for mid, n in mids:
+        a = inputs.skew_gaussian(n, seed, inputs.STREAM_BATCH0 + mid, threads=threads)
+        mats[mid] = skf.to_device_colmajor(a, device)
+    for r in reqs:
+        r.A = mats[r.matrix_id]
+        if r.kind == "solve":
+            r.B = skf.to_device_colmajor(inputs.gaussian(r.n, r.nrhs, seed, inputs.STREAM_BATCH0 + 1_000_000 + r.rid),
+                                         device)
+    return mats

@@ -1,0 +1,128 @@
+"""Serving scheduler logic on the CPU: a fake executor that sleeps a modelled time
+and records what ran concurrently."""
+from __future__ import annotations
+
+import threading
+import time
+
+import pytest
+
+from paper_2408_05238_amd import serve
+
+
+class FakeExecutor:
+    def __init__(self, num_cus=256, scale=2e-10, ws=lambda n: 8 * n * n):
+        self.num_cus = num_cus
+        self.scale = scale
+        self._ws = ws
+        self.lock = threading.Lock()
+        self.tok = 0
+        self.max_tok = 0
+        self.calls = []
+        self.running = 0
+        self.max_running = 0
+
+    def ltlt_ws(self, n, prec):
+        return self._ws(n)
+
+    def solve_ws(self, n, nrhs):
+        return 8 * n * nrhs
+
+    def refine_ws(self, n, nrhs):
+        return 8 * n * nrhs * 4
+
+    def run(self, reqs, factors):
+        tk = sum(serve.tokens(r, factors is not None) for r in reqs)
+        with self.lock:
+            self.tok += tk
+            self.max_tok = max(self.max_tok, self.tok)
+            self.running += 1
+            self.max_running = max(self.max_running, self.running)
+            self.calls.append(([r.rid for r in reqs], factors is not None))
+        work = sum(0 if factors is not None else r.n ** 3 / 3 for r in reqs)
+        time.sleep(min(0.02, 1e-4 + work * self.scale))
+        out = []
+        for r in reqs:
+            # deterministic per-matrix "result"
+            out.append(serve.Result(r.rid, r.arrival, logabs=float(r.matrix_id * 1000 + r.n), sign=1,
+                                    cached=factors is not None, batched=len(reqs) > 1))
+        with self.lock:
+            self.tok -= tk
+            self.running -= 1
+        new = None if (factors is not None or len(reqs) > 1 or (reqs[0].kind == "pf" and reqs[0].n <= 512)) \
+            else ("factors", reqs[0].matrix_id)
+        return out, new
+
+
+def test_percentile_nearest_rank():
+    v = list(range(1, 101))
+    assert serve.percentile(v, 50) == 50 and serve.percentile(v, 99) == 99 and serve.percentile(v, 100) == 100
+    assert serve.percentile([3.0], 99) == 3.0
+
+
+def test_workload_recipe():
+    reqs, mids = serve.make_workload(2000, rate_hz=100.0, seed=8)
+    again, _ = serve.make_workload(2000, rate_hz=100.0, seed=8)
+    assert [(r.n, r.kind, r.prec, r.matrix_id, r.arrival) for r in reqs] == \
+        [(r.n, r.kind, r.prec, r.matrix_id, r.arrival) for r in again]
+    ns = [r.n for r in reqs]
+    assert all(n % 2 == 0 and 64 <= n <= 4096 for n in ns)
+    f32 = sum(r.prec == "f32" for r in reqs) / len(reqs)
+    solves = sum(r.kind == "solve" for r in reqs) / len(reqs)
+    assert 0.26 < f32 < 0.34 and 0.45 < solves < 0.55
+    # log-uniform: about half the draws below the geometric mean sqrt(64*4096) = 512
+    fresh = [n for _, n in mids]
+    assert 0.45 < sum(n < 512 for n in fresh) / len(fresh) < 0.55
+    # Poisson: mean gap 1/rate
+    gaps = [b.arrival - a.arrival for a, b in zip(reqs, reqs[1:])]
+    assert abs(sum(gaps) / len(gaps) - 0.01) < 0.001
+    assert len(mids) < len(reqs)           # some requests reuse a matrix
+
+
+def test_scheduler_completes_and_respects_limits():
+    reqs, _ = serve.make_workload(300, rate_hz=3000.0, seed=8, nmax=2048)
+    ex = FakeExecutor(num_cus=64)
+    budget = 1 << 30
+    sch = serve.Scheduler(ex, budget_bytes=budget, workers=6)
+    t0 = time.perf_counter()
+    res = sch.run_trace(reqs, t0=t0)
+    st = sch.stats(t0)
+    assert st["completed"] == 300 and st["rejected"] == 0
+    assert sch.high_water <= budget
+    assert ex.max_tok <= 64
+    assert ex.max_running > 1                       # work overlapped
+    assert sch.reserved == 0 and sch.tokens_used == 0 and not sch.cache.pins
+    for r in reqs:
+        assert res[r.rid].logabs == r.matrix_id * 1000 + r.n and res[r.rid].end >= r.arrival
+    assert st["batched"] > 0 and st["cache_hits"] > 0
+    assert st["p99_ms"] >= st["p50_ms"] > 0
+
+
+def test_scheduler_rejects_oversized_and_evicts():
+    ex = FakeExecutor()
+    budget = 3 * serve.factor_bytes(1000) + 3 * 8 * 1000 * 1000
+    sch = serve.Scheduler(ex, budget_bytes=budget, workers=2)
+    reqs = [serve.Request(rid=i, kind="solve", n=1000, prec="f64", matrix_id=i, arrival=0.0) for i in range(5)]
+    reqs.append(serve.Request(rid=5, kind="pf", n=4000, prec="f64", matrix_id=99, arrival=0.0))
+    res = sch.run_trace(reqs)
+    assert res[5].info == -100 and sch.rejected == 1
+    assert all(res[i].info == 0 for i in range(5))
+    assert sch.evictions >= 1 and sch.high_water <= budget and sch.cache.bytes <= budget
+
+
+def test_tokens_limit_serialises_large_factorizations():
+    ex = FakeExecutor(num_cus=40)
+    sch = serve.Scheduler(ex, budget_bytes=1 << 40, workers=4)
+    reqs = [serve.Request(rid=i, kind="pf", n=2048, prec="f64", matrix_id=i, arrival=0.0) for i in range(4)]
+    sch.run_trace(reqs)
+    assert ex.max_tok <= 40 and ex.max_running == 1      # 32 tokens each: never two at once
+
+
+def test_cached_factors_skip_factorization():
+    ex = FakeExecutor()
+    sch = serve.Scheduler(ex, budget_bytes=1 << 40, workers=1)
+    reqs = [serve.Request(rid=0, kind="solve", n=1000, prec="f64", matrix_id=7, arrival=0.0),
+            serve.Request(rid=1, kind="pf", n=1000, prec="f64", matrix_id=7, arrival=0.05),
+            serve.Request(rid=2, kind="pf", n=1000, prec="f32", matrix_id=7, arrival=0.1)]
+    res = sch.run_trace(reqs)
+    assert not res[0].cached and res[1].cached and not res[2].cached    # other precision: new factors
