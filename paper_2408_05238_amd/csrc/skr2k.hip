@@ -8,10 +8,12 @@
 //
 // Tiling: a 256-thread workgroup owns a 128 x 128 tile of C; each of its four
 // waves owns a 64 x 64 quarter (4 x 4 MFMA blocks of 16 x 16; a quarter lying
-// wholly above the diagonal is skipped).  K is short (nb = 128), so operand
-// fragments are loaded straight from global memory into registers, two
-// k-steps ahead, with no LDS and no barriers; the 128 x nb operand panels of a
-// tile row stay in L2 because consecutive tiles of one XCD walk a band of rows.
+// wholly above the diagonal skips its products but still helps to load).  The
+// inner dimension is walked in chunks of 16: the workgroup stages the chunk's
+// 128 x 16 slices of X (its rows) and Y (its columns) in LDS, double-buffered,
+// with the global loads of chunk c+1 in flight while the matrix cores work on
+// chunk c (one barrier per chunk).  Registers are kept to 256 per lane so that
+// two workgroups share a CU and cover each other's load and barrier waits.
 // In the trailing-update form the accumulators start from the permuted source
 // tile, so the epilogue is a plain store.
 //
@@ -24,9 +26,12 @@
 namespace skf {
 namespace {
 
-constexpr int TM = 128;    // workgroup tile
-constexpr int WT = 64;     // wave tile
+constexpr int TM = 128;     // workgroup tile
+constexpr int WT = 64;      // wave tile
 constexpr int NTHR = 256;
+constexpr int KC = 16;      // inner terms per LDS chunk
+constexpr int LSTR = TM + 16;  // doubles per staged column: consecutive k-groups land 128 B apart in the banks
+constexpr int PER_THR = KC * TM / NTHR;  // staged doubles per thread and operand (8)
 
 template <typename T>
 struct Mfma;
@@ -75,116 +80,101 @@ struct Operands {
   int64_t n;         // rows (loads clamp to n-1; rows >= n are never stored)
 };
 
-// One k-step (4 values of the inner index) of raw FP64 operand fragments.
-// Loaded values are not touched until the k-step is consumed, so the loads of
-// the next steps stay in flight under the current MFMAs.
-struct Frag {
-  double a[4], b[4];
+struct Stage {
+  double X[KC][LSTR];  // X rows of the tile's row block, k-major
+  double Y[KC][LSTR];  // Y rows of the tile's column block
 };
 
-// Fragments for inner indices c = kk + lane/16 of Xb (rows ra) and Yb (rows rb);
-// masked: zero past k (only for the last, partial k-step).  Offsets are 32-bit
-// byte offsets from wave-uniform bases (the launcher checks they fit).
-template <bool kMasked>
-__device__ inline void load_frag(const double* __restrict__ Xb, int64_t ldx, const double* __restrict__ Yb,
-                                 int64_t ldy, const uint32_t ra[4], const uint32_t rb[4], int64_t k,
-                                 int64_t kk, int lane, Frag& f) {
-  const int64_t c = kk + (lane >> 4);
-  const bool in = !kMasked || c < k;
-  const uint32_t cx = in ? (uint32_t)(c * ldx) : 0u;
-  const uint32_t cy = in ? (uint32_t)(c * ldy) : 0u;
-  const char* xb = reinterpret_cast<const char*>(Xb);
-  const char* yb = reinterpret_cast<const char*>(Yb);
+// Global loads of one chunk into registers: thread t takes, for u < 8, entry
+// e = t + 256 u, i.e. column e / 128 of the chunk and row e % 128 (a wave
+// instruction reads 64 consecutive doubles of one column).  Chunk c < nh covers
+// inner terms 16c.. of P Q^T, chunk c >= nh those of (-Q) P^T.
+struct ChunkRegs {
+  double x[PER_THR], y[PER_THR];
+};
+
+__device__ inline void chunk_load(const Operands& o, int64_t c, int64_t nh, int64_t rI, int64_t rJ,
+                                  ChunkRegs& R) {
+  const bool h2 = c >= nh;
+  const int64_t kk = (h2 ? c - nh : c) * KC;
+  const double* Xb = h2 ? o.Q : o.P;
+  const double* Yb = h2 ? o.P : o.Q;
+  const int64_t ldx = h2 ? o.ldq : o.ldp, ldy = h2 ? o.ldp : o.ldq;
+  const int t = threadIdx.x;
+  const int row = t & (TM - 1);
+  const int64_t ia = rI + row < o.n ? rI + row : o.n - 1;
+  const int64_t ib = rJ + row < o.n ? rJ + row : o.n - 1;
+  const char* xb = reinterpret_cast<const char*>(Xb + kk * ldx);
+  const char* yb = reinterpret_cast<const char*>(Yb + kk * ldy);
 #pragma unroll
-  for (int t = 0; t < 4; ++t) {
-    f.a[t] = *reinterpret_cast<const double*>(xb + ((ra[t] + cx) << 3));
-    f.b[t] = *reinterpret_cast<const double*>(yb + ((rb[t] + cy) << 3));
-    if (kMasked && !in) {
-      f.a[t] = 0.0;
-      f.b[t] = 0.0;
-    }
+  for (int u = 0; u < PER_THR; ++u) {
+    const int col = (t >> 7) + 2 * u;
+    const int64_t cc = kk + col < o.k ? col : 0;  // past k: reload column 0, zeroed at the store
+    R.x[u] = *reinterpret_cast<const double*>(xb + ((uint32_t)(ia + cc * ldx) << 3));
+    R.y[u] = *reinterpret_cast<const double*>(yb + ((uint32_t)(ib + cc * ldy) << 3));
   }
 }
 
-// acc += (+-A) B^T for one k-step; the sign and the FP32 rounding are applied here.
+__device__ inline void chunk_store(const Operands& o, int64_t c, int64_t nh, const ChunkRegs& R, Stage& s) {
+  const bool h2 = c >= nh;
+  const int64_t kk = (h2 ? c - nh : c) * KC;
+  const int t = threadIdx.x;
+  const int row = t & (TM - 1);
+#pragma unroll
+  for (int u = 0; u < PER_THR; ++u) {
+    const int col = (t >> 7) + 2 * u;
+    const bool in = kk + col < o.k;
+    s.X[col][row] = in ? R.x[u] : 0.0;
+    s.Y[col][row] = in ? R.y[u] : 0.0;
+  }
+}
+
+// acc += (+-X) Y^T over one staged chunk (four k-steps of 4).
 template <typename T>
-__device__ inline void mma_step(const Frag& f, bool negA, typename Mfma<T>::acc_t acc[4][4]) {
-  T a[4], b[4];
+__device__ inline void chunk_mma(const Stage& s, int wr, int wc, bool neg, typename Mfma<T>::acc_t acc[4][4]) {
+  const int lane = threadIdx.x & 63;
+  const int kq = lane >> 4, rr = lane & 15;
 #pragma unroll
-  for (int t = 0; t < 4; ++t) {
-    a[t] = (T)(negA ? -f.a[t] : f.a[t]);
-    b[t] = (T)f.b[t];
+  for (int ks = 0; ks < KC / 4; ++ks) {
+    T a[4], b[4];
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+      const double va = s.X[4 * ks + kq][wr + 16 * t + rr];
+      a[t] = (T)(neg ? -va : va);
+      b[t] = (T)s.Y[4 * ks + kq][wc + 16 * t + rr];
+    }
+#pragma unroll
+    for (int mi = 0; mi < 4; ++mi)
+#pragma unroll
+      for (int ni = 0; ni < 4; ++ni) acc[mi][ni] = Mfma<T>::op(a[mi], b[ni], acc[mi][ni]);
   }
-#pragma unroll
-  for (int mi = 0; mi < 4; ++mi)
-#pragma unroll
-    for (int ni = 0; ni < 4; ++ni) acc[mi][ni] = Mfma<T>::op(a[mi], b[ni], acc[mi][ni]);
 }
 
-// acc[mi][ni] += (P Q^T - Q P^T)[rA + 16 mi + ., rB + 16 ni + .], as the
-// k-steps of P Q^T followed by those of (-Q) P^T in one software pipeline with
-// four k-steps of operand loads in flight (about 4000 MFMA cycles of cover).
-// mid() is called once, early in the second half, to issue the loads of the C
-// tile; they are consumed only in the epilogue.
-template <typename T, typename Mid>
-__device__ inline void wave_mainloop(const Operands& o, int64_t rA, int64_t rB,
-                                     typename Mfma<T>::acc_t acc[4][4], Mid&& mid) {
-  const int lane = threadIdx.x & 63;
-  uint32_t ra[4], rb[4];
-#pragma unroll
-  for (int t = 0; t < 4; ++t) {
-    const int64_t a = rA + t * 16 + (lane & 15), b = rB + t * 16 + (lane & 15);
-    ra[t] = (uint32_t)(a < o.n ? a : o.n - 1);
-    rb[t] = (uint32_t)(b < o.n ? b : o.n - 1);
+// The workgroup's main loop: acc[mi][ni] of the calling wave accumulates
+// (P Q^T - Q P^T)[rI + wr + 16 mi + ., rJ + wc + 16 ni + .].  Every wave of the
+// workgroup must call it (it contains barriers); `active` waves do the products.
+// pro() runs once while the first chunk's loads are in flight (the trailing
+// update issues its source-tile gathers there, so both latencies overlap).
+template <typename T, typename Pro>
+__device__ inline void tile_mainloop(const Operands& o, int64_t rI, int64_t rJ, int wr, int wc, bool active,
+                                     Stage* st, typename Mfma<T>::acc_t acc[4][4], Pro&& pro) {
+  const int64_t nh = (o.k + KC - 1) / KC;
+  const int64_t nch = 2 * nh;
+  if (nch == 0) {
+    pro();
+    return;
   }
-  const int64_t nsf = o.k >> 2;  // full k-steps per half
-  const int64_t total = 2 * nsf;
-  // Branch-free issue: a step past the end reloads the last step (discarded), so
-  // every path has the same loads in flight and no wait lands inside the loop.
-  auto issue = [&](int64_t st, Frag& f) {
-    st = st < total ? st : total - 1;
-    const bool h2 = st >= nsf;
-    const double* Xb = h2 ? o.Q : o.P;
-    const double* Yb = h2 ? o.P : o.Q;
-    const int64_t ldx = h2 ? o.ldq : o.ldp, ldy = h2 ? o.ldp : o.ldq;
-    load_frag<false>(Xb, ldx, Yb, ldy, ra, rb, o.k, (h2 ? st - nsf : st) * 4, lane, f);
-  };
-  if (total > 0 && (nsf & 3) == 0) {
-    // four rotating fragments; the pipeline runs across the two halves
-    Frag f0, f1, f2, f3;
-    issue(0, f0);
-    issue(1, f1);
-    issue(2, f2);
-    issue(3, f3);
-    auto quad = [&](int64_t st, bool neg) {
-      mma_step<T>(f0, neg, acc);
-      issue(st + 4, f0);
-      mma_step<T>(f1, neg, acc);
-      issue(st + 5, f1);
-      mma_step<T>(f2, neg, acc);
-      issue(st + 6, f2);
-      mma_step<T>(f3, neg, acc);
-      issue(st + 7, f3);
-    };
-    for (int64_t st = 0; st < nsf; st += 4) quad(st, false);
-    mid();  // the first four k-steps of the second half are already in flight
-    for (int64_t st = nsf; st < total; st += 4) quad(st, true);
-  } else if (total > 0) {
-    Frag f0;
-    for (int64_t st = 0; st < total; ++st) {
-      if (st == nsf) mid();
-      issue(st, f0);
-      mma_step<T>(f0, st >= nsf, acc);
-    }
-  } else {
-    mid();
-  }
-  if ((o.k & 3) != 0) {  // partial last k-step of each half
-    Frag f;
-    load_frag<true>(o.P, o.ldp, o.Q, o.ldq, ra, rb, o.k, nsf * 4, lane, f);
-    mma_step<T>(f, false, acc);
-    load_frag<true>(o.Q, o.ldq, o.P, o.ldp, ra, rb, o.k, nsf * 4, lane, f);
-    mma_step<T>(f, true, acc);
+  ChunkRegs R;
+  chunk_load(o, 0, nh, rI, rJ, R);
+  pro();
+  chunk_store(o, 0, nh, R, st[0]);
+  __syncthreads();
+  for (int64_t c = 0; c < nch; ++c) {
+    const bool more = c + 1 < nch;
+    if (more) chunk_load(o, c + 1, nh, rI, rJ, R);
+    if (active) chunk_mma<T>(st[c & 1], wr, wc, c >= nh, acc);
+    if (more) chunk_store(o, c + 1, nh, R, st[(c + 1) & 1]);
+    __syncthreads();
   }
 }
 
@@ -192,43 +182,40 @@ __device__ inline void wave_mainloop(const Operands& o, int64_t rA, int64_t rB,
 // Plain in-place update: C := beta C + alpha (P Q^T - Q P^T), strict lower.
 // ---------------------------------------------------------------------------
 template <typename T>
-__global__ void __launch_bounds__(NTHR) skr2k_kernel(Operands o, double alpha, double beta, double* C,
-                                                     int64_t ldc, int64_t ntiles) {
+__global__ void __launch_bounds__(NTHR, 2) skr2k_kernel(Operands o, double alpha, double beta, double* C,
+                                                        int64_t ldc, int64_t ntiles) {
+  __shared__ Stage st[2];
   const int64_t n = o.n;
   int64_t bi, bj;
   tri_tile(xcd_remap(blockIdx.x, ntiles), &bi, &bj);
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int wm = wave >> 1, wn = wave & 1;
-  if (bi == bj && wm < wn) return;  // quarter wholly above the diagonal
-  const int64_t i0 = bi * TM + wm * WT, j0 = bj * TM + wn * WT;
-  if (i0 >= n) return;
+  const int64_t rI = bi * TM, rJ = bj * TM;
+  const int64_t i0 = rI + wm * WT, j0 = rJ + wn * WT;
+  // a quarter wholly above the diagonal, or below the last row, has no products
+  const bool active = !(bi == bj && wm < wn) && i0 < n;
   typename Mfma<T>::acc_t acc[4][4];
 #pragma unroll
   for (int a = 0; a < 4; ++a)
 #pragma unroll
     for (int b = 0; b < 4; ++b) acc[a][b] = typename Mfma<T>::acc_t{0, 0, 0, 0};
-  // FP32 accumulators leave room to prefetch the C tile mid-loop; FP64 reads it at the end.
-  constexpr bool kPre = sizeof(T) == 4;
-  double cv[4][4][4];
-  auto load_c = [&]() {
-    if constexpr (kPre) {
+  if (alpha != 0.0) tile_mainloop<T>(o, rI, rJ, wm * WT, wn * WT, active, st, acc, [] {});
+  if (!active) return;
+  // Epilogue by 16-row slices: the slice's 16 loads of C are issued together
+  // (clamped addresses, no branch around a load), then combined and stored.
 #pragma unroll
-      for (int mi = 0; mi < 4; ++mi)
+  for (int mi = 0; mi < 4; ++mi) {
+    double cv[4][4];
 #pragma unroll
-        for (int ni = 0; ni < 4; ++ni) {
-          const int64_t j = j0 + ni * 16 + (lane & 15);
+    for (int ni = 0; ni < 4; ++ni) {
+      const int64_t j = j0 + ni * 16 + (lane & 15);
 #pragma unroll
-          for (int r = 0; r < 4; ++r) {
-            const int64_t i = i0 + mi * 16 + Mfma<T>::row(lane, r);
-            cv[mi][ni][r] = (beta != 0.0 && i < n && i > j) ? C[i + j * ldc] : 0.0;
-          }
-        }
+      for (int r = 0; r < 4; ++r) {
+        const int64_t i = i0 + mi * 16 + Mfma<T>::row(lane, r);
+        const bool st_ok = i < n && i > j;
+        cv[ni][r] = (beta != 0.0) ? C[st_ok ? i + j * ldc : 0] : 0.0;
+      }
     }
-  };
-  if (alpha != 0.0) wave_mainloop<T>(o, i0, j0, acc, load_c);
-  else load_c();
-#pragma unroll
-  for (int mi = 0; mi < 4; ++mi)
 #pragma unroll
     for (int ni = 0; ni < 4; ++ni) {
       const int64_t j = j0 + ni * 16 + (lane & 15);
@@ -237,11 +224,11 @@ __global__ void __launch_bounds__(NTHR) skr2k_kernel(Operands o, double alpha, d
         const int64_t i = i0 + mi * 16 + Mfma<T>::row(lane, r);
         if (i < n && i > j) {
           const double u = alpha * (double)acc[mi][ni][r];
-          if (beta == 0.0) C[i + j * ldc] = u;
-          else C[i + j * ldc] = beta * (kPre ? cv[mi][ni][r] : C[i + j * ldc]) + u;
+          C[i + j * ldc] = (beta == 0.0) ? u : beta * cv[ni][r] + u;
         }
       }
     }
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -249,87 +236,143 @@ __global__ void __launch_bounds__(NTHR) skr2k_kernel(Operands o, double alpha, d
 //   dst[i,j] = (j == lo) ? cnext[i] : S(pi[i], pi[j]) + (P Q^T - Q P^T)[i,j]
 // ---------------------------------------------------------------------------
 template <typename T>
-__global__ void __launch_bounds__(NTHR) skr2k_perm_kernel(Operands o, int64_t lo,
-                                                          const double* __restrict__ src, int64_t lds,
-                                                          double* __restrict__ dst, int64_t ldd,
-                                                          const int32_t* __restrict__ pi,
-                                                          const double* __restrict__ cnext,
-                                                          int64_t ntiles) {
+__global__ void __launch_bounds__(NTHR, 2) skr2k_perm_kernel(Operands o, int64_t lo,
+                                                             const double* __restrict__ src, int64_t lds,
+                                                             double* __restrict__ dst, int64_t ldd,
+                                                             const int32_t* __restrict__ pi,
+                                                             const double* __restrict__ cnext,
+                                                             int64_t ntiles) {
+  __shared__ Stage st[2];
   const int64_t n = o.n;
   int64_t bi, bj;
   tri_tile(xcd_remap(blockIdx.x, ntiles), &bi, &bj);
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int wm = wave >> 1, wn = wave & 1;
-  if (bi == bj && wm < wn) return;
-  const int64_t i0 = lo + bi * TM + wm * WT, j0 = lo + bj * TM + wn * WT;
-  if (i0 >= n) return;
-  // permutation of the tile's rows and columns, loaded once
-  int32_t pa[4][4], pb[4];
+  const int64_t rI = lo + bi * TM, rJ = lo + bj * TM;
+  const int64_t i0 = rI + wm * WT, j0 = rJ + wn * WT;
+  const bool active = !(bi == bj && wm < wn) && i0 < n;
+  // Source tile S(pi[i], pi[j]) (column lo: the panel's next column).  Every
+  // address is formed first and all 64 loads per lane are issued at once into
+  // v; the masks (inside the strict lower triangle) and the signs (upper-storage
+  // reads) are applied after a single wait.
+  uint64_t ok = 0, neg = 0;
+  auto gather = [&](int m_lo, int m_hi, auto&& put) {
+    int32_t pb[4];
 #pragma unroll
-  for (int ni = 0; ni < 4; ++ni) {
-    const int64_t j = j0 + ni * 16 + (lane & 15);
-    pb[ni] = (j < n) ? pi[j] : 0;
-  }
-#pragma unroll
-  for (int mi = 0; mi < 4; ++mi)
-#pragma unroll
-    for (int r = 0; r < 4; ++r) {
-      const int64_t i = i0 + mi * 16 + Mfma<T>::row(lane, r);
-      pa[mi][r] = (i < n) ? pi[i] : 0;
+    for (int ni = 0; ni < 4; ++ni) {
+      const int64_t j = j0 + ni * 16 + (lane & 15);
+      pb[ni] = pi[j < n ? j : n - 1];
     }
-  // S(pi[i], pi[j]) of the tile; column lo takes the panel's next column instead
-  auto src_val = [&](int mi, int ni, int r) -> double {
-    const int64_t j = j0 + ni * 16 + (lane & 15);
-    const int64_t i = i0 + mi * 16 + Mfma<T>::row(lane, r);
-    if (!(i < n && i > j)) return 0.0;
-    if (j == lo) return cnext[i];
-    const int64_t a = pa[mi][r], b = pb[ni];
-    return (a > b) ? src[a + b * lds] : -src[b + a * lds];
+#pragma unroll
+    for (int mi = m_lo; mi < m_hi; ++mi) {
+      int32_t pa[4];
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int64_t i = i0 + mi * 16 + Mfma<T>::row(lane, r);
+        pa[r] = pi[i < n ? i : n - 1];
+      }
+#pragma unroll
+      for (int ni = 0; ni < 4; ++ni) {
+        const int64_t j = j0 + ni * 16 + (lane & 15);
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int64_t i = i0 + mi * 16 + Mfma<T>::row(lane, r);
+          const bool valid = i < n && i > j;
+          const int64_t a = pa[r], b = pb[ni];
+          const bool lower = a > b;
+          const double* p = (j == lo) ? cnext + (i < n ? i : n - 1) : src + (lower ? a + b * lds : b + a * lds);
+          put(mi, ni, r, *p);
+          const int e = (mi * 4 + ni) * 4 + r;
+          ok |= (uint64_t)valid << e;
+          neg |= (uint64_t)(j != lo && !lower) << e;
+        }
+      }
+    }
+  };
+  auto fix = [&](double& x, int e) {
+    const double y = ((neg >> e) & 1u) ? -x : x;
+    x = ((ok >> e) & 1u) ? y : 0.0;
   };
   typename Mfma<T>::acc_t acc[4][4];
   if constexpr (sizeof(T) == 8) {
-    // FP64 accumulates straight onto the source tile
+    // FP64 accumulates straight onto the source tile, gathered while the
+    // first operand chunk is loading
+    tile_mainloop<T>(o, rI, rJ, wm * WT, wn * WT, active, st, acc, [&] {
+      // by 16-row slices: 16 loads per lane in flight per slice
+#pragma unroll
+      for (int mi = 0; mi < 4; ++mi) {
+        double v[4][4];
+        if (active) gather(mi, mi + 1, [&](int, int ni, int r, double x) { v[ni][r] = x; });
+#pragma unroll
+        for (int ni = 0; ni < 4; ++ni)
+#pragma unroll
+          for (int r = 0; r < 4; ++r) {
+            double x = active ? v[ni][r] : 0.0;
+            fix(x, (mi * 4 + ni) * 4 + r);
+            acc[mi][ni][r] = x;
+          }
+      }
+    });
+    if (!active) return;
 #pragma unroll
     for (int mi = 0; mi < 4; ++mi)
 #pragma unroll
-      for (int ni = 0; ni < 4; ++ni)
+      for (int ni = 0; ni < 4; ++ni) {
+        const int64_t j = j0 + ni * 16 + (lane & 15);
 #pragma unroll
-        for (int r = 0; r < 4; ++r) acc[mi][ni][r] = src_val(mi, ni, r);
-    wave_mainloop<T>(o, i0, j0, acc, [] {});
+        for (int r = 0; r < 4; ++r) {
+          const int64_t i = i0 + mi * 16 + Mfma<T>::row(lane, r);
+          if (i < n && i > j) {
+            double x = acc[mi][ni][r];
+            if (j == lo) x = cnext[i];  // column lo is the panel's next column as it stands
+            dst[i + j * ldd] = x;
+          }
+        }
+      }
   } else {
     // FP32 products are added to the FP64 source tile in the epilogue
 #pragma unroll
     for (int a = 0; a < 4; ++a)
 #pragma unroll
       for (int b = 0; b < 4; ++b) acc[a][b] = typename Mfma<T>::acc_t{0, 0, 0, 0};
-    wave_mainloop<T>(o, i0, j0, acc, [] {});
-  }
+    tile_mainloop<T>(o, rI, rJ, wm * WT, wn * WT, active, st, acc, [] {});
+    if (!active) return;
+    // two halves of 32 rows: 32 source loads per lane in flight at a time
 #pragma unroll
-  for (int mi = 0; mi < 4; ++mi)
+    for (int h = 0; h < 2; ++h) {
+      double v[2][4][4];
+      gather(2 * h, 2 * h + 2, [&](int mi, int ni, int r, double x) { v[mi - 2 * h][ni][r] = x; });
 #pragma unroll
-    for (int ni = 0; ni < 4; ++ni) {
-      const int64_t j = j0 + ni * 16 + (lane & 15);
+      for (int mm = 0; mm < 2; ++mm)
 #pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const int64_t i = i0 + mi * 16 + Mfma<T>::row(lane, r);
-        if (i < n && i > j) {
-          double v;
-          if (j == lo) v = cnext[i];
-          else if constexpr (sizeof(T) == 8) v = (double)acc[mi][ni][r];
-          else v = src_val(mi, ni, r) + (double)acc[mi][ni][r];
-          dst[i + j * ldd] = v;
+        for (int ni = 0; ni < 4; ++ni) {
+          const int mi = 2 * h + mm;
+          const int64_t j = j0 + ni * 16 + (lane & 15);
+#pragma unroll
+          for (int r = 0; r < 4; ++r) {
+            const int64_t i = i0 + mi * 16 + Mfma<T>::row(lane, r);
+            double x = v[mm][ni][r];
+            fix(x, (mi * 4 + ni) * 4 + r);
+            x += (double)acc[mi][ni][r];
+            if (j == lo) x = cnext[i < n ? i : n - 1];
+            if (i < n && i > j) dst[i + j * ldd] = x;
+          }
         }
-      }
     }
+  }
 }
 
 }  // namespace
+
+// Per-lane operand offsets are 32-bit byte offsets from a chunk's base.
+static bool offsets_fit(int64_t n, int64_t ld) { return (n + (int64_t)KC * ld) * 8 < ((int64_t)1 << 32); }
 
 template <typename T>
 static int launch_plain(int64_t n, int64_t k, double alpha, const double* X, int64_t ldx,
                         const double* Y, int64_t ldy, double beta, double* C, int64_t ldc,
                         hipStream_t s) {
   if (n < 2) return 0;
+  if (alpha != 0.0 && k > 0 && !(offsets_fit(n, ldx) && offsets_fit(n, ldy))) return SKF_ENOTIMPL;
   const int64_t nt = (n + TM - 1) / TM;
   const int64_t ntiles = nt * (nt + 1) / 2;
   Operands o{X, Y, ldx, ldy, (alpha == 0.0) ? 0 : k, n};
@@ -356,6 +399,7 @@ int launch_skr2k_perm(int64_t n, int64_t lo, int64_t npairs, const double* src, 
                       const double* Wp, int64_t ldp, const double* cnext, bool f32, hipStream_t s) {
   const int64_t m = n - lo;
   if (m < 2) return 0;
+  if (!offsets_fit(n, ldp)) return SKF_ENOTIMPL;
   const int64_t nt = (m + TM - 1) / TM;
   const int64_t ntiles = nt * (nt + 1) / 2;
   Operands o{Lp, Wp, ldp, ldp, npairs, n};

@@ -145,6 +145,21 @@ def _ptr(t):
     return ctypes.c_void_p(t.data_ptr()) if t is not None else ctypes.c_void_p(0)
 
 
+def _ptr_array(tensors, dev, stream):
+    """Device array of the tensors' data pointers for an asynchronous call.
+
+    The caller must keep the returned tensor alive until the call is enqueued;
+    when the call runs on a stream other than the current one the block is also
+    recorded on that stream, so the caching allocator cannot hand it out before
+    the call's kernels have read it.
+    """
+    torch = _torch()
+    arr = torch.tensor([t.data_ptr() for t in tensors] or [0], dtype=torch.int64, device=dev)
+    if stream is not None and stream != torch.cuda.current_stream(dev):
+        arr.record_stream(stream)
+    return arr
+
+
 def workspace(nbytes: int, device="cuda"):
     torch = _torch()
     return torch.empty(max(int(nbytes), 256), dtype=torch.uint8, device=device)
@@ -306,7 +321,7 @@ def ltlt_batched(mats, with_factors: bool = True, work=None, stream=None):
     B = len(mats)
     n_h = np.array([m.shape[0] for m in mats], dtype=np.int64)
     lda_h = np.array([_ld(m) if m.shape[0] > 0 else 1 for m in mats], dtype=np.int64)
-    aptr = torch.tensor([m.data_ptr() for m in mats] or [0], dtype=torch.int64, device=dev)
+    aptr = _ptr_array(mats, dev, stream)
     logabs = torch.empty(max(B, 1), dtype=torch.float64, device=dev)
     sign = torch.empty(max(B, 1), dtype=torch.int32, device=dev)
     info = torch.empty(max(B, 1), dtype=torch.int32, device=dev)
@@ -316,8 +331,8 @@ def ltlt_batched(mats, with_factors: bool = True, work=None, stream=None):
     if with_factors:
         ipivs = [torch.empty(max(int(n), 1), dtype=torch.int32, device=dev) for n in n_h]
         Ts = [torch.empty(max(int(n) - 1, 1), dtype=torch.float64, device=dev) for n in n_h]
-        pp = torch.tensor([t.data_ptr() for t in ipivs] or [0], dtype=torch.int64, device=dev)
-        tp = torch.tensor([t.data_ptr() for t in Ts] or [0], dtype=torch.int64, device=dev)
+        pp = _ptr_array(ipivs, dev, stream)
+        tp = _ptr_array(Ts, dev, stream)
         rc = _load().skf_ltlt_batched(B, n_h.ctypes.data_as(ctypes.c_void_p), _ptr(aptr),
                                       lda_h.ctypes.data_as(ctypes.c_void_p), _ptr(pp), _ptr(tp), _ptr(logabs),
                                       _ptr(sign), _ptr(info), _ptr(work), work.numel(), _stream(stream))
@@ -343,6 +358,8 @@ def logpf_batched_packed(buf, offsets, n_list, work=None, stream=None):
     base = buf.data_ptr()
     aptr = torch.tensor((base + 8 * np.asarray(offsets, dtype=np.int64)).tolist() or [0], dtype=torch.int64,
                         device=dev)
+    if stream is not None and stream != torch.cuda.current_stream(dev):
+        aptr.record_stream(stream)
     logabs = torch.empty(max(B, 1), dtype=torch.float64, device=dev)
     sign = torch.empty(max(B, 1), dtype=torch.int32, device=dev)
     info = torch.empty(max(B, 1), dtype=torch.int32, device=dev)
@@ -353,3 +370,32 @@ def logpf_batched_packed(buf, offsets, n_list, work=None, stream=None):
                                    _ptr(work), work.numel(), _stream(stream))
     _check(rc, "skf_logpf_batched")
     return logabs[:B], sign[:B], info[:B], aptr
+
+
+def solve_batched(LTs, ipivs, Ts, Bs, work=None, stream=None):
+    """X_b = A_b^{-1} B_b in place over each B_b, with the factors of
+    :func:`ltlt_batched` (or :func:`ltlt`).  Returns the device info array."""
+    import numpy as np
+    torch = _torch()
+    nb = len(LTs)
+    dev = LTs[0].device if nb else torch.device("cuda")
+    n_h = np.array([m.shape[0] for m in LTs], dtype=np.int64)
+    lda_h = np.array([_ld(m) if m.shape[0] > 0 else 1 for m in LTs], dtype=np.int64)
+    nr_h = np.array([b.shape[1] if b.dim() == 2 else 1 for b in Bs], dtype=np.int64)
+    ldb_h = np.array([_ld(b) if b.dim() == 2 and b.shape[0] > 0 else max(int(n), 1) for b, n in zip(Bs, n_h)],
+                     dtype=np.int64)
+    if work is None:
+        need = max([solve_workspace(int(n), int(r)) for n, r in zip(n_h, nr_h)] or [256])
+        work = workspace(need, dev)
+    lt_arr = _ptr_array(LTs, dev, stream)
+    ip_arr = _ptr_array(ipivs, dev, stream)
+    t_arr = _ptr_array(Ts, dev, stream)
+    b_arr = _ptr_array(Bs, dev, stream)
+    info = torch.empty(max(nb, 1), dtype=torch.int32, device=dev)
+    rc = _load().skf_solve_batched(nb, n_h.ctypes.data_as(ctypes.c_void_p), _ptr(lt_arr),
+                                   lda_h.ctypes.data_as(ctypes.c_void_p), _ptr(ip_arr), _ptr(t_arr),
+                                   nr_h.ctypes.data_as(ctypes.c_void_p), _ptr(b_arr),
+                                   ldb_h.ctypes.data_as(ctypes.c_void_p), _ptr(info), _ptr(work), work.numel(),
+                                   _stream(stream))
+    _check(rc, "skf_solve_batched")
+    return info[:nb]

@@ -71,28 +71,13 @@ def test_batched_logpf_only_and_nonfinite(skf, oracle_mod, gen):
 
 
 def test_solve_batched(skf, oracle_mod, gen):
-    import ctypes
-    import torch
     ns = [64, 100, 2]
     mats_h = [gen.batch_matrix(n, 17, b) for b, n in enumerate(ns)]
     mats = [skf.to_device_colmajor(A) for A in mats_h]
     _, _, _, ipivs, Ts = skf.ltlt_batched(mats)
     Bs_h = [gen.gaussian(n, 3, 100 + b) for b, n in enumerate(ns)]
     Bs = [skf.to_device_colmajor(B) for B in Bs_h]
-    dev = mats[0].device
-    P = lambda ts: torch.tensor([t.data_ptr() for t in ts], dtype=torch.int64, device=dev)
-    n_h = np.array(ns, dtype=np.int64)
-    nr = np.array([3] * 3, dtype=np.int64)
-    info = torch.empty(3, dtype=torch.int32, device=dev)
-    work = skf.workspace(skf.batched_workspace(ns))
-    lib = skf.lib()
-    rc = lib.skf_solve_batched(3, n_h.ctypes.data_as(ctypes.c_void_p), skf._ptr(P(mats)),
-                               n_h.ctypes.data_as(ctypes.c_void_p), skf._ptr(P(ipivs)), skf._ptr(P(Ts)),
-                               nr.ctypes.data_as(ctypes.c_void_p), skf._ptr(P(Bs)),
-                               n_h.ctypes.data_as(ctypes.c_void_p), skf._ptr(info), skf._ptr(work), work.numel(),
-                               skf._stream(None))
-    assert rc == 0
-    torch.cuda.synchronize()
+    info = skf.solve_batched(mats, ipivs, Ts, Bs)
     assert _host(info).tolist() == [0, 0, 0]
     for b in range(3):
         assert oracle_mod.backward_error(mats_h[b], _host(Bs[b]), Bs_h[b]) <= 1e-13
