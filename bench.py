@@ -47,6 +47,8 @@ def parse():
                          "2000-request Poisson trace")
     ap.add_argument("--sizes", default="16384,32768", help="orders for --workload mixed")
     ap.add_argument("--count", type=int, default=0, help="matrices (batched) or requests (serve); 0 = default")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="after the timed steps, run three plain device copies of 1 GiB (reference for HBM counters)")
     return ap.parse_args()
 
 
@@ -348,6 +350,15 @@ def main():
     cnt = (ctypes.c_int64 * 2)()
     lib.skf_profile_read(ms, fl, cnt, 1)
 
+    if args.copy_calibration:
+        # a plain copy of known size: 1 GiB read + 1 GiB written per launch
+        a = torch.empty(1 << 27, dtype=torch.float64, device=dev)
+        b = torch.empty_like(a)
+        a.fill_(1.0)
+        for _ in range(3):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        del a, b
     infos = dinfo.cpu().tolist()
     assert all(v == 0 for v in infos), f"factorization reported info {infos}"
     ms_per_step = (t1 - t0) * 1e3 / args.steps

@@ -18,19 +18,20 @@
 namespace skf {
 
 // The panel kernel is one wave per workgroup with 64 row slots; LDS holds three
-// (nb/2) x 64 FP64 arrays per workgroup (96 KB at nb = 128, 48 KB at nb = 64), so
-// a CU hosts one (nb = 128) or three (nb = 64) of them at once.  Every
+// (nb/2) x 64 FP64 arrays per workgroup (97 KB at nb = 128, 49 KB at nb = 64),
+// so a CU hosts one (nb = 128) or two (nb = 64) of them at once.  Every
 // workgroup of a panel launch must be resident together.
-static constexpr int kSlots = 64;
 static constexpr int kMaxPanelG = 512;
 
+static int slots() { return panel_slots(); }
+
 static int64_t max_panel_groups(int nb) {
-  const int64_t per_cu = (nb == 128) ? 1 : 3;
+  const int64_t per_cu = (nb == 128) ? 1 : 2;
   return std::min<int64_t>(kMaxPanelG, per_cu * device_info().num_cus);
 }
 
 int ltlt_plan_nb(int64_t n) {
-  const int64_t g0 = std::max<int64_t>(1, (n - 1 + kSlots - 1) / kSlots);
+  const int64_t g0 = std::max<int64_t>(1, (n - 1 + slots() - 1) / slots());
   // override for tests and tuning: SKF_NB=64 or 128 (ignored when infeasible)
   if (const char* e = getenv("SKF_NB")) {
     const int want = atoi(e);
@@ -42,10 +43,10 @@ int ltlt_plan_nb(int64_t n) {
 }
 
 int ltlt_panel_grid(int64_t m, int nb, int* G, int* S) {
-  const int64_t g = std::max<int64_t>(1, (m + kSlots - 1) / kSlots);
+  const int64_t g = std::max<int64_t>(1, (m + slots() - 1) / slots());
   if (g > max_panel_groups(nb)) return SKF_ENOTIMPL;
   *G = (int)g;
-  *S = kSlots;
+  *S = slots();
   return 0;
 }
 
@@ -59,7 +60,7 @@ static size_t carve(LtltWork* w, char* base, int64_t n, int nb) {
     return base ? (void*)(base + o) : nullptr;
   };
   const int64_t np = npanels_of(n, nb);
-  const int gmax = (int)std::max<int64_t>(1, (n - 1 + kSlots - 1) / kSlots);  // first (largest) panel
+  const int gmax = (int)std::max<int64_t>(1, (n - 1 + slots() - 1) / slots());  // first (largest) panel
   w->W = (double*)take(sizeof(double) * (size_t)n * n);
   w->Lbuf = (double*)take(sizeof(double) * (size_t)n * nb);
   w->Lp = (double*)take(sizeof(double) * (size_t)n * (nb / 2));
@@ -69,6 +70,7 @@ static size_t carve(LtltWork* w, char* base, int64_t n, int nb) {
   w->sigma = (int32_t*)take(sizeof(int32_t) * (size_t)std::max<int64_t>(np, 1) * n);
   w->rec = (uint64_t*)take(sizeof(uint64_t) * panel_record_words(gmax));
   w->mirror = (uint64_t*)take(sizeof(uint64_t) * panel_mirror_words(gmax, nb));
+  w->Lscr = (double*)take(sizeof(double) * panel_scratch_doubles(gmax, nb));
   w->status = (int*)take(256);
   w->bytes = off;
   return off;
@@ -97,7 +99,7 @@ int run_ltlt(int64_t n, double* A, int64_t lda, int32_t* ipiv, double* T, int pr
   if (nb < 0) return SKF_ENOTIMPL;
   LtltWork w = ltlt_carve(work, n, prec);
   if (lwork < w.bytes) return SKF_EWORK;
-  const int gmax = (int)std::max<int64_t>(1, (n - 1 + kSlots - 1) / kSlots);
+  const int gmax = (int)std::max<int64_t>(1, (n - 1 + slots() - 1) / slots());
   int rc;
   if ((rc = launch_fill_i32(w.status, 1, 0, s))) return rc;
   if ((rc = launch_fill_i32(ipiv, 1, 0, s))) return rc;  // ipiv[0] = 0
@@ -132,6 +134,7 @@ int run_ltlt(int64_t n, double* A, int64_t lda, int32_t* ipiv, double* T, int pr
     pp.ipiv = ipiv;
     pp.rec = w.rec;
     pp.mirror = w.mirror;
+    pp.Lscr = w.Lscr;
     pp.status = w.status;
     pp.tag_base = (uint32_t)k0;
     prof_begin(s);
@@ -144,8 +147,8 @@ int run_ltlt(int64_t n, double* A, int64_t lda, int32_t* ipiv, double* T, int pr
                              ldb[(P + 1) % 2], pp.pi, w.Lp, w.Wp, n, w.cnext,
                              prec == SKF_PREC_F32_TRAILING, s);
       if (rc) return rc;
-      const double m = (double)(n - lo);
-      prof_end(s, 1, 2.0 * (double)nsteps * m * (m - 1.0) / 2.0);
+      const double mt = (double)(n - lo);
+      prof_end(s, 1, 2.0 * (double)nsteps * mt * (mt - 1.0) / 2.0);
     }
     if ((rc = launch_copy_panel_L(n, k0, nsteps, w.Lbuf, w.W, n, s))) return rc;
   }

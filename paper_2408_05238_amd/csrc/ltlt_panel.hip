@@ -39,10 +39,20 @@
 namespace skf {
 
 constexpr int kPanelThreads = 64;
-constexpr int kRecWords = 8;  // psi, (slot<<24 | hbm), c hi, c lo, l0 hi, l0 lo, -, -
+// A workgroup's record for one step is two 64-bit words, each carrying a 16-bit
+// step tag and 48 payload bits:
+//   w0 = tag | flags:2 | slot:6 | psi:24 | |c| bits 62..47
+//   w1 = tag | sign of c | |c| bits 46..0
+// (flags: bit 31 of the 32-bit field = no candidate, bit 30 = non-finite
+// column), so a reader needs two atomic 64-bit loads per record.  Records sit
+// kRecStride words apart; the candidate's l0 (read only from the winner) is kept
+// in a separate pair of 32-bit-tagged words.
+constexpr int kRecStride = 16;
+constexpr uint32_t kFlagNonFinite = 1u << 30;
+constexpr uint32_t kFlagNoCand = 1u << 31;
+constexpr uint64_t kLow47 = (1ull << 47) - 1;
 constexpr int kMaxG = 512;    // workgroups of one panel launch
 constexpr uint32_t kNoCand = 0xFFFFFFFFu;
-constexpr uint32_t kNonFinite = 0xFFFFFFFEu;
 
 namespace {
 
@@ -54,6 +64,8 @@ __device__ inline void st_word(uint64_t* p, uint64_t v) {
 }
 __device__ inline uint64_t mk(uint32_t tag, uint32_t payload) { return ((uint64_t)tag << 32) | payload; }
 __device__ inline uint32_t tag_of(uint64_t w) { return (uint32_t)(w >> 32); }
+__device__ inline uint32_t tag16(uint32_t tag) { return (tag - 1u) % 65535u + 1u; }  // never 0
+__device__ inline uint32_t tag16_of(uint64_t w) { return (uint32_t)(w >> 48); }
 __device__ inline uint32_t hi32(double x) { return (uint32_t)((uint64_t)__double_as_longlong(x) >> 32); }
 __device__ inline uint32_t lo32(double x) { return (uint32_t)(__double_as_longlong(x)); }
 __device__ inline double from32(uint32_t h, uint32_t l) {
@@ -77,43 +89,36 @@ __device__ inline bool better(double a, uint32_t pa, double b, uint32_t pb) {
   return (a > b) || (a == b && pa < pb);
 }
 
-template <int CTRL>
-__device__ inline void best_step(double& v, uint32_t& p, int& s) {
-  const double ov = dppd<CTRL>(v);
-  const uint32_t op = dpp32<CTRL>(p);
-  const int os = (int)dpp32<CTRL>((uint32_t)s);
-  if (better(ov, op, v, p)) {
-    v = ov;
-    p = op;
-    s = os;
-  }
+// Wave-wide maximum of v / minimum of u; every lane ends with the result.
+// Inside each row of 16 lanes: xor-1, xor-2, rotate-4, rotate-8 (DPP); across
+// the four rows: readlane of lanes 0, 16, 32, 48.
+__device__ inline double wave_max(double v) {
+  v = fmax(v, dppd<0xB1>(v));   // quad_perm [1,0,3,2]
+  v = fmax(v, dppd<0x4E>(v));   // quad_perm [2,3,0,1]
+  v = fmax(v, dppd<0x124>(v));  // row_ror:4
+  v = fmax(v, dppd<0x128>(v));  // row_ror:8
+  return fmax(fmax(rld(v, 0), rld(v, 16)), fmax(rld(v, 32), rld(v, 48)));
+}
+__device__ inline uint32_t wave_min_u32(uint32_t u) {
+  u = min(u, dpp32<0xB1>(u));
+  u = min(u, dpp32<0x4E>(u));
+  u = min(u, dpp32<0x124>(u));
+  u = min(u, dpp32<0x128>(u));
+  return min(min(rl32(u, 0), rl32(u, 16)), min(rl32(u, 32), rl32(u, 48)));
 }
 
-// Wave-wide arg-best over (v, p, s); every lane ends with the result.  Within a
-// row of 16 lanes: xor-1, xor-2, rotate-4, rotate-8 (DPP); across the four rows:
-// readlane of lanes 0, 16, 32, 48.
-__device__ inline void wave_best(double& v, uint32_t& p, int& s) {
-  best_step<0xB1>(v, p, s);   // quad_perm [1,0,3,2]
-  best_step<0x4E>(v, p, s);   // quad_perm [2,3,0,1]
-  best_step<0x124>(v, p, s);  // row_ror:4
-  best_step<0x128>(v, p, s);  // row_ror:8
-  double bv = rld(v, 0);
-  uint32_t bp = rl32(p, 0);
-  int bs = (int)rl32((uint32_t)s, 0);
-#pragma unroll
-  for (int r = 1; r < 4; ++r) {
-    const double ov = rld(v, 16 * r);
-    const uint32_t op = rl32(p, 16 * r);
-    const int os = (int)rl32((uint32_t)s, 16 * r);
-    if (better(ov, op, bv, bp)) {
-      bv = ov;
-      bp = op;
-      bs = os;
-    }
-  }
-  v = bv;
-  p = bp;
-  s = bs;
+// Lane of the best candidate (largest v, then lowest p) among the lanes with
+// `cand` set (their v >= 0), or -1 if there is none.  The maximum is found with
+// plain max steps and the lanes holding it by one ballot; only an exact tie of
+// values needs the index reduction.
+__device__ inline int wave_argbest(double v, uint32_t p, bool cand) {
+  const double m = wave_max(cand ? v : -1.0);
+  const uint64_t at = __ballot(cand && v == m);
+  if (at == 0) return -1;
+  if ((at & (at - 1)) == 0) return (int)__builtin_ctzll(at);
+  const bool mine = (at >> threadIdx.x) & 1ull;
+  const uint32_t q = wave_min_u32(mine ? p : 0xFFFFFFFFu);
+  return (int)__builtin_ctzll(__ballot(mine && p == q));
 }
 
 // Wall-clock limit for one wait (the constant 100 MHz counter): 2 s.
@@ -133,25 +138,32 @@ __global__ void __launch_bounds__(kPanelThreads) panel_kernel(PanelParams P) {
 
   const int lane = threadIdx.x;
   const int g = blockIdx.x;
-  if (*P.status != 0) return;  // an earlier panel failed: every workgroup leaves at once
   const int64_t n = P.n, k0 = P.k0, ld = P.ld;
   const double* __restrict__ src = P.src;
   const int64_t rowbase = k0 + 1 + (int64_t)g * P.S;
   const int nslots = (int)max((int64_t)0, min((int64_t)P.S, n - rowbase));
   const int G = P.G;
   const bool mine = lane < nslots;
+  if (g == 0)
+    for (int64_t i = lane; i <= k0; i += kPanelThreads) P.pi[i] = (int32_t)i;
+  if (*P.status != 0) {
+    // an earlier panel failed: every workgroup leaves at once, with this
+    // panel's permutation the identity (later kernels index rows through it)
+    if (mine) P.pi[rowbase + lane] = (int32_t)(rowbase + lane);
+    return;
+  }
   uint64_t* const my_mirror = P.mirror + ((size_t)g * 64 + lane) * NP * 4;
 
   for (int q = 0; q < NP; ++q) {
     sm.LW[q][lane] = make_double2(0.0, 0.0);
     sm.Le[q][lane] = 0.0;
   }
-  if (g == 0)
-    for (int64_t i = lane; i <= k0; i += kPanelThreads) P.pi[i] = (int32_t)i;
+  if (lane < NP) sm.coef[lane] = make_double2(0.0, 0.0);
 
   int32_t psi = mine ? (int32_t)(rowbase + lane) : INT32_MAX;
   const int32_t hbm = mine ? (int32_t)(rowbase + lane) : 0;
   double cur = mine ? src[rowbase + lane + k0 * ld] : 0.0;
+  double lj = 0.0;  // this slot's l of the current pair (register copy of sm.Le[j][lane])
   int stop = 0;
 
   for (int si = 0; si < P.nsteps; ++si) {
@@ -159,54 +171,64 @@ __global__ void __launch_bounds__(kPanelThreads) panel_kernel(PanelParams P) {
     const int j = si >> 1;
     const int ph = si & 1;
     const uint32_t tag = P.tag_base + (uint32_t)si + 1u;
-    uint64_t* const recs = P.rec + (size_t)(si & 1) * G * kRecWords;
+    const uint32_t t16 = tag16(tag);
+    uint64_t* const recs = P.rec + (size_t)(si & 1) * G * (kRecStride + 2);
+    uint64_t* const lzs = recs + (size_t)G * kRecStride;  // l0 words of record g at 2g, 2g+1
 
     // (A) local candidate: this lane's slot if its current index is >= k+1
     const bool act = mine && psi >= k + 1;
-    double bv = act ? fabs(cur) : -1.0;
-    uint32_t bp = act ? (uint32_t)psi : kNoCand;
-    int bs = act ? lane : -1;
     const bool nonfin = __any(act && !isfinite(cur));
-    wave_best(bv, bp, bs);
+    const int bs = wave_argbest(fabs(cur), (uint32_t)psi, act);
 
-    // (B) publish this workgroup's record (read the candidate's data by readlane)
+    // (B) publish this workgroup's record (the candidate's data by readlane);
+    // lanes 0..3 each store one word, the payloads picked without branches
     {
       const int owner = (bs >= 0) ? bs : 0;
       const double cval = rld(cur, owner);
-      const uint32_t h = rl32((uint32_t)hbm, owner);
-      const double lz = (bs >= 0) ? sm.Le[j][owner] : 0.0;
-      uint32_t pay = 0;
-      if (lane == 0) pay = nonfin ? kNonFinite : bp;
-      else if (lane == 1) pay = ((uint32_t)owner << 24) | h;
-      else if (lane == 2) pay = hi32(cval);
-      else if (lane == 3) pay = lo32(cval);
-      else if (lane == 4) pay = hi32(lz);
-      else if (lane == 5) pay = lo32(lz);
-      if (lane < 6) st_word(recs + (size_t)g * kRecWords + lane, mk(tag, pay));
+      const double lz = rld(lj, owner);  // readers ignore it when there is no candidate
+      const uint32_t meta = nonfin ? kFlagNonFinite
+                                   : (bs < 0 ? kFlagNoCand : (rl32((uint32_t)psi, owner) | ((uint32_t)owner << 24)));
+      const uint64_t cb = (uint64_t)__double_as_longlong(cval);
+      const uint64_t mag = cb & ~(1ull << 63);
+      const uint64_t th = (uint64_t)t16 << 48;
+      const uint64_t w0 = th | ((uint64_t)meta << 16) | (mag >> 47);
+      const uint64_t w1 = th | ((cb >> 63) << 47) | (mag & kLow47);
+      const uint64_t v = (lane == 0) ? w0 : (lane == 1) ? w1 : (lane == 2) ? mk(tag, hi32(lz)) : mk(tag, lo32(lz));
+      uint64_t* const dstw = (lane < 2) ? recs + (size_t)g * kRecStride + lane : lzs + 2 * g + (lane - 2);
+      if (lane < 4) st_word(dstw, v);
     }
 
-    // (C) every workgroup's record (lane t reads records t, t+64, ...) -> global pivot
-    double gv = -1.0;
-    uint32_t gp = kNoCand;
+    // (C) every workgroup's record (lane t reads records t, t+64, ...) -> global pivot.
+    // Each round reloads both words of every record (addresses always valid;
+    // lanes past G read record 0 and ignore it) until all carry this step's tag.
+    double gv = -1.0, gc = 0.0;
+    uint32_t gp = kNoCand, gslot = 0;
     int gs = -1;
     bool bad = false, tout = false;
-    double cc[NQ];
-    uint32_t ch[NQ];
     {
-      uint64_t w[NQ][4];
+      uint64_t w[NQ][2];
+      const uint64_t* rp[NQ];
 #pragma unroll
       for (int q = 0; q < NQ; ++q) {
         const int rr = lane + 64 * q;
-#pragma unroll
-        for (int t = 0; t < 4; ++t) w[q][t] = (rr < G) ? ld_word(recs + (size_t)rr * kRecWords + t) : mk(tag, 0);
+        rp[q] = recs + (size_t)(rr < G ? rr : 0) * kRecStride;
       }
+      auto load_all = [&]() {
+#pragma unroll
+        for (int q = 0; q < NQ; ++q) {
+          w[q][0] = ld_word(rp[q]);
+          w[q][1] = ld_word(rp[q] + 1);
+        }
+      };
+      load_all();
       uint64_t t0 = 0;
       for (int it = 0;; ++it) {
         bool ok = true;
 #pragma unroll
-        for (int q = 0; q < NQ; ++q)
-#pragma unroll
-          for (int t = 0; t < 4; ++t) ok = ok && tag_of(w[q][t]) == tag;
+        for (int q = 0; q < NQ; ++q) {
+          const bool need = lane + 64 * q < G;
+          ok &= !need | ((tag16_of(w[q][0]) == t16) & (tag16_of(w[q][1]) == t16));  // no short-circuit branches
+        }
         if (__all(ok)) break;
         if ((it & 31) == 0) {
           const uint64_t now = wall_clock64();
@@ -216,56 +238,40 @@ __global__ void __launch_bounds__(kPanelThreads) panel_kernel(PanelParams P) {
             break;
           }
         }
-#pragma unroll
-        for (int q = 0; q < NQ; ++q) {
-          const int rr = lane + 64 * q;
-#pragma unroll
-          for (int t = 0; t < 4; ++t)
-            if (tag_of(w[q][t]) != tag) w[q][t] = ld_word(recs + (size_t)rr * kRecWords + t);
-        }
+        load_all();
       }
 #pragma unroll
       for (int q = 0; q < NQ; ++q) {
         const int rr = lane + 64 * q;
-        cc[q] = 0.0;
-        ch[q] = 0;
-        if (rr < G && !tout) {
-          const uint32_t ps = (uint32_t)w[q][0];
-          if (ps == kNonFinite) {
-            bad = true;
-          } else if (ps != kNoCand) {
-            const double c = from32((uint32_t)w[q][2], (uint32_t)w[q][3]);
-            cc[q] = c;
-            ch[q] = (uint32_t)w[q][1];
-            if (better(fabs(c), ps, gv, gp)) {
-              gv = fabs(c);
-              gp = ps;
-              gs = rr;
-            }
+        const uint32_t meta = (uint32_t)(w[q][0] >> 16);
+        const bool use = rr < G && !tout;
+        bad |= use && (meta & kFlagNonFinite);
+        if (use && !(meta & (kFlagNonFinite | kFlagNoCand))) {
+          const uint64_t mag = ((w[q][0] & 0xFFFFull) << 47) | (w[q][1] & kLow47);
+          const double a = __longlong_as_double((long long)mag);
+          const uint32_t ps = meta & 0xFFFFFFu;
+          if (better(a, ps, gv, gp)) {
+            gv = a;
+            gc = __longlong_as_double((long long)(mag | (((w[q][1] >> 47) & 1ull) << 63)));
+            gp = ps;
+            gs = rr;
+            gslot = meta >> 24 & 63u;
           }
         }
       }
     }
     tout = __any(tout);
     bad = __any(bad);
-    wave_best(gv, gp, gs);
-    stop = tout ? 4 : (bad ? 2 : (gs < 0 ? 4 : 0));
+    const int wl = wave_argbest(gv, gp, gs >= 0);
+    stop = tout ? 4 : (bad ? 2 : (wl < 0 ? 4 : 0));
     if (stop) break;
 
-    // pivot's value and origin: in lane gs % 64, entry gs / 64 of its records
-    const int wl = gs & 63, wq = gs >> 6;
-    double wc = 0.0;
-    uint32_t wh = 0;
-#pragma unroll
-    for (int q = 0; q < NQ; ++q)
-      if (q == wq) {
-        wc = cc[q];
-        wh = ch[q];
-      }
-    const double alpha = rld(wc, wl);
-    const uint32_t hw = rl32(wh, wl);
-    const int64_t hx = hw & 0xFFFFFFu;  // panel-start row of the new row r (= column x)
-    const int wslot = (int)(hw >> 24);  // its slot inside workgroup gs
+    // the pivot: its value, current index, workgroup and slot (from lane wl)
+    const double alpha = rld(gc, wl);
+    gp = rl32(gp, wl);
+    gs = (int)rl32((uint32_t)gs, wl);
+    const int wslot = (int)rl32(gslot, wl);
+    const int64_t hx = k0 + 1 + (int64_t)gs * P.S + wslot;  // panel-start row of the new row r (= column x)
     const int64_t pidx = gp, r = k + 1;
 
     // (D) relabel the two slots; record the step
@@ -279,31 +285,41 @@ __global__ void __launch_bounds__(kPanelThreads) panel_kernel(PanelParams P) {
     }
     const bool below = mine && psi >= k + 2;  // rows of the new column x = k+1
 
-    // (F) gather column x below its diagonal; fetch the pivot row's coefficients
-    double gat = 0.0;
-    if (below) {
-      const int64_t a = hbm;
-      gat = (a > hx) ? src[a + hx * ld] : -src[hx + a * ld];
-    }
+    // (F) gather column x below its diagonal (every lane loads from a valid
+    // address; the sign and the mask are applied afterwards); fetch the pivot
+    // row's coefficients and l0
+    const bool lowr = (int64_t)hbm > hx;
+    const double graw = src[lowr ? (int64_t)hbm + hx * ld : hx + (int64_t)hbm * ld];
     // lane t holds coefficient d = t (and d = t + 64): d = 2q -> l'[q], d = 2q+1 -> w[q]
-    double cA = 0.0, cB = 0.0, l0 = 0.0;
+    double l0 = 0.0;
     {
+      constexpr bool kTwo = 2 * NP > 64;  // coefficients 64.. exist (nb = 128)
       const uint64_t* wm = P.mirror + ((size_t)gs * 64 + wslot) * NP * 4;
       const int nd = 2 * j;
       const uint32_t tA = P.tag_base + 2u * (uint32_t)(lane >> 1) + 2u;
       const uint32_t tB = P.tag_base + 2u * (uint32_t)((lane + 64) >> 1) + 2u;
-      const bool hasA = lane < nd, hasB = lane + 64 < nd;
-      uint64_t a0 = hasA ? ld_word(wm + 2 * lane) : mk(tA, 0);
-      uint64_t a1 = hasA ? ld_word(wm + 2 * lane + 1) : mk(tA, 0);
-      uint64_t b0 = hasB ? ld_word(wm + 2 * (lane + 64)) : mk(tB, 0);
-      uint64_t b1 = hasB ? ld_word(wm + 2 * (lane + 64) + 1) : mk(tB, 0);
-      const uint64_t* lwp = recs + (size_t)gs * kRecWords + 4;
-      uint64_t z0 = (lane == 0) ? ld_word(lwp) : mk(tag, 0);
-      uint64_t z1 = (lane == 0) ? ld_word(lwp + 1) : mk(tag, 0);
+      const bool hasA = lane < nd, hasB = kTwo && lane + 64 < nd;
+      const int ia = 2 * lane, ib = kTwo ? 2 * (lane + 64) : 2 * lane;
+      const uint64_t* lwp = lzs + 2 * gs;
+      uint64_t a0, a1, b0, b1, z0, z1;
+      auto load_all = [&]() {
+        a0 = ld_word(wm + ia);
+        a1 = ld_word(wm + ia + 1);
+        if constexpr (kTwo) {
+          b0 = ld_word(wm + ib);
+          b1 = ld_word(wm + ib + 1);
+        } else {
+          b0 = b1 = 0;
+        }
+        z0 = ld_word(lwp);
+        z1 = ld_word(lwp + 1);
+      };
+      load_all();
       uint64_t t0 = 0;
       for (int it = 0;; ++it) {
-        const bool ok = tag_of(a0) == tA && tag_of(a1) == tA && tag_of(b0) == tB && tag_of(b1) == tB &&
-                        tag_of(z0) == tag && tag_of(z1) == tag;
+        const bool ok = (!hasA | ((tag_of(a0) == tA) & (tag_of(a1) == tA))) &
+                        (!hasB | ((tag_of(b0) == tB) & (tag_of(b1) == tB))) & (tag_of(z0) == tag) &
+                        (tag_of(z1) == tag);
         if (__all(ok)) break;
         if ((it & 31) == 0) {
           const uint64_t now = wall_clock64();
@@ -313,24 +329,18 @@ __global__ void __launch_bounds__(kPanelThreads) panel_kernel(PanelParams P) {
             break;
           }
         }
-        if (tag_of(a0) != tA) a0 = ld_word(wm + 2 * lane);
-        if (tag_of(a1) != tA) a1 = ld_word(wm + 2 * lane + 1);
-        if (tag_of(b0) != tB) b0 = ld_word(wm + 2 * (lane + 64));
-        if (tag_of(b1) != tB) b1 = ld_word(wm + 2 * (lane + 64) + 1);
-        if (tag_of(z0) != tag) z0 = ld_word(lwp);
-        if (tag_of(z1) != tag) z1 = ld_word(lwp + 1);
+        load_all();
       }
-      cA = from32((uint32_t)a0, (uint32_t)a1);
-      cB = from32((uint32_t)b0, (uint32_t)b1);
       // coefficient d sits in component d % 2 of pair d / 2
-      if (hasA) reinterpret_cast<double*>(&sm.coef[0])[lane] = cA;
-      if (hasB) reinterpret_cast<double*>(&sm.coef[0])[lane + 64] = cB;
-      l0 = rld(from32((uint32_t)z0, (uint32_t)z1), 0);
+      if (hasA) reinterpret_cast<double*>(&sm.coef[0])[lane] = from32((uint32_t)a0, (uint32_t)a1);
+      if (hasB) reinterpret_cast<double*>(&sm.coef[0])[lane + 64] = from32((uint32_t)b0, (uint32_t)b1);
+      l0 = from32((uint32_t)z0, (uint32_t)z1);
       if (__any(tout)) {
         stop = 4;
         break;
       }
     }
+    const double gat = below ? (lowr ? graw : -graw) : 0.0;
 
     // (E) multipliers below row k+1, alpha at row k+1
     if (mine) {
@@ -343,24 +353,31 @@ __global__ void __launch_bounds__(kPanelThreads) panel_kernel(PanelParams P) {
         if (ph == 0) sm.Le[j][lane] = val;
         else sm.LW[j][lane].x = val;
       }
+      if (ph == 0) lj = wr ? val : 0.0;
     }
 
-    // skew GEMV with the pivot row over the pairs so far
-    double corr = 0.0, corr2 = 0.0;
+    // skew GEMV with the pivot row over the pairs so far: eight pairs per pass,
+    // their LDS reads issued together (coefficients of pairs >= j are zero)
+    double corr = 0.0;
     {
-      int q = 0;
-      for (; q + 1 < j; q += 2) {
-        const double2 a = sm.LW[q][lane], b = sm.LW[q + 1][lane];
-        const double2 ca = sm.coef[q], cb = sm.coef[q + 1];
-        corr += a.x * ca.y - a.y * ca.x;
-        corr2 += b.x * cb.y - b.y * cb.x;
+      double c0 = 0.0, c1 = 0.0, c2 = 0.0, c3 = 0.0;
+      const int jr = (j + 7) & ~7;
+      for (int q = 0; q < jr; q += 8) {
+        double2 a[8], c[8];
+#pragma unroll
+        for (int t = 0; t < 8; ++t) {
+          a[t] = sm.LW[q + t][lane];
+          c[t] = sm.coef[q + t];
+        }
+#pragma unroll
+        for (int t = 0; t < 8; t += 4) {
+          c0 += a[t].x * c[t].y - a[t].y * c[t].x;
+          c1 += a[t + 1].x * c[t + 1].y - a[t + 1].y * c[t + 1].x;
+          c2 += a[t + 2].x * c[t + 2].y - a[t + 2].y * c[t + 2].x;
+          c3 += a[t + 3].x * c[t + 3].y - a[t + 3].y * c[t + 3].x;
+        }
       }
-      if (q < j) {
-        const double2 a = sm.LW[q][lane];
-        const double2 ca = sm.coef[q];
-        corr += a.x * ca.y - a.y * ca.x;
-      }
-      corr += corr2;
+      corr = (c0 + c1) + (c2 + c3);
     }
 
     // finish the column
@@ -370,7 +387,7 @@ __global__ void __launch_bounds__(kPanelThreads) panel_kernel(PanelParams P) {
       const double w = below ? gat + corr : 0.0;
       sm.LW[j][lane].y = w;
       const double lp = sm.LW[j][lane].x;
-      if (below) cur = w + alpha * (sm.Le[j][lane] - l0 * lp);
+      if (below) cur = w + alpha * (lj - l0 * lp);
       // mirror entries of pair j for this slot (read by other workgroups' later steps)
       if (mine) {
         const uint32_t mt = P.tag_base + 2u * (uint32_t)j + 2u;
@@ -386,6 +403,8 @@ __global__ void __launch_bounds__(kPanelThreads) panel_kernel(PanelParams P) {
   // ---- panel end ----
   if (stop) {
     if (lane == 0) atomicMin(P.status, (stop & 4) ? SKF_ETIMEOUT : SKF_ENONFINITE);
+    // the permutation stays in range (row indices of this panel) for the kernels after it
+    if (mine) P.pi[psi] = hbm;
     return;
   }
   if (!mine) return;
@@ -429,8 +448,12 @@ int launch_panel(const PanelParams& p, hipStream_t s) {
   return SKF_ENOTIMPL;
 }
 
-size_t panel_record_words(int G) { return (size_t)2 * G * kRecWords; }
+size_t panel_record_words(int G) { return (size_t)2 * G * (kRecStride + 2); }
 
 size_t panel_mirror_words(int G, int nb) { return (size_t)G * 64 * (nb / 2) * 4; }
+
+int panel_slots() { return 64; }
+
+size_t panel_scratch_doubles(int, int) { return 0; }
 
 }  // namespace skf

@@ -82,15 +82,18 @@ struct PanelParams {
   double* cnext;     // n: first column of the next panel
   double* T;         // global T output
   int32_t* ipiv;     // global ipiv output
-  uint64_t* rec;     // sync records: 2 x G x kRecWords
+  uint64_t* rec;     // sync records, double-buffered by step parity
   uint64_t* mirror;  // per-workgroup tagged copy of each slot's pair coefficients
+  double* Lscr;      // (nb/2) x G x slots: first-step multipliers, slot-indexed
   int* status;       // device status word (0 ok)
   uint32_t tag_base; // tag of step k is tag_base + (k - k0) + 1
 };
 
 int launch_panel(const PanelParams& p, hipStream_t s);
+int panel_slots();
 size_t panel_record_words(int G);
 size_t panel_mirror_words(int G, int nb);
+size_t panel_scratch_doubles(int G, int nb);
 
 // Workspace layout of the blocked path.
 struct LtltWork {
@@ -103,6 +106,7 @@ struct LtltWork {
   int32_t* sigma;  // npanels x n: composed later permutations
   uint64_t* rec;   // sync records
   uint64_t* mirror;  // panel coefficient mirrors
+  double* Lscr;    // panel multiplier scratch
   int* status;     // 1 int (+ padding)
   size_t bytes;
 };
