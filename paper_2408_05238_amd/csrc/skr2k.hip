@@ -9,11 +9,12 @@
 // Tiling: a 256-thread workgroup owns a 128 x 128 tile of C; each of its four
 // waves owns a 64 x 64 quarter (4 x 4 MFMA blocks of 16 x 16; a quarter lying
 // wholly above the diagonal skips its products but still helps to load).  The
-// inner dimension is walked in chunks of 16: the workgroup stages the chunk's
-// 128 x 16 slices of X (its rows) and Y (its columns) in LDS, double-buffered,
-// with the global loads of chunk c+1 in flight while the matrix cores work on
-// chunk c (one barrier per chunk).  Registers are kept to 256 per lane so that
-// two workgroups share a CU and cover each other's load and barrier waits.
+// inner dimension is walked in chunks of 8: the chunk's 128 x 8 slices of X
+// (the tile's rows) and Y (its columns) are copied from global memory straight
+// into LDS (global_load_lds, no registers), into a ring of four stages, so three
+// chunks are in flight while the matrix cores work on the fourth; one barrier
+// per chunk.  Registers stay under 256 per lane so that two workgroups share a
+// CU and cover each other's barrier and epilogue waits.
 // In the trailing-update form the accumulators start from the permuted source
 // tile, so the epilogue is a plain store.
 //
@@ -29,9 +30,9 @@ namespace {
 constexpr int TM = 128;     // workgroup tile
 constexpr int WT = 64;      // wave tile
 constexpr int NTHR = 256;
-constexpr int KC = 16;      // inner terms per LDS chunk
+constexpr int KC = 8;       // inner terms per LDS chunk
+constexpr int NSTG = 4;     // LDS stages: three chunks in flight ahead of the one multiplied
 constexpr int LSTR = TM + 16;  // doubles per staged column: consecutive k-groups land 128 B apart in the banks
-constexpr int PER_THR = KC * TM / NTHR;  // staged doubles per thread and operand (8)
 
 template <typename T>
 struct Mfma;
@@ -85,62 +86,74 @@ struct Stage {
   double Y[KC][LSTR];  // Y rows of the tile's column block
 };
 
-// Global loads of one chunk into registers: thread t takes, for u < 8, entry
-// e = t + 256 u, i.e. column e / 128 of the chunk and row e % 128 (a wave
-// instruction reads 64 consecutive doubles of one column).  Chunk c < nh covers
-// inner terms 16c.. of P Q^T, chunk c >= nh those of (-Q) P^T.
-struct ChunkRegs {
-  double x[PER_THR], y[PER_THR];
-};
+// Global -> LDS copy of one wave: lane l's VEC bytes land at lds + VEC * l.
+// Issued as inline assembly so that the only waits on these copies are the
+// explicit vmcnt waits of the main loop (a load issued here is never consumed
+// through a register).
+template <int VEC>
+__device__ inline void dma(const void* g, uint32_t lds) {
+  if constexpr (VEC == 16)
+    asm volatile("s_mov_b32 m0, %1\n\tglobal_load_lds_dwordx4 %0, off" ::"v"(g), "s"(lds) : "memory");
+  else
+    asm volatile("s_mov_b32 m0, %1\n\tglobal_load_lds_dword %0, off" ::"v"(g), "s"(lds) : "memory");
+}
 
-__device__ inline void chunk_load(const Operands& o, int64_t c, int64_t nh, int64_t rI, int64_t rJ,
-                                  ChunkRegs& R) {
+// Copies issued per wave and chunk: each wave stages 2 columns of X and 2 of Y;
+// a 128-double column is one 16-byte-lane copy or four 4-byte-lane copies.
+template <int VEC>
+constexpr int kCopiesPerChunk = (VEC == 16) ? 4 : 16;
+
+// Issue chunk c (inner terms 8c.. of P Q^T for c < nh, of (-Q) P^T after) into
+// stage s.  Columns past k are reloaded from a valid column and masked in
+// chunk_mma; rows past n are clamped to valid rows (never stored).  VEC = 16
+// needs 16-byte aligned bases, even leading dimensions and, for odd n, one
+// padding row (the launcher checks).
+template <int VEC>
+__device__ inline void chunk_issue(const Operands& o, int64_t c, int64_t nh, int64_t rI, int64_t rJ, Stage& s) {
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   const bool h2 = c >= nh;
   const int64_t kk = (h2 ? c - nh : c) * KC;
   const double* Xb = h2 ? o.Q : o.P;
   const double* Yb = h2 ? o.P : o.Q;
   const int64_t ldx = h2 ? o.ldq : o.ldp, ldy = h2 ? o.ldp : o.ldq;
-  const int t = threadIdx.x;
-  const int row = t & (TM - 1);
-  const int64_t ia = rI + row < o.n ? rI + row : o.n - 1;
-  const int64_t ib = rJ + row < o.n ? rJ + row : o.n - 1;
-  const char* xb = reinterpret_cast<const char*>(Xb + kk * ldx);
-  const char* yb = reinterpret_cast<const char*>(Yb + kk * ldy);
 #pragma unroll
-  for (int u = 0; u < PER_THR; ++u) {
-    const int col = (t >> 7) + 2 * u;
-    const int64_t cc = kk + col < o.k ? col : 0;  // past k: reload column 0, zeroed at the store
-    R.x[u] = *reinterpret_cast<const double*>(xb + ((uint32_t)(ia + cc * ldx) << 3));
-    R.y[u] = *reinterpret_cast<const double*>(yb + ((uint32_t)(ib + cc * ldy) << 3));
+  for (int u = 0; u < 2; ++u) {
+    const int col = 2 * wv + u;
+    const int64_t kc = (kk + col < o.k) ? kk + col : kk;
+    const double* xc = Xb + kc * ldx;
+    const double* yc = Yb + kc * ldy;
+    const uint32_t lx = __builtin_amdgcn_readfirstlane((uint32_t)(uintptr_t)&s.X[col][0]);
+    const uint32_t ly = __builtin_amdgcn_readfirstlane((uint32_t)(uintptr_t)&s.Y[col][0]);
+    if constexpr (VEC == 16) {
+      const int64_t rmax = (o.n - 1) & ~(int64_t)1;
+      const int64_t ra = min(rI + 2 * lane, rmax), rb = min(rJ + 2 * lane, rmax);
+      dma<16>(xc + ra, lx);
+      dma<16>(yc + rb, ly);
+    } else {
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const int64_t ra = min(rI + 32 * i + (lane >> 1), o.n - 1), rb = min(rJ + 32 * i + (lane >> 1), o.n - 1);
+        dma<4>(reinterpret_cast<const char*>(xc + ra) + 4 * (lane & 1), lx + 256 * i);
+        dma<4>(reinterpret_cast<const char*>(yc + rb) + 4 * (lane & 1), ly + 256 * i);
+      }
+    }
   }
 }
 
-__device__ inline void chunk_store(const Operands& o, int64_t c, int64_t nh, const ChunkRegs& R, Stage& s) {
-  const bool h2 = c >= nh;
-  const int64_t kk = (h2 ? c - nh : c) * KC;
-  const int t = threadIdx.x;
-  const int row = t & (TM - 1);
-#pragma unroll
-  for (int u = 0; u < PER_THR; ++u) {
-    const int col = (t >> 7) + 2 * u;
-    const bool in = kk + col < o.k;
-    s.X[col][row] = in ? R.x[u] : 0.0;
-    s.Y[col][row] = in ? R.y[u] : 0.0;
-  }
-}
-
-// acc += (+-X) Y^T over one staged chunk (four k-steps of 4).
+// acc += (+-X) Y^T over one staged chunk (two k-steps of 4); terms past k are zero.
 template <typename T>
-__device__ inline void chunk_mma(const Stage& s, int wr, int wc, bool neg, typename Mfma<T>::acc_t acc[4][4]) {
+__device__ inline void chunk_mma(const Stage& s, int wr, int wc, bool neg, int64_t kvalid,
+                                 typename Mfma<T>::acc_t acc[4][4]) {
   const int lane = threadIdx.x & 63;
   const int kq = lane >> 4, rr = lane & 15;
 #pragma unroll
   for (int ks = 0; ks < KC / 4; ++ks) {
+    const bool in = 4 * ks + kq < kvalid;
     T a[4], b[4];
 #pragma unroll
     for (int t = 0; t < 4; ++t) {
       const double va = s.X[4 * ks + kq][wr + 16 * t + rr];
-      a[t] = (T)(neg ? -va : va);
+      a[t] = in ? (T)(neg ? -va : va) : (T)0;
       b[t] = (T)s.Y[4 * ks + kq][wc + 16 * t + rr];
     }
 #pragma unroll
@@ -150,12 +163,26 @@ __device__ inline void chunk_mma(const Stage& s, int wr, int wc, bool neg, typen
   }
 }
 
+// Wait until this wave's copies of the chunk before the last `later` issued
+// chunks have landed (loads complete in order).
+template <int VEC>
+__device__ inline void wait_chunk(int later) {
+  constexpr int P = kCopiesPerChunk<VEC>;
+  // s_waitcnt: vmcnt[3:0] bits 0-3, expcnt bits 4-6, lgkmcnt bits 8-11, vmcnt[5:4] bits 14-15
+  constexpr int enc2 = ((2 * P) & 15) | (7 << 4) | (15 << 8) | (((2 * P) >> 4) << 14);
+  constexpr int enc1 = (P & 15) | (7 << 4) | (15 << 8) | ((P >> 4) << 14);
+  constexpr int enc0 = (7 << 4) | (15 << 8);
+  if (later >= 2) __builtin_amdgcn_s_waitcnt(enc2);
+  else if (later == 1) __builtin_amdgcn_s_waitcnt(enc1);
+  else __builtin_amdgcn_s_waitcnt(enc0);
+}
+
 // The workgroup's main loop: acc[mi][ni] of the calling wave accumulates
 // (P Q^T - Q P^T)[rI + wr + 16 mi + ., rJ + wc + 16 ni + .].  Every wave of the
 // workgroup must call it (it contains barriers); `active` waves do the products.
-// pro() runs once while the first chunk's loads are in flight (the trailing
-// update issues its source-tile gathers there, so both latencies overlap).
-template <typename T, typename Pro>
+// pro() runs once while the first chunks are in flight (the trailing update
+// issues its source-tile gathers there, so the latencies overlap).
+template <typename T, int VEC, typename Pro>
 __device__ inline void tile_mainloop(const Operands& o, int64_t rI, int64_t rJ, int wr, int wc, bool active,
                                      Stage* st, typename Mfma<T>::acc_t acc[4][4], Pro&& pro) {
   const int64_t nh = (o.k + KC - 1) / KC;
@@ -164,27 +191,28 @@ __device__ inline void tile_mainloop(const Operands& o, int64_t rI, int64_t rJ, 
     pro();
     return;
   }
-  ChunkRegs R;
-  chunk_load(o, 0, nh, rI, rJ, R);
+  const int64_t pre = nch < NSTG - 1 ? nch : NSTG - 1;
+  for (int64_t c = 0; c < pre; ++c) chunk_issue<VEC>(o, c, nh, rI, rJ, st[c]);
   pro();
-  chunk_store(o, 0, nh, R, st[0]);
-  __syncthreads();
   for (int64_t c = 0; c < nch; ++c) {
-    const bool more = c + 1 < nch;
-    if (more) chunk_load(o, c + 1, nh, rI, rJ, R);
-    if (active) chunk_mma<T>(st[c & 1], wr, wc, c >= nh, acc);
-    if (more) chunk_store(o, c + 1, nh, R, st[(c + 1) & 1]);
-    __syncthreads();
+    const int64_t later = min((int64_t)NSTG - 2, nch - 1 - c);  // chunks issued after c so far
+    wait_chunk<VEC>((int)later);
+    __builtin_amdgcn_s_barrier();  // chunk c visible to all waves; stage (c-1) % NSTG free
+    if (c + NSTG - 1 < nch) chunk_issue<VEC>(o, c + NSTG - 1, nh, rI, rJ, st[(c + NSTG - 1) % NSTG]);
+    if (active) {
+      const int64_t kk = (c >= nh ? c - nh : c) * KC;
+      chunk_mma<T>(st[c % NSTG], wr, wc, c >= nh, o.k - kk, acc);
+    }
   }
 }
 
 // ---------------------------------------------------------------------------
 // Plain in-place update: C := beta C + alpha (P Q^T - Q P^T), strict lower.
 // ---------------------------------------------------------------------------
-template <typename T>
+template <typename T, int VEC>
 __global__ void __launch_bounds__(NTHR, 2) skr2k_kernel(Operands o, double alpha, double beta, double* C,
                                                         int64_t ldc, int64_t ntiles) {
-  __shared__ Stage st[2];
+  __shared__ Stage st[NSTG];
   const int64_t n = o.n;
   int64_t bi, bj;
   tri_tile(xcd_remap(blockIdx.x, ntiles), &bi, &bj);
@@ -199,7 +227,7 @@ __global__ void __launch_bounds__(NTHR, 2) skr2k_kernel(Operands o, double alpha
   for (int a = 0; a < 4; ++a)
 #pragma unroll
     for (int b = 0; b < 4; ++b) acc[a][b] = typename Mfma<T>::acc_t{0, 0, 0, 0};
-  if (alpha != 0.0) tile_mainloop<T>(o, rI, rJ, wm * WT, wn * WT, active, st, acc, [] {});
+  if (alpha != 0.0) tile_mainloop<T, VEC>(o, rI, rJ, wm * WT, wn * WT, active, st, acc, [] {});
   if (!active) return;
   // Epilogue by 16-row slices: the slice's 16 loads of C are issued together
   // (clamped addresses, no branch around a load), then combined and stored.
@@ -235,14 +263,14 @@ __global__ void __launch_bounds__(NTHR, 2) skr2k_kernel(Operands o, double alpha
 // Out-of-place trailing update through the panel permutation:
 //   dst[i,j] = (j == lo) ? cnext[i] : S(pi[i], pi[j]) + (P Q^T - Q P^T)[i,j]
 // ---------------------------------------------------------------------------
-template <typename T>
+template <typename T, int VEC>
 __global__ void __launch_bounds__(NTHR, 2) skr2k_perm_kernel(Operands o, int64_t lo,
                                                              const double* __restrict__ src, int64_t lds,
                                                              double* __restrict__ dst, int64_t ldd,
                                                              const int32_t* __restrict__ pi,
                                                              const double* __restrict__ cnext,
                                                              int64_t ntiles) {
-  __shared__ Stage st[2];
+  __shared__ Stage st[NSTG];
   const int64_t n = o.n;
   int64_t bi, bj;
   tri_tile(xcd_remap(blockIdx.x, ntiles), &bi, &bj);
@@ -255,22 +283,31 @@ __global__ void __launch_bounds__(NTHR, 2) skr2k_perm_kernel(Operands o, int64_t
   // address is formed first and all 64 loads per lane are issued at once into
   // v; the masks (inside the strict lower triangle) and the signs (upper-storage
   // reads) are applied after a single wait.
+  // The tile's permutation is loaded first and waited for before the first
+  // operand copies are issued (a wait issued after them would drain them too).
+  int32_t pb[4], pa[4][4];
+#pragma unroll
+  for (int ni = 0; ni < 4; ++ni) {
+    const int64_t j = j0 + ni * 16 + (lane & 15);
+    pb[ni] = pi[j < n ? j : n - 1];
+  }
+#pragma unroll
+  for (int mi = 0; mi < 4; ++mi)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int64_t i = i0 + mi * 16 + Mfma<T>::row(lane, r);
+      pa[mi][r] = pi[i < n ? i : n - 1];
+    }
+  {
+    int32_t all = pb[0] ^ pb[1] ^ pb[2] ^ pb[3];
+#pragma unroll
+    for (int mi = 0; mi < 4; ++mi) all ^= pa[mi][0] ^ pa[mi][1] ^ pa[mi][2] ^ pa[mi][3];
+    asm volatile("" ::"v"(all));
+  }
   uint64_t ok = 0, neg = 0;
   auto gather = [&](int m_lo, int m_hi, auto&& put) {
-    int32_t pb[4];
-#pragma unroll
-    for (int ni = 0; ni < 4; ++ni) {
-      const int64_t j = j0 + ni * 16 + (lane & 15);
-      pb[ni] = pi[j < n ? j : n - 1];
-    }
 #pragma unroll
     for (int mi = m_lo; mi < m_hi; ++mi) {
-      int32_t pa[4];
-#pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const int64_t i = i0 + mi * 16 + Mfma<T>::row(lane, r);
-        pa[r] = pi[i < n ? i : n - 1];
-      }
 #pragma unroll
       for (int ni = 0; ni < 4; ++ni) {
         const int64_t j = j0 + ni * 16 + (lane & 15);
@@ -278,7 +315,7 @@ __global__ void __launch_bounds__(NTHR, 2) skr2k_perm_kernel(Operands o, int64_t
         for (int r = 0; r < 4; ++r) {
           const int64_t i = i0 + mi * 16 + Mfma<T>::row(lane, r);
           const bool valid = i < n && i > j;
-          const int64_t a = pa[r], b = pb[ni];
+          const int64_t a = pa[mi][r], b = pb[ni];
           const bool lower = a > b;
           const double* p = (j == lo) ? cnext + (i < n ? i : n - 1) : src + (lower ? a + b * lds : b + a * lds);
           put(mi, ni, r, *p);
@@ -297,7 +334,7 @@ __global__ void __launch_bounds__(NTHR, 2) skr2k_perm_kernel(Operands o, int64_t
   if constexpr (sizeof(T) == 8) {
     // FP64 accumulates straight onto the source tile, gathered while the
     // first operand chunk is loading
-    tile_mainloop<T>(o, rI, rJ, wm * WT, wn * WT, active, st, acc, [&] {
+    tile_mainloop<T, VEC>(o, rI, rJ, wm * WT, wn * WT, active, st, acc, [&] {
       // by 16-row slices: 16 loads per lane in flight per slice
 #pragma unroll
       for (int mi = 0; mi < 4; ++mi) {
@@ -335,7 +372,7 @@ __global__ void __launch_bounds__(NTHR, 2) skr2k_perm_kernel(Operands o, int64_t
     for (int a = 0; a < 4; ++a)
 #pragma unroll
       for (int b = 0; b < 4; ++b) acc[a][b] = typename Mfma<T>::acc_t{0, 0, 0, 0};
-    tile_mainloop<T>(o, rI, rJ, wm * WT, wn * WT, active, st, acc, [] {});
+    tile_mainloop<T, VEC>(o, rI, rJ, wm * WT, wn * WT, active, st, acc, [] {});
     if (!active) return;
     // two halves of 32 rows: 32 source loads per lane in flight at a time
 #pragma unroll
@@ -364,20 +401,26 @@ __global__ void __launch_bounds__(NTHR, 2) skr2k_perm_kernel(Operands o, int64_t
 
 }  // namespace
 
-// Per-lane operand offsets are 32-bit byte offsets from a chunk's base.
-static bool offsets_fit(int64_t n, int64_t ld) { return (n + (int64_t)KC * ld) * 8 < ((int64_t)1 << 32); }
+// 16-byte copies need 16-byte aligned operand bases, even leading dimensions and
+// a readable padding row when n is odd (rows are copied in pairs).
+static bool vec16_ok(const double* p, int64_t ld, int64_t n) {
+  return ((uintptr_t)p & 15) == 0 && (ld & 1) == 0 && ((n & 1) == 0 || ld > n);
+}
 
 template <typename T>
 static int launch_plain(int64_t n, int64_t k, double alpha, const double* X, int64_t ldx,
                         const double* Y, int64_t ldy, double beta, double* C, int64_t ldc,
                         hipStream_t s) {
   if (n < 2) return 0;
-  if (alpha != 0.0 && k > 0 && !(offsets_fit(n, ldx) && offsets_fit(n, ldy))) return SKF_ENOTIMPL;
   const int64_t nt = (n + TM - 1) / TM;
   const int64_t ntiles = nt * (nt + 1) / 2;
   Operands o{X, Y, ldx, ldy, (alpha == 0.0) ? 0 : k, n};
-  hipLaunchKernelGGL(skr2k_kernel<T>, dim3((unsigned)ntiles), dim3(NTHR), 0, s, o, alpha, beta, C, ldc,
-                     ntiles);
+  if (o.k > 0 && vec16_ok(X, ldx, n) && vec16_ok(Y, ldy, n))
+    hipLaunchKernelGGL((skr2k_kernel<T, 16>), dim3((unsigned)ntiles), dim3(NTHR), 0, s, o, alpha, beta, C, ldc,
+                       ntiles);
+  else
+    hipLaunchKernelGGL((skr2k_kernel<T, 4>), dim3((unsigned)ntiles), dim3(NTHR), 0, s, o, alpha, beta, C, ldc,
+                       ntiles);
   SKF_CHECK_LAUNCH("skr2k");
   return 0;
 }
@@ -399,16 +442,18 @@ int launch_skr2k_perm(int64_t n, int64_t lo, int64_t npairs, const double* src, 
                       const double* Wp, int64_t ldp, const double* cnext, bool f32, hipStream_t s) {
   const int64_t m = n - lo;
   if (m < 2) return 0;
-  if (!offsets_fit(n, ldp)) return SKF_ENOTIMPL;
   const int64_t nt = (m + TM - 1) / TM;
   const int64_t ntiles = nt * (nt + 1) / 2;
   Operands o{Lp, Wp, ldp, ldp, npairs, n};
-  if (f32)
-    hipLaunchKernelGGL(skr2k_perm_kernel<float>, dim3((unsigned)ntiles), dim3(NTHR), 0, s, o, lo, src,
-                       ld_src, dst, ld_dst, pi, cnext, ntiles);
-  else
-    hipLaunchKernelGGL(skr2k_perm_kernel<double>, dim3((unsigned)ntiles), dim3(NTHR), 0, s, o, lo, src,
-                       ld_src, dst, ld_dst, pi, cnext, ntiles);
+  const bool v16 = vec16_ok(Lp, ldp, n) && vec16_ok(Wp, ldp, n);
+  const dim3 grid((unsigned)ntiles), blk(NTHR);
+  if (f32) {
+    if (v16) hipLaunchKernelGGL((skr2k_perm_kernel<float, 16>), grid, blk, 0, s, o, lo, src, ld_src, dst, ld_dst, pi, cnext, ntiles);
+    else hipLaunchKernelGGL((skr2k_perm_kernel<float, 4>), grid, blk, 0, s, o, lo, src, ld_src, dst, ld_dst, pi, cnext, ntiles);
+  } else {
+    if (v16) hipLaunchKernelGGL((skr2k_perm_kernel<double, 16>), grid, blk, 0, s, o, lo, src, ld_src, dst, ld_dst, pi, cnext, ntiles);
+    else hipLaunchKernelGGL((skr2k_perm_kernel<double, 4>), grid, blk, 0, s, o, lo, src, ld_src, dst, ld_dst, pi, cnext, ntiles);
+  }
   SKF_CHECK_LAUNCH("skr2k_perm");
   return 0;
 }
