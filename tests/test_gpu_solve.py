@@ -77,3 +77,27 @@ def test_refine_fp64_and_fp32(skf, oracle_mod, gen, n):
         assert berr <= 1e-13
         Xh = _host(X)
         assert oracle_mod.backward_error(A, Xh, B) <= 2e-13
+
+
+@pytest.mark.parametrize("kappa", [1e4, 1e6])
+def test_refine_fp32_ill_conditioned(skf, oracle_mod, gen, kappa):
+    """A = Q D Q^T with skew 2x2 blocks d_i log-spaced over [1/kappa, 1] and Q
+    orthogonal: FP32-trailing factors are too inexact for plain refinement to
+    contract on such a matrix, and the GMRES-based correction has to take over."""
+    n = 600
+    G = gen.gaussian(n, n, 910)
+    Q, _ = np.linalg.qr(G)
+    d = np.logspace(0.0, -np.log10(kappa), n // 2)
+    D = np.zeros((n, n))
+    for i, v in enumerate(d):
+        D[2 * i, 2 * i + 1], D[2 * i + 1, 2 * i] = v, -v
+    A = Q @ D @ Q.T
+    A = 0.5 * (A - A.T)
+    B = gen.gaussian(n, 16, 911)
+    A0 = skf.to_device_colmajor(A)
+    dA = skf.to_device_colmajor(A)
+    ipiv, T, info = skf.ltlt(dA, prec=skf.PREC_F32_TRAILING)
+    assert info == 0
+    X, st, iters, berr = skf.solve_refine(A0, dA, ipiv, T, skf.to_device_colmajor(B), tol=1e-13, maxit=10)
+    assert st == 0 and berr <= 1e-13, (st, iters, berr)
+    assert oracle_mod.backward_error(A, _host(X), B) <= 2e-13
