@@ -168,7 +168,7 @@ size_t skf_batched_workspace(skf_int batch, const skf_int* n_host);
  * Batched LTL^T + Pfaffian: `batch` independent skew matrices, each of order
  * n <= 512, factored by ONE persistent launch: every workgroup takes matrices
  * from a device work queue (largest first) and factors one at a time in its
- * storage (paired elimination steps, eager interchanges, delayed rank-32
+ * storage (paired elimination steps, eager interchanges, delayed rank-16
  * updates).  A matrix's results do not depend on the rest of the batch.
  *   n_host, lda_host  host arrays [batch]: orders and leading dimensions
  *   A                 device array [batch] of device pointers (overwritten by L, T)
@@ -181,7 +181,8 @@ int skf_ltlt_batched(skf_int batch, const skf_int* n_host, double* const* A, con
                      int32_t* const* ipiv, double* const* T, double* logabs, int* sign, int* info,
                      void* work, size_t lwork, void* stream);
 
-/* log|Pf| and sign of every matrix of the batch (A overwritten). */
+/* log|Pf| and sign of every matrix of the batch.  A is used as scratch: its
+ * trailing parts are overwritten and no factor is left in it. */
 int skf_logpf_batched(skf_int batch, const skf_int* n_host, double* const* A, const skf_int* lda_host,
                       double* logabs, int* sign, int* info, void* work, size_t lwork, void* stream);
 

@@ -109,7 +109,7 @@ size_t batched_workspace_bytes(int64_t batch);
 int batched_max_n();
 int run_batched(int64_t batch, const int64_t* n_host, double* const* A, const int64_t* lda_host,
                 int32_t* const* ipiv, double* const* T, double* logabs, int* sign, int* info, void* work,
-                size_t lwork, hipStream_t s);
+                size_t lwork, bool want_L, hipStream_t s);
 size_t refine_workspace_bytes(int64_t n, int64_t nrhs);
 int run_refine(int64_t n, int64_t nrhs, const double* A0, int64_t lda0, const double* LT, int64_t lda,
                const int32_t* ipiv, const double* T, const double* B, int64_t ldb, double* X, int64_t ldx,
@@ -327,7 +327,7 @@ int skf_ltlt_batched(skf_int batch, const skf_int* n_host, double* const* A, con
                      size_t lwork, void* stream) {
   int rc = check_batched(batch, n_host, A, lda_host, work, lwork);
   if (rc) return rc;
-  return run_batched(batch, n_host, A, lda_host, ipiv, T, logabs, sign, info, work, lwork, (hipStream_t)stream);
+  return run_batched(batch, n_host, A, lda_host, ipiv, T, logabs, sign, info, work, lwork, true, (hipStream_t)stream);
 }
 
 int skf_logpf_batched(skf_int batch, const skf_int* n_host, double* const* A, const skf_int* lda_host,
@@ -335,7 +335,7 @@ int skf_logpf_batched(skf_int batch, const skf_int* n_host, double* const* A, co
   int rc = check_batched(batch, n_host, A, lda_host, work, lwork);
   if (rc) return rc;
   if (batch > 0 && (!logabs || !sign)) return -5;
-  return run_batched(batch, n_host, A, lda_host, nullptr, nullptr, logabs, sign, info, work, lwork,
+  return run_batched(batch, n_host, A, lda_host, nullptr, nullptr, logabs, sign, info, work, lwork, false,
                      (hipStream_t)stream);
 }
 

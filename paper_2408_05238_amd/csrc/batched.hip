@@ -9,9 +9,9 @@
 //   * elimination steps are paired as in the single-matrix path: a pair (k,k+1)
 //     contributes one skew rank-2 term l' w^T - w l'^T to the trailing matrix,
 //     and the next pair's first column is w + alpha' (l - l_0 l');
-//   * updates are delayed over a panel of nb = 32 steps: each new pivot column
+//   * updates are delayed over a panel of nb = 16 steps: each new pivot column
 //     is the stored (panel-start) column plus a skew GEMV with the panel's
-//     pairs (kept in LDS), and the trailing matrix receives one rank-32 update
+//     pairs (kept in LDS), and the trailing matrix receives one rank-16 update
 //     per panel;
 //   * the interchange reads the pivot row/column once and thereby also obtains
 //     the next column, so a step costs one memory round trip plus LDS work.
@@ -27,7 +27,8 @@ namespace skf {
 namespace {
 
 constexpr int BR = 512;   // largest order handled per workgroup
-constexpr int BNP = 16;   // pairs per panel (nb = 32)
+constexpr int BNP = 8;    // pairs per panel (nb = 16): LDS and registers fit two workgroups per CU
+constexpr int kWgPerCu = 2;
 constexpr int BT = 256;   // threads
 constexpr int RPT = BR / BT;
 
@@ -91,7 +92,10 @@ __device__ inline void block_argmax(Smem& sm, double v, int p, double* ov, int* 
   __syncthreads();
 }
 
-__global__ void __launch_bounds__(BT) batched_kernel(BatchArgs a) {
+// kFactors: also leave L in place (the Pfaffian-only form needs neither the
+// finished columns of L nor their row interchanges).
+template <bool kFactors>
+__global__ void __launch_bounds__(BT, kWgPerCu) batched_kernel(BatchArgs a) {
   __shared__ Smem sm;
   const int tid = threadIdx.x;
   for (;;) {
@@ -164,6 +168,7 @@ __global__ void __launch_bounds__(BT) batched_kernel(BatchArgs a) {
         }
         if (p != rr) {
           // row segments left of r (finished columns of L; column k is carried in cur)
+          if (kFactors)
           for (int64_t c = tid; c < k; c += BT) {
             const double x = A[rr + c * ld], y = A[p + c * ld];
             A[rr + c * ld] = y;
@@ -180,11 +185,12 @@ __global__ void __launch_bounds__(BT) batched_kernel(BatchArgs a) {
             }
           }
         }
-        __syncthreads();
-        for (int r = 0; r < RPT; ++r) {
-          const int i = tid + BT * r;
-          if (i > rr && i < n) A[i + rr * ld] = newc[r];
-        }
+        // (column r itself is not stored: it is kept in newc and becomes the
+        // pivot column through cur; the next step overwrites it with L).
+        // Every thread has read alpha = cur[p] before rows r and p of the LDS
+        // arrays are swapped: an LDS-only barrier (global stores stay in flight).
+        __builtin_amdgcn_s_waitcnt(0xC07F);  // lgkmcnt(0); vmcnt and expcnt not waited
+        __builtin_amdgcn_s_barrier();
         if (p != rr && tid < BNP + 2) {
           // LDS rows r and p: pairs, current-pair multipliers, pivot column
           if (tid < BNP) {
@@ -210,12 +216,12 @@ __global__ void __launch_bounds__(BT) batched_kernel(BatchArgs a) {
         for (int r = 0; r < RPT; ++r) {
           const int i = tid + BT * r;
           if (i == rr) {
-            A[i + k * ld] = alpha;
+            if (kFactors) A[i + k * ld] = alpha;
             if (ph == 0) sm.Le[i] = alpha;
             else sm.LW[j][i].x = alpha;
           } else if (i > rr && i < n) {
             const double l = (alpha != 0.0) ? sm.cur[i] / alpha : 0.0;
-            A[i + k * ld] = l;
+            if (kFactors) A[i + k * ld] = l;
             if (ph == 0) sm.Le[i] = l;
             else sm.LW[j][i].x = l;
           }
@@ -231,7 +237,7 @@ __global__ void __launch_bounds__(BT) batched_kernel(BatchArgs a) {
               const double2 u = sm.LW[q][i], x = sm.LW[q][rr];
               corr += u.x * x.y - u.y * x.x;
             }
-            const double g = A[i + rr * ld] + corr;
+            const double g = newc[r] + corr;
             if (ph == 0) {
               sm.cur[i] = g;
             } else {
@@ -251,26 +257,32 @@ __global__ void __launch_bounds__(BT) batched_kernel(BatchArgs a) {
       if (nsteps % 2 == 0 && n - lo >= 3) {
         const int64_t c1 = lo + 1;
         const int64_t m = n - c1;
-        const int64_t nstrip = (m + 7) / 8;
-        // strips of 8 columns; thread handles (strip, row) items
-        for (int64_t sidx = 0; sidx < nstrip; ++sidx) {
-          const int64_t j0 = c1 + sidx * 8;
+        constexpr int SW = 8, NS = 2;  // strip width; strips per pass (their loads in flight together)
+        const int64_t nstrip = (m + SW - 1) / SW;
+        // work items (pass, row): a thread loads all NS x SW elements of its
+        // row in the pass first, then accumulates from LDS, then stores
+        for (int64_t s0 = 0; s0 < nstrip; s0 += NS) {
+          const int64_t j0 = c1 + s0 * SW;
           for (int64_t i = j0 + 1 + tid; i < n; i += BT) {
-            double acc[8];
+            double cv[NS * SW], acc[NS * SW];
 #pragma unroll
-            for (int t = 0; t < 8; ++t) acc[t] = 0.0;
+            for (int t = 0; t < NS * SW; ++t) {
+              const int64_t jj = j0 + t;
+              cv[t] = (jj < i) ? A[i + jj * ld] : 0.0;
+              acc[t] = 0.0;
+            }
             for (int q = 0; q < npairs; ++q) {
               const double2 u = sm.LW[q][i];
 #pragma unroll
-              for (int t = 0; t < 8; ++t) {
+              for (int t = 0; t < NS * SW; ++t) {
                 const double2 v = sm.LW[q][min(j0 + t, (int64_t)BR - 1)];
                 acc[t] += u.x * v.y - u.y * v.x;
               }
             }
 #pragma unroll
-            for (int t = 0; t < 8; ++t) {
+            for (int t = 0; t < NS * SW; ++t) {
               const int64_t jj = j0 + t;
-              if (jj < i) A[i + jj * ld] += acc[t];
+              if (jj < i) A[i + jj * ld] = cv[t] + acc[t];
             }
           }
         }
@@ -345,7 +357,7 @@ struct BatchedWork {
   size_t bytes;
 };
 
-int batched_grid() { return 2 * device_info().num_cus; }
+int batched_grid() { return kWgPerCu * device_info().num_cus; }
 
 BatchedWork batched_carve(void* base, int64_t batch) {
   BatchedWork w{};
@@ -376,7 +388,7 @@ int batched_max_n() { return BR; }
 // of O(batch) words); everything else is asynchronous on `s`.
 int run_batched(int64_t batch, const int64_t* n_host, double* const* A, const int64_t* lda_host,
                 int32_t* const* ipiv, double* const* T, double* logabs, int* sign, int* info, void* work,
-                size_t lwork, hipStream_t s) {
+                size_t lwork, bool want_L, hipStream_t s) {
   BatchedWork w = batched_carve(work, batch);
   if (lwork < w.bytes) return SKF_EWORK;
   if (batch == 0) return 0;
@@ -390,7 +402,10 @@ int run_batched(int64_t batch, const int64_t* n_host, double* const* A, const in
   int rc;
   if ((rc = launch_fill_i32(w.queue, 1, 0, s))) return rc;
   BatchArgs args{batch, w.order, w.nn, w.lda, A, ipiv, T, logabs, sign, info, w.queue, w.ipiv_scratch, w.T_scratch};
-  hipLaunchKernelGGL(batched_kernel, dim3((unsigned)batched_grid()), dim3(BT), 0, s, args);
+  if (want_L)
+    hipLaunchKernelGGL(batched_kernel<true>, dim3((unsigned)batched_grid()), dim3(BT), 0, s, args);
+  else
+    hipLaunchKernelGGL(batched_kernel<false>, dim3((unsigned)batched_grid()), dim3(BT), 0, s, args);
   SKF_CHECK_LAUNCH("batched");
   return 0;
 }

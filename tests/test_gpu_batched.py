@@ -81,3 +81,21 @@ def test_solve_batched(skf, oracle_mod, gen):
     assert _host(info).tolist() == [0, 0, 0]
     for b in range(3):
         assert oracle_mod.backward_error(mats_h[b], _host(Bs[b]), Bs_h[b]) <= 1e-13
+
+
+def test_batched_repeatable_large_mix(skf, gen):
+    """Two launches over the same 300-matrix mix give the same bits (a race
+    between the threads of a workgroup would show here)."""
+    ns = gen.even_sizes(300, 32, 512, 99).tolist()
+    mats_h = [gen.batch_matrix(n, 99, b) for b, n in enumerate(ns)]
+    outs = []
+    for _ in range(2):
+        mats = [skf.to_device_colmajor(A) for A in mats_h]
+        la, sg, info, ipivs, Ts = skf.ltlt_batched(mats)
+        outs.append((_host(la), _host(sg), _host(info), [_host(t) for t in Ts], [_host(m) for m in mats]))
+    a, b = outs
+    assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1]) and np.array_equal(a[2], b[2])
+    assert all(np.array_equal(x, y) for x, y in zip(a[3], b[3]))
+    assert all(np.array_equal(x, y) for x, y in zip(a[4], b[4]))
+    la2, sg2, _, _, _ = skf.ltlt_batched([skf.to_device_colmajor(A) for A in mats_h], with_factors=False)
+    assert np.array_equal(_host(la2), a[0]) and np.array_equal(_host(sg2), a[1])
