@@ -140,7 +140,9 @@ __device__ inline void chunk_issue(const Operands& o, int64_t c, int64_t nh, int
   }
 }
 
-// acc += (+-X) Y^T over one staged chunk (two k-steps of 4); terms past k are zero.
+// acc += (+-X) Y^T over one staged chunk (two k-steps of 4); terms past k are
+// zero.  The mask is an integer AND on the loaded bits, so no per-lane branch
+// separates an LDS read from its use (and a masked value is exactly 0).
 template <typename T>
 __device__ inline void chunk_mma(const Stage& s, int wr, int wc, bool neg, int64_t kvalid,
                                  typename Mfma<T>::acc_t acc[4][4]) {
@@ -148,12 +150,13 @@ __device__ inline void chunk_mma(const Stage& s, int wr, int wc, bool neg, int64
   const int kq = lane >> 4, rr = lane & 15;
 #pragma unroll
   for (int ks = 0; ks < KC / 4; ++ks) {
-    const bool in = 4 * ks + kq < kvalid;
+    const uint64_t keep = (4 * ks + kq < kvalid) ? ~0ull : 0ull;
     T a[4], b[4];
 #pragma unroll
     for (int t = 0; t < 4; ++t) {
       const double va = s.X[4 * ks + kq][wr + 16 * t + rr];
-      a[t] = in ? (T)(neg ? -va : va) : (T)0;
+      const double sa = __longlong_as_double((long long)((uint64_t)__double_as_longlong(neg ? -va : va) & keep));
+      a[t] = (T)sa;
       b[t] = (T)s.Y[4 * ks + kq][wc + 16 * t + rr];
     }
 #pragma unroll
