@@ -412,10 +412,13 @@ __global__ void __launch_bounds__(kPanelThreads) panel_kernel(PanelParams P) {
   const int64_t lo = k0 + P.nsteps;
   for (int c = 0; c < P.nsteps; ++c)
     P.Lbuf[psi + (int64_t)c * n] = (c & 1) ? sm.LW[c >> 1][lane].x : sm.Le[c >> 1][lane];
+  // the pair vectors are the trailing update's operands; row lo is stored as
+  // zero, so the update leaves column lo (the next panel's first column, taken
+  // from cnext as it stands) without products
   for (int q = 0; q < npairs; ++q) {
     const double2 v = sm.LW[q][lane];
-    P.Lp[psi + (int64_t)q * n] = v.x;
-    P.Wp[psi + (int64_t)q * n] = v.y;
+    P.Lp[psi + (int64_t)q * n] = (psi == lo) ? 0.0 : v.x;
+    P.Wp[psi + (int64_t)q * n] = (psi == lo) ? 0.0 : v.y;
   }
   P.pi[psi] = hbm;
   if ((P.nsteps & 1) == 0 && psi >= lo + 1) P.cnext[psi] = cur;

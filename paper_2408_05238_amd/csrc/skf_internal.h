@@ -58,7 +58,8 @@ int launch_skr2k_f32(int64_t n, int64_t k, double alpha, const double* X, int64_
 //     dst[i,j] = (j == lo) ? cnext[i]
 //              : S(pi[i], pi[j]) + sum_q (Lp[i,q] Wp[j,q] - Wp[i,q] Lp[j,q]),
 //   where S(a,b) = src[a,b] if a > b else -src[b,a] (strict lower storage).
-// Lp, Wp: n x npairs (ld = ldp, rows indexed by the current index).
+// Lp, Wp: n x npairs (ld = ldp, rows indexed by the current index); their row
+// lo must be zero (column lo then receives no products and equals cnext).
 int launch_skr2k_perm(int64_t n, int64_t lo, int64_t npairs, const double* src, int64_t ld_src,
                       double* dst, int64_t ld_dst, const int32_t* pi, const double* Lp,
                       const double* Wp, int64_t ldp, const double* cnext, bool f32, hipStream_t s);

@@ -22,6 +22,11 @@
 // (row l%16, k l/16), operand B lane l holds (k l/16, column l%16); accumulator
 // element r of lane l is column l%16 and row l/16 + 4r for
 // v_mfma_f64_16x16x4f64, row 4(l/16) + r for v_mfma_f32_16x16x4f32.
+// Each 16 x 16 block is formed transposed, as Y X^T (A = Y, B = X^T), so that
+// accumulator element r of lane l is C row l%16 and C column row(l, r): one
+// load or store instruction of the source or result tile then covers 16
+// consecutive rows of four columns, i.e. four whole 128-byte lines of the
+// column-major matrix, instead of 32-byte pieces of sixteen lines.
 #include "skf_internal.h"
 
 namespace skf {
@@ -62,6 +67,34 @@ __device__ inline void tri_tile(int64_t x, int64_t* bi, int64_t* bj) {
   while ((r + 1) * (r + 2) / 2 <= x) ++r;
   *bi = r;
   *bj = x - r * (r + 1) / 2;
+}
+
+// Tile of linear index x when the lower triangle of nt x nt tiles is walked in
+// bands of kBand block rows: inside a band, column block by column block, the
+// band's rows at or below the diagonal.  Tiles running together then share a
+// few row and column blocks of the operands, which stay in L2.
+constexpr int64_t kBand = 8;
+__device__ inline void band_tile(int64_t x, int64_t ntiles, int64_t* bi, int64_t* bj) {
+  int64_t nt, r, c0;
+  tri_tile(ntiles - 1, &nt, &c0);
+  ++nt;
+  tri_tile(x, &r, &c0);
+  const int64_t t = (r / kBand) * kBand;     // first block row of the band
+  const int64_t R = min(kBand, nt - t);      // block rows in the band
+  int64_t y = x - t * (t + 1) / 2;           // offset inside the band
+  if (y < t * R) {
+    *bj = y / R;
+    *bi = t + y % R;
+    return;
+  }
+  y -= t * R;
+  int64_t c = 0;
+  while (y >= R - c) {
+    y -= R - c;
+    ++c;
+  }
+  *bj = t + c;
+  *bi = t + c + y;
 }
 
 // Hardware dispatches consecutive workgroups round-robin over the 8 XCDs;
@@ -148,22 +181,26 @@ __device__ inline void chunk_mma(const Stage& s, int wr, int wc, bool neg, int64
                                  typename Mfma<T>::acc_t acc[4][4]) {
   const int lane = threadIdx.x & 63;
   const int kq = lane >> 4, rr = lane & 15;
+  // both k-steps' fragments are read before the first product, so the second
+  // step's LDS latency hides under the first step's products
+  T a[KC / 4][4], b[KC / 4][4];
 #pragma unroll
   for (int ks = 0; ks < KC / 4; ++ks) {
     const uint64_t keep = (4 * ks + kq < kvalid) ? ~0ull : 0ull;
-    T a[4], b[4];
 #pragma unroll
     for (int t = 0; t < 4; ++t) {
       const double va = s.X[4 * ks + kq][wr + 16 * t + rr];
       const double sa = __longlong_as_double((long long)((uint64_t)__double_as_longlong(neg ? -va : va) & keep));
-      a[t] = (T)sa;
-      b[t] = (T)s.Y[4 * ks + kq][wc + 16 * t + rr];
+      a[ks][t] = (T)sa;
+      b[ks][t] = (T)s.Y[4 * ks + kq][wc + 16 * t + rr];
     }
+  }
+#pragma unroll
+  for (int ks = 0; ks < KC / 4; ++ks)
 #pragma unroll
     for (int mi = 0; mi < 4; ++mi)
 #pragma unroll
-      for (int ni = 0; ni < 4; ++ni) acc[mi][ni] = Mfma<T>::op(a[mi], b[ni], acc[mi][ni]);
-  }
+      for (int ni = 0; ni < 4; ++ni) acc[mi][ni] = Mfma<T>::op(b[ks][ni], a[ks][mi], acc[mi][ni]);
 }
 
 // Wait until this wave's copies of the chunk before the last `later` issued
@@ -218,7 +255,7 @@ __global__ void __launch_bounds__(NTHR, 2) skr2k_kernel(Operands o, double alpha
   __shared__ Stage st[NSTG];
   const int64_t n = o.n;
   int64_t bi, bj;
-  tri_tile(xcd_remap(blockIdx.x, ntiles), &bi, &bj);
+  band_tile(xcd_remap(blockIdx.x, ntiles), ntiles, &bi, &bj);
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int wm = wave >> 1, wn = wave & 1;
   const int64_t rI = bi * TM, rJ = bj * TM;
@@ -239,20 +276,18 @@ __global__ void __launch_bounds__(NTHR, 2) skr2k_kernel(Operands o, double alpha
     double cv[4][4];
 #pragma unroll
     for (int ni = 0; ni < 4; ++ni) {
-      const int64_t j = j0 + ni * 16 + (lane & 15);
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
-        const int64_t i = i0 + mi * 16 + Mfma<T>::row(lane, r);
+        const int64_t i = i0 + mi * 16 + (lane & 15), j = j0 + ni * 16 + Mfma<T>::row(lane, r);
         const bool st_ok = i < n && i > j;
         cv[ni][r] = (beta != 0.0) ? C[st_ok ? i + j * ldc : 0] : 0.0;
       }
     }
 #pragma unroll
     for (int ni = 0; ni < 4; ++ni) {
-      const int64_t j = j0 + ni * 16 + (lane & 15);
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
-        const int64_t i = i0 + mi * 16 + Mfma<T>::row(lane, r);
+        const int64_t i = i0 + mi * 16 + (lane & 15), j = j0 + ni * 16 + Mfma<T>::row(lane, r);
         if (i < n && i > j) {
           const double u = alpha * (double)acc[mi][ni][r];
           C[i + j * ldc] = (beta == 0.0) ? u : beta * cv[ni][r] + u;
@@ -265,6 +300,8 @@ __global__ void __launch_bounds__(NTHR, 2) skr2k_kernel(Operands o, double alpha
 // ---------------------------------------------------------------------------
 // Out-of-place trailing update through the panel permutation:
 //   dst[i,j] = (j == lo) ? cnext[i] : S(pi[i], pi[j]) + (P Q^T - Q P^T)[i,j]
+// Column lo starts from cnext and gets no products because row lo of P and Q
+// is zero (the panel stores it so); the epilogue is a plain masked store.
 // ---------------------------------------------------------------------------
 template <typename T, int VEC>
 __global__ void __launch_bounds__(NTHR, 2) skr2k_perm_kernel(Operands o, int64_t lo,
@@ -276,7 +313,7 @@ __global__ void __launch_bounds__(NTHR, 2) skr2k_perm_kernel(Operands o, int64_t
   __shared__ Stage st[NSTG];
   const int64_t n = o.n;
   int64_t bi, bj;
-  tri_tile(xcd_remap(blockIdx.x, ntiles), &bi, &bj);
+  band_tile(xcd_remap(blockIdx.x, ntiles), ntiles, &bi, &bj);
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int wm = wave >> 1, wn = wave & 1;
   const int64_t rI = lo + bi * TM, rJ = lo + bj * TM;
@@ -288,23 +325,23 @@ __global__ void __launch_bounds__(NTHR, 2) skr2k_perm_kernel(Operands o, int64_t
   // reads) are applied after a single wait.
   // The tile's permutation is loaded first and waited for before the first
   // operand copies are issued (a wait issued after them would drain them too).
-  int32_t pb[4], pa[4][4];
+  int32_t pa[4], pb[4][4];
 #pragma unroll
-  for (int ni = 0; ni < 4; ++ni) {
-    const int64_t j = j0 + ni * 16 + (lane & 15);
-    pb[ni] = pi[j < n ? j : n - 1];
+  for (int mi = 0; mi < 4; ++mi) {
+    const int64_t i = i0 + mi * 16 + (lane & 15);
+    pa[mi] = pi[i < n ? i : n - 1];
   }
 #pragma unroll
-  for (int mi = 0; mi < 4; ++mi)
+  for (int ni = 0; ni < 4; ++ni)
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
-      const int64_t i = i0 + mi * 16 + Mfma<T>::row(lane, r);
-      pa[mi][r] = pi[i < n ? i : n - 1];
+      const int64_t j = j0 + ni * 16 + Mfma<T>::row(lane, r);
+      pb[ni][r] = pi[j < n ? j : n - 1];
     }
   {
-    int32_t all = pb[0] ^ pb[1] ^ pb[2] ^ pb[3];
+    int32_t all = pa[0] ^ pa[1] ^ pa[2] ^ pa[3];
 #pragma unroll
-    for (int mi = 0; mi < 4; ++mi) all ^= pa[mi][0] ^ pa[mi][1] ^ pa[mi][2] ^ pa[mi][3];
+    for (int ni = 0; ni < 4; ++ni) all ^= pb[ni][0] ^ pb[ni][1] ^ pb[ni][2] ^ pb[ni][3];
     asm volatile("" ::"v"(all));
   }
   uint64_t ok = 0, neg = 0;
@@ -313,12 +350,11 @@ __global__ void __launch_bounds__(NTHR, 2) skr2k_perm_kernel(Operands o, int64_t
     for (int mi = m_lo; mi < m_hi; ++mi) {
 #pragma unroll
       for (int ni = 0; ni < 4; ++ni) {
-        const int64_t j = j0 + ni * 16 + (lane & 15);
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
-          const int64_t i = i0 + mi * 16 + Mfma<T>::row(lane, r);
+          const int64_t i = i0 + mi * 16 + (lane & 15), j = j0 + ni * 16 + Mfma<T>::row(lane, r);
           const bool valid = i < n && i > j;
-          const int64_t a = pa[mi][r], b = pb[ni];
+          const int64_t a = pa[mi], b = pb[ni][r];
           const bool lower = a > b;
           const double* p = (j == lo) ? cnext + (i < n ? i : n - 1) : src + (lower ? a + b * lds : b + a * lds);
           put(mi, ni, r, *p);
@@ -358,15 +394,10 @@ __global__ void __launch_bounds__(NTHR, 2) skr2k_perm_kernel(Operands o, int64_t
     for (int mi = 0; mi < 4; ++mi)
 #pragma unroll
       for (int ni = 0; ni < 4; ++ni) {
-        const int64_t j = j0 + ni * 16 + (lane & 15);
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
-          const int64_t i = i0 + mi * 16 + Mfma<T>::row(lane, r);
-          if (i < n && i > j) {
-            double x = acc[mi][ni][r];
-            if (j == lo) x = cnext[i];  // column lo is the panel's next column as it stands
-            dst[i + j * ldd] = x;
-          }
+          const int64_t i = i0 + mi * 16 + (lane & 15), j = j0 + ni * 16 + Mfma<T>::row(lane, r);
+          if (i < n && i > j) dst[i + j * ldd] = acc[mi][ni][r];
         }
       }
   } else {
@@ -387,14 +418,12 @@ __global__ void __launch_bounds__(NTHR, 2) skr2k_perm_kernel(Operands o, int64_t
 #pragma unroll
         for (int ni = 0; ni < 4; ++ni) {
           const int mi = 2 * h + mm;
-          const int64_t j = j0 + ni * 16 + (lane & 15);
 #pragma unroll
           for (int r = 0; r < 4; ++r) {
-            const int64_t i = i0 + mi * 16 + Mfma<T>::row(lane, r);
+            const int64_t i = i0 + mi * 16 + (lane & 15), j = j0 + ni * 16 + Mfma<T>::row(lane, r);
             double x = v[mm][ni][r];
             fix(x, (mi * 4 + ni) * 4 + r);
             x += (double)acc[mi][ni][r];
-            if (j == lo) x = cnext[i < n ? i : n - 1];
             if (i < n && i > j) dst[i + j * ldd] = x;
           }
         }
