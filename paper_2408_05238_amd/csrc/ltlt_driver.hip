@@ -65,6 +65,7 @@ static size_t carve(LtltWork* w, char* base, int64_t n, int nb) {
   w->Lbuf = (double*)take(sizeof(double) * (size_t)n * nb);
   w->Lp = (double*)take(sizeof(double) * (size_t)n * (nb / 2));
   w->Wp = (double*)take(sizeof(double) * (size_t)n * (nb / 2));
+  w->NLp = (double*)take(sizeof(double) * (size_t)n * (nb / 2));
   w->cnext = (double*)take(sizeof(double) * (size_t)n);
   w->pis = (int32_t*)take(sizeof(int32_t) * (size_t)std::max<int64_t>(np, 1) * n);
   w->sigma = (int32_t*)take(sizeof(int32_t) * (size_t)std::max<int64_t>(np, 1) * n);
@@ -128,6 +129,7 @@ int run_ltlt(int64_t n, double* A, int64_t lda, int32_t* ipiv, double* T, int pr
     pp.Lbuf = w.Lbuf;
     pp.Lp = w.Lp;
     pp.Wp = w.Wp;
+    pp.NLp = w.NLp;
     pp.pi = w.pis + P * n;
     pp.cnext = w.cnext;
     pp.T = T;
@@ -144,7 +146,7 @@ int run_ltlt(int64_t n, double* A, int64_t lda, int32_t* ipiv, double* T, int pr
     if (n - lo >= 2 && nsteps % 2 == 0) {
       prof_begin(s);
       rc = launch_skr2k_perm(n, lo, nsteps / 2, buf[P % 2], ldb[P % 2], buf[(P + 1) % 2],
-                             ldb[(P + 1) % 2], pp.pi, w.Lp, w.Wp, n, w.cnext,
+                             ldb[(P + 1) % 2], pp.pi, w.Lp, w.Wp, w.NLp, n, w.cnext,
                              prec == SKF_PREC_F32_TRAILING, s);
       if (rc) return rc;
       const double mt = (double)(n - lo);

@@ -417,8 +417,10 @@ __global__ void __launch_bounds__(kPanelThreads) panel_kernel(PanelParams P) {
   // from cnext as it stands) without products
   for (int q = 0; q < npairs; ++q) {
     const double2 v = sm.LW[q][lane];
-    P.Lp[psi + (int64_t)q * n] = (psi == lo) ? 0.0 : v.x;
+    const double lp = (psi == lo) ? 0.0 : v.x;
+    P.Lp[psi + (int64_t)q * n] = lp;
     P.Wp[psi + (int64_t)q * n] = (psi == lo) ? 0.0 : v.y;
+    P.NLp[psi + (int64_t)q * n] = -lp;
   }
   P.pi[psi] = hbm;
   if ((P.nsteps & 1) == 0 && psi >= lo + 1) P.cnext[psi] = cur;

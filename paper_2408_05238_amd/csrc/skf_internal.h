@@ -60,9 +60,12 @@ int launch_skr2k_f32(int64_t n, int64_t k, double alpha, const double* X, int64_
 //   where S(a,b) = src[a,b] if a > b else -src[b,a] (strict lower storage).
 // Lp, Wp: n x npairs (ld = ldp, rows indexed by the current index); their row
 // lo must be zero (column lo then receives no products and equals cnext).
+// NLp: -Lp with the same layout, or null; when given (and npairs is a multiple
+// of 8) the products need no sign changes in registers.
 int launch_skr2k_perm(int64_t n, int64_t lo, int64_t npairs, const double* src, int64_t ld_src,
                       double* dst, int64_t ld_dst, const int32_t* pi, const double* Lp,
-                      const double* Wp, int64_t ldp, const double* cnext, bool f32, hipStream_t s);
+                      const double* Wp, const double* NLp, int64_t ldp, const double* cnext, bool f32,
+                      hipStream_t s);
 
 // ---------------------------------------------------------------------------
 // Blocked factorization pieces
@@ -79,6 +82,7 @@ struct PanelParams {
   double* Lbuf;      // n x nb: L columns of the panel, current order at panel end
   double* Lp;        // n x nb/2: l' of each pair
   double* Wp;        // n x nb/2: w of each pair
+  double* NLp;       // n x nb/2: -l' of each pair
   int32_t* pi;       // n: panel permutation (current index -> src row)
   double* cnext;     // n: first column of the next panel
   double* T;         // global T output
@@ -102,6 +106,7 @@ struct LtltWork {
   double* Lbuf;    // n x nb
   double* Lp;      // n x nb/2
   double* Wp;      // n x nb/2
+  double* NLp;     // n x nb/2
   double* cnext;   // n
   int32_t* pis;    // npanels x n: per-panel permutations
   int32_t* sigma;  // npanels x n: composed later permutations

@@ -109,6 +109,7 @@ __device__ inline int64_t xcd_remap(int64_t b, int64_t nblocks) {
 struct Operands {
   const double* P;
   const double* Q;
+  const double* NP;  // -P (leading dimension ldp) or null: the second half's Y
   int64_t ldp, ldq;  // leading dimensions of P and Q
   int64_t k;         // columns of P and Q; K = 2k
   int64_t n;         // rows (loads clamp to n-1; rows >= n are never stored)
@@ -136,8 +137,9 @@ __device__ inline void dma(const void* g, uint32_t lds) {
 template <int VEC>
 constexpr int kCopiesPerChunk = (VEC == 16) ? 4 : 16;
 
-// Issue chunk c (inner terms 8c.. of P Q^T for c < nh, of (-Q) P^T after) into
-// stage s.  Columns past k are reloaded from a valid column and masked in
+// Issue chunk c (inner terms 8c.. of P Q^T for c < nh, of Q (-P)^T after) into
+// stage s; with o.NP the second half stages -P itself, otherwise P (negated in
+// registers).  Columns past k are reloaded from a valid column and masked in
 // chunk_mma; rows past n are clamped to valid rows (never stored).  VEC = 16
 // needs 16-byte aligned bases, even leading dimensions and, for odd n, one
 // padding row (the launcher checks).
@@ -147,7 +149,7 @@ __device__ inline void chunk_issue(const Operands& o, int64_t c, int64_t nh, int
   const bool h2 = c >= nh;
   const int64_t kk = (h2 ? c - nh : c) * KC;
   const double* Xb = h2 ? o.Q : o.P;
-  const double* Yb = h2 ? o.P : o.Q;
+  const double* Yb = h2 ? (o.NP ? o.NP : o.P) : o.Q;
   const int64_t ldx = h2 ? o.ldq : o.ldp, ldy = h2 ? o.ldp : o.ldq;
 #pragma unroll
   for (int u = 0; u < 2; ++u) {
@@ -176,7 +178,9 @@ __device__ inline void chunk_issue(const Operands& o, int64_t c, int64_t nh, int
 // acc += (+-X) Y^T over one staged chunk (two k-steps of 4); terms past k are
 // zero.  The mask is an integer AND on the loaded bits, so no per-lane branch
 // separates an LDS read from its use (and a masked value is exactly 0).
-template <typename T>
+// kPlain: every term is valid and the staged operands carry their signs, so
+// the fragments go from LDS to the matrix cores untouched.
+template <typename T, bool kPlain>
 __device__ inline void chunk_mma(const Stage& s, int wr, int wc, bool neg, int64_t kvalid,
                                  typename Mfma<T>::acc_t acc[4][4]) {
   const int lane = threadIdx.x & 63;
@@ -190,8 +194,12 @@ __device__ inline void chunk_mma(const Stage& s, int wr, int wc, bool neg, int64
 #pragma unroll
     for (int t = 0; t < 4; ++t) {
       const double va = s.X[4 * ks + kq][wr + 16 * t + rr];
-      const double sa = __longlong_as_double((long long)((uint64_t)__double_as_longlong(neg ? -va : va) & keep));
-      a[ks][t] = (T)sa;
+      if constexpr (kPlain) {
+        a[ks][t] = (T)va;
+      } else {
+        const double sa = __longlong_as_double((long long)((uint64_t)__double_as_longlong(neg ? -va : va) & keep));
+        a[ks][t] = (T)sa;
+      }
       b[ks][t] = (T)s.Y[4 * ks + kq][wc + 16 * t + rr];
     }
   }
@@ -222,7 +230,7 @@ __device__ inline void wait_chunk(int later) {
 // workgroup must call it (it contains barriers); `active` waves do the products.
 // pro() runs once while the first chunks are in flight (the trailing update
 // issues its source-tile gathers there, so the latencies overlap).
-template <typename T, int VEC, typename Pro>
+template <typename T, int VEC, bool kPlain, typename Pro>
 __device__ inline void tile_mainloop(const Operands& o, int64_t rI, int64_t rJ, int wr, int wc, bool active,
                                      Stage* st, typename Mfma<T>::acc_t acc[4][4], Pro&& pro) {
   const int64_t nh = (o.k + KC - 1) / KC;
@@ -241,7 +249,7 @@ __device__ inline void tile_mainloop(const Operands& o, int64_t rI, int64_t rJ, 
     if (c + NSTG - 1 < nch) chunk_issue<VEC>(o, c + NSTG - 1, nh, rI, rJ, st[(c + NSTG - 1) % NSTG]);
     if (active) {
       const int64_t kk = (c >= nh ? c - nh : c) * KC;
-      chunk_mma<T>(st[c % NSTG], wr, wc, c >= nh, o.k - kk, acc);
+      chunk_mma<T, kPlain>(st[c % NSTG], wr, wc, c >= nh && !o.NP, o.k - kk, acc);
     }
   }
 }
@@ -267,7 +275,7 @@ __global__ void __launch_bounds__(NTHR, 2) skr2k_kernel(Operands o, double alpha
   for (int a = 0; a < 4; ++a)
 #pragma unroll
     for (int b = 0; b < 4; ++b) acc[a][b] = typename Mfma<T>::acc_t{0, 0, 0, 0};
-  if (alpha != 0.0) tile_mainloop<T, VEC>(o, rI, rJ, wm * WT, wn * WT, active, st, acc, [] {});
+  if (alpha != 0.0) tile_mainloop<T, VEC, false>(o, rI, rJ, wm * WT, wn * WT, active, st, acc, [] {});
   if (!active) return;
   // Epilogue by 16-row slices: the slice's 16 loads of C are issued together
   // (clamped addresses, no branch around a load), then combined and stored.
@@ -303,7 +311,7 @@ __global__ void __launch_bounds__(NTHR, 2) skr2k_kernel(Operands o, double alpha
 // Column lo starts from cnext and gets no products because row lo of P and Q
 // is zero (the panel stores it so); the epilogue is a plain masked store.
 // ---------------------------------------------------------------------------
-template <typename T, int VEC>
+template <typename T, int VEC, bool kPlain>
 __global__ void __launch_bounds__(NTHR, 2) skr2k_perm_kernel(Operands o, int64_t lo,
                                                              const double* __restrict__ src, int64_t lds,
                                                              double* __restrict__ dst, int64_t ldd,
@@ -373,7 +381,7 @@ __global__ void __launch_bounds__(NTHR, 2) skr2k_perm_kernel(Operands o, int64_t
   if constexpr (sizeof(T) == 8) {
     // FP64 accumulates straight onto the source tile, gathered while the
     // first operand chunk is loading
-    tile_mainloop<T, VEC>(o, rI, rJ, wm * WT, wn * WT, active, st, acc, [&] {
+    tile_mainloop<T, VEC, kPlain>(o, rI, rJ, wm * WT, wn * WT, active, st, acc, [&] {
       // by 16-row slices: 16 loads per lane in flight per slice
 #pragma unroll
       for (int mi = 0; mi < 4; ++mi) {
@@ -406,7 +414,7 @@ __global__ void __launch_bounds__(NTHR, 2) skr2k_perm_kernel(Operands o, int64_t
     for (int a = 0; a < 4; ++a)
 #pragma unroll
       for (int b = 0; b < 4; ++b) acc[a][b] = typename Mfma<T>::acc_t{0, 0, 0, 0};
-    tile_mainloop<T, VEC>(o, rI, rJ, wm * WT, wn * WT, active, st, acc, [] {});
+    tile_mainloop<T, VEC, kPlain>(o, rI, rJ, wm * WT, wn * WT, active, st, acc, [] {});
     if (!active) return;
     // two halves of 32 rows: 32 source loads per lane in flight at a time
 #pragma unroll
@@ -446,7 +454,7 @@ static int launch_plain(int64_t n, int64_t k, double alpha, const double* X, int
   if (n < 2) return 0;
   const int64_t nt = (n + TM - 1) / TM;
   const int64_t ntiles = nt * (nt + 1) / 2;
-  Operands o{X, Y, ldx, ldy, (alpha == 0.0) ? 0 : k, n};
+  Operands o{X, Y, nullptr, ldx, ldy, (alpha == 0.0) ? 0 : k, n};
   if (o.k > 0 && vec16_ok(X, ldx, n) && vec16_ok(Y, ldy, n))
     hipLaunchKernelGGL((skr2k_kernel<T, 16>), dim3((unsigned)ntiles), dim3(NTHR), 0, s, o, alpha, beta, C, ldc,
                        ntiles);
@@ -469,23 +477,36 @@ int launch_skr2k_f32(int64_t n, int64_t k, double alpha, const double* X, int64_
   return launch_plain<float>(n, k, alpha, X, ldx, Y, ldy, beta, C, ldc, s);
 }
 
+template <typename T, int VEC, bool kPlain>
+static void launch_perm_t(const Operands& o, int64_t lo, const double* src, int64_t ld_src, double* dst,
+                          int64_t ld_dst, const int32_t* pi, const double* cnext, int64_t ntiles, hipStream_t s) {
+  hipLaunchKernelGGL((skr2k_perm_kernel<T, VEC, kPlain>), dim3((unsigned)ntiles), dim3(NTHR), 0, s, o, lo, src,
+                     ld_src, dst, ld_dst, pi, cnext, ntiles);
+}
+
+template <typename T>
+static void launch_perm(const Operands& o, bool v16, int64_t lo, const double* src, int64_t ld_src, double* dst,
+                        int64_t ld_dst, const int32_t* pi, const double* cnext, int64_t ntiles, hipStream_t s) {
+  const bool plain = o.NP != nullptr;
+  if (v16 && plain) launch_perm_t<T, 16, true>(o, lo, src, ld_src, dst, ld_dst, pi, cnext, ntiles, s);
+  else if (v16) launch_perm_t<T, 16, false>(o, lo, src, ld_src, dst, ld_dst, pi, cnext, ntiles, s);
+  else launch_perm_t<T, 4, false>(o, lo, src, ld_src, dst, ld_dst, pi, cnext, ntiles, s);
+}
+
 int launch_skr2k_perm(int64_t n, int64_t lo, int64_t npairs, const double* src, int64_t ld_src,
                       double* dst, int64_t ld_dst, const int32_t* pi, const double* Lp,
-                      const double* Wp, int64_t ldp, const double* cnext, bool f32, hipStream_t s) {
+                      const double* Wp, const double* NLp, int64_t ldp, const double* cnext, bool f32,
+                      hipStream_t s) {
   const int64_t m = n - lo;
   if (m < 2) return 0;
   const int64_t nt = (m + TM - 1) / TM;
   const int64_t ntiles = nt * (nt + 1) / 2;
-  Operands o{Lp, Wp, ldp, ldp, npairs, n};
-  const bool v16 = vec16_ok(Lp, ldp, n) && vec16_ok(Wp, ldp, n);
-  const dim3 grid((unsigned)ntiles), blk(NTHR);
-  if (f32) {
-    if (v16) hipLaunchKernelGGL((skr2k_perm_kernel<float, 16>), grid, blk, 0, s, o, lo, src, ld_src, dst, ld_dst, pi, cnext, ntiles);
-    else hipLaunchKernelGGL((skr2k_perm_kernel<float, 4>), grid, blk, 0, s, o, lo, src, ld_src, dst, ld_dst, pi, cnext, ntiles);
-  } else {
-    if (v16) hipLaunchKernelGGL((skr2k_perm_kernel<double, 16>), grid, blk, 0, s, o, lo, src, ld_src, dst, ld_dst, pi, cnext, ntiles);
-    else hipLaunchKernelGGL((skr2k_perm_kernel<double, 4>), grid, blk, 0, s, o, lo, src, ld_src, dst, ld_dst, pi, cnext, ntiles);
-  }
+  const bool v16 = vec16_ok(Lp, ldp, n) && vec16_ok(Wp, ldp, n) && (!NLp || vec16_ok(NLp, ldp, n));
+  // the sign-free inner loop needs -Lp staged and no partial chunk
+  const bool plain = NLp != nullptr && npairs % KC == 0;
+  Operands o{Lp, Wp, plain ? NLp : nullptr, ldp, ldp, npairs, n};
+  if (f32) launch_perm<float>(o, v16, lo, src, ld_src, dst, ld_dst, pi, cnext, ntiles, s);
+  else launch_perm<double>(o, v16, lo, src, ld_src, dst, ld_dst, pi, cnext, ntiles, s);
   SKF_CHECK_LAUNCH("skr2k_perm");
   return 0;
 }
