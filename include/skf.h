@@ -133,10 +133,10 @@ size_t skf_solve_workspace(skf_int n, skf_int nrhs);
 
 /*
  * Solve A X = B with the factors of skf_ltlt: X = P^T L^{-T} T^{-1} L^{-1} P B,
- * in place over B (n x nrhs, ldb >= n).  T is solved through its 2x2 block
- * structure (two independent recurrences dividing by the even T[k]).
+ * in place over B (n x nrhs, ldb >= n).  T is solved by Gaussian elimination
+ * with partial pivoting on the tridiagonal.
  * Numerical outcome (dinfo / return): 0, or k+1 for the first even k with
- * T[k] == 0, or n for odd n (T, hence A, is singular).
+ * T[k] == 0, or n for odd n (T, hence A, is singular; B is then unspecified).
  */
 int skf_solve(skf_int n, skf_int nrhs, const double* LT, skf_int lda, const int32_t* ipiv,
               const double* T, double* B, skf_int ldb, void* work, size_t lwork, int* dinfo,

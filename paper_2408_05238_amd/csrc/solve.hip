@@ -8,8 +8,8 @@
 //   gather Y = P B (workspace);
 //   L^{-1} blocked forward substitution over 64-row blocks: the unit-lower
 //          64 x 64 diagonal blocks are inverted first (all in parallel), then
-//          block I accumulates -L_IJ Y_J as each Y_J is published (a tagged
-//          per-block flag) and finishes with Y_I = inv(L_II) acc;
+//          block I accumulates -L_IJ Y_J as each Y_J is published (tagged
+//          words, no fences) and finishes with Y_I = inv(L_II) acc;
 //   T^{-1} Gaussian elimination with partial pivoting on the tridiagonal
 //          (sequential over rows, one lane per right-hand side);
 //   L^{-T} the same blocked scheme from the last block upwards with the
@@ -27,21 +27,18 @@ constexpr int BS = 64;        // row block of the triangular solves
 constexpr int RC = 16;        // right-hand sides per pass
 constexpr int NT = 256;
 
-__device__ inline uint64_t ld_flag(const uint64_t* p) {
-  return __hip_atomic_load(p, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
+// A block of the solution is published to the other workgroups as tagged
+// words: each double travels as two 64-bit words (tag << 32 | half), written
+// and read with relaxed agent-scope atomics.  A reader takes a word only when it
+// carries the expected tag, so no fence (and no cache write-back or
+// invalidation) is needed, and the data words are their own ready flags.
+__device__ inline uint64_t ld_word(const uint64_t* p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
-__device__ inline void st_flag(uint64_t* p, uint64_t v) {
-  __hip_atomic_store(p, v, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+__device__ inline void st_word(uint64_t* p, uint64_t v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
-// Values published by other workgroups are read and written at agent scope.
-__device__ inline double ld_agent(const double* p) {
-  return __longlong_as_double((long long)__hip_atomic_load(reinterpret_cast<const uint64_t*>(p), __ATOMIC_RELAXED,
-                                                           __HIP_MEMORY_SCOPE_AGENT));
-}
-__device__ inline void st_agent(double* p, double v) {
-  __hip_atomic_store(reinterpret_cast<uint64_t*>(p), (uint64_t)__double_as_longlong(v), __ATOMIC_RELAXED,
-                     __HIP_MEMORY_SCOPE_AGENT);
-}
+__device__ inline uint64_t tagged(uint32_t tag, uint32_t half) { return ((uint64_t)tag << 32) | half; }
 constexpr uint64_t kWaitTicks = 200000000ull;  // 2 s of the 100 MHz counter
 
 // L element (i, j), i > j, from the factored array.
@@ -64,8 +61,12 @@ __global__ void __launch_bounds__(256) perm_kernel(int64_t n, const int32_t* __r
     __syncthreads();
     for (int64_t s = lo + threadIdx.x; s < hi; s += blockDim.x) sp[s - lo] = ipiv[s];
     __syncthreads();
-    for (int64_t s = hi - 1; s >= lo; --s)
-      if (s < j && sp[s - lo] == pos) pos = s;
+    // the scan order matters (the last match wins), the LDS reads do not: unrolled
+    // so that they issue in batches ahead of the compare chain
+    const int64_t top = min(hi, j);  // only interchanges before j count
+#pragma unroll 16
+    for (int64_t s = top - 1; s >= lo; --s)
+      if (sp[s - lo] == pos) pos = s;
   }
   if (j < n) perm[j] = (int32_t)pos;
 }
@@ -116,12 +117,37 @@ __global__ void inv_diag_kernel(int64_t n, const double* __restrict__ LT, int64_
 
 // Blocked substitution with L (forward, kTrans = false) or L^T (backward, kTrans = true)
 // on Y (n x RC, in place).  Workgroup b handles row block I = b (forward) or
-// I = nb-1-b (backward); flags[I] carries `tag` once Y_I is final.
+// I = nb-1-b (backward) and publishes Y_I in `pub` (tagged words, value (r, c)
+// of block I at pub + 2 ((I RC + c) BS + r)) once it is final.  The L block
+// of the next J is fetched into registers (16 loads per thread from clamped
+// addresses, masks applied afterwards) while the current one is waited for and
+// multiplied, and lands in the other half of a double-buffered LDS tile.
+constexpr int kLdPerThread = BS * BS / NT;  // 16
+
+// acc[i][c] -= sum_j Lb[i][j] y[j][c] over the 64 x 16 block: thread (row i =
+// tid % 64, column group g = tid / 64) keeps four sums in registers; the y
+// reads are the same address across a wave (LDS broadcast).
+__device__ inline void block_mv(const double (&Lb)[BS][BS + 1], const double (&y)[BS][RC + 1],
+                                double (&acc)[BS][RC + 1], int tid) {
+  static_assert(NT == BS * (RC / 4), "one thread per row and group of four columns");
+  const int i = tid % BS, g = tid / BS;
+  double s4[4] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll 8
+  for (int j = 0; j < BS; ++j) {
+    const double l = Lb[i][j];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) s4[q] += l * y[j][4 * g + q];
+  }
+#pragma unroll
+  for (int q = 0; q < 4; ++q) acc[i][4 * g + q] -= s4[q];
+}
+
 template <bool kTrans>
 __global__ void __launch_bounds__(NT) trsv_kernel(int64_t n, const double* __restrict__ LT, int64_t lda,
                                                   const double* __restrict__ Dinv, double* __restrict__ Y,
-                                                  uint64_t* __restrict__ flags, uint64_t tag, int* status) {
-  __shared__ double Lb[BS][BS + 1];
+                                                  uint64_t* __restrict__ pub, uint32_t tag, int* status) {
+  __shared__ double Lb[2][BS][BS + 1];
+  __shared__ double Db[BS][BS + 1];  // inv(L_II), or its transpose (backward)
   __shared__ double yJ[BS][RC + 1];
   __shared__ double acc[BS][RC + 1];
   __shared__ int stop;
@@ -135,132 +161,324 @@ __global__ void __launch_bounds__(NT) trsv_kernel(int64_t n, const double* __res
     acc[i][c] = (i < bs) ? Y[r0 + i + (int64_t)c * n] : 0.0;
   }
   if (tid == 0) stop = 0;
-  __syncthreads();
-  // contributions of the other blocks J (J < I forward, J > I backward), in order of readiness
+  {
+    // the inverse diagonal block is needed only at the end: fetched now, off the chain
+    const double* D = Dinv + I * BS * BS;
+    for (int t = tid; t < BS * BS; t += NT) {
+      const int i = t % BS, j = t / BS;
+      Db[i][j] = kTrans ? D[j + i * BS] : D[i + j * BS];
+    }
+  }
+  // element e = tid + NT q of a block: (i, j) = (e % BS, e / BS) forward, (e / BS, e % BS)
+  // backward, so consecutive threads walk down a stored column of L either way
+  auto elem = [&](int q, int* i, int* j) {
+    const int e = tid + NT * q;
+    *i = kTrans ? e / BS : e % BS;
+    *j = kTrans ? e % BS : e / BS;
+  };
+  // L(a, b) (a > b) sits at LT[a + (b - 1) lda] for b >= 1; column 0 of L is e_0
+  auto fetch = [&](int64_t J, double (&v)[kLdPerThread]) {
+    const int64_t c0 = J * BS;
+#pragma unroll
+    for (int q = 0; q < kLdPerThread; ++q) {
+      int i, j;
+      elem(q, &i, &j);
+      const int64_t a = kTrans ? c0 + j : r0 + i, b = kTrans ? r0 + i : c0 + j;
+      const bool ok = a < n && b >= 1;
+      v[q] = LT[ok ? a + (b - 1) * lda : 0];
+    }
+  };
+  auto put = [&](int buf, int64_t J, const double (&v)[kLdPerThread]) {
+    const int64_t c0 = J * BS;
+#pragma unroll
+    for (int q = 0; q < kLdPerThread; ++q) {
+      int i, j;
+      elem(q, &i, &j);
+      const int64_t a = kTrans ? c0 + j : r0 + i, b = kTrans ? r0 + i : c0 + j;
+      Lb[buf][i][j] = (a < n && b >= 1) ? v[q] : 0.0;
+    }
+  };
+  // contributions of the other blocks J (J < I forward, J > I backward), nearest-ready first
+  const int64_t count = kTrans ? nb - 1 - I : I;
   const int64_t jfirst = kTrans ? nb - 1 : 0;
   const int64_t jstep = kTrans ? -1 : 1;
-  for (int64_t J = jfirst; kTrans ? (J > I) : (J < I); J += jstep) {
-    const int64_t c0 = J * BS;
-    const int cs = (int)min((int64_t)BS, n - c0);
-    // block of L (rows I, cols J) forward, or of L^T = (L rows J, cols I)^T backward
-    for (int t = tid; t < BS * BS; t += NT) {
-      // consecutive threads walk down a stored column of L in both orientations
-      const int i = kTrans ? t / BS : t % BS, j = kTrans ? t % BS : t / BS;
-      double v = 0.0;
-      if (!kTrans) {
-        if (i < bs && j < cs) v = Lij(LT, lda, r0 + i, c0 + j);
-      } else {
-        if (i < bs && j < cs) v = Lij(LT, lda, c0 + j, r0 + i);
-      }
-      Lb[i][j] = v;
-    }
-    if (tid == 0) {
-      const uint64_t t0 = wall_clock64();
-      while (ld_flag(flags + J) != tag) {
-        if (wall_clock64() - t0 > kWaitTicks) {
-          stop = 1;
-          break;
+  double v[kLdPerThread];
+  if (count > 0) {
+    fetch(jfirst, v);
+    put(0, jfirst, v);
+  }
+  __syncthreads();
+  for (int64_t idx = 0; idx < count; ++idx) {
+    const int64_t J = jfirst + idx * jstep;
+    const int buf = (int)(idx & 1);
+    const bool more = idx + 1 < count;
+    if (more) fetch(J + jstep, v);
+    {
+      // Y_J: thread t takes values e = t + NT q, (j, c) = (e % BS, e / BS); every
+      // word is reloaded until all carry this solve's tag (bounded wait)
+      const uint64_t* pj = pub + (size_t)J * RC * BS * 2;
+      uint64_t w[4][2];
+      auto load_all = [&]() {
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          const int e = tid + NT * q;
+          w[q][0] = ld_word(pj + 2 * e);
+          w[q][1] = ld_word(pj + 2 * e + 1);
         }
+      };
+      load_all();
+      uint64_t t0 = 0;
+      for (int it = 0;; ++it) {
+        bool ok = true;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) ok &= ((uint32_t)(w[q][0] >> 32) == tag) & ((uint32_t)(w[q][1] >> 32) == tag);
+        if (ok) break;
+        if ((it & 31) == 0) {
+          const uint64_t now = wall_clock64();
+          if (it == 0) t0 = now;
+          else if (now - t0 > kWaitTicks) {
+            stop = 1;
+            break;
+          }
+        }
+        load_all();
+      }
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int e = tid + NT * q;
+        yJ[e % BS][e / BS] = __longlong_as_double((long long)((w[q][0] << 32) | (uint32_t)w[q][1]));
       }
     }
     __syncthreads();
     if (stop) break;
-    for (int t = tid; t < BS * RC; t += NT) {
-      const int j = t % BS, c = t / BS;
-      yJ[j][c] = (j < cs) ? ld_agent(Y + c0 + j + (int64_t)c * n) : 0.0;
-    }
-    __syncthreads();
-    for (int t = tid; t < BS * RC; t += NT) {
-      const int i = t % BS, c = t / BS;
-      double s = 0.0;
-#pragma unroll 8
-      for (int j = 0; j < BS; ++j) s += Lb[i][j] * yJ[j][c];
-      acc[i][c] -= s;
-    }
-    __syncthreads();
+    block_mv(Lb[buf], yJ, acc, tid);
+    // the other buffer was last read before this iteration's barriers
+    if (more) put(buf ^ 1, J + jstep, v);
   }
+  __syncthreads();
   if (stop) {
     if (tid == 0) atomicMin(status, SKF_ETIMEOUT);
-    if (tid == 0) st_flag(flags + I, tag);  // let dependants finish (their result is void)
+    // publish anyway so that dependants finish (their result is void)
+    for (int e = tid; e < BS * RC; e += NT) {
+      st_word(pub + (size_t)I * RC * BS * 2 + 2 * e, tagged(tag, 0));
+      st_word(pub + (size_t)I * RC * BS * 2 + 2 * e + 1, tagged(tag, 0));
+    }
     return;
   }
   // Y_I = inv(L_II) acc  (forward)  or  inv(L_II)^T acc  (backward)
-  const double* D = Dinv + I * BS * BS;
-  for (int t = tid; t < BS * BS; t += NT) {
-    const int i = t % BS, j = t / BS;
-    Lb[i][j] = kTrans ? D[j + i * BS] : D[i + j * BS];
-  }
-  __syncthreads();
-  for (int t = tid; t < BS * RC; t += NT) {
-    const int i = t % BS, c = t / BS;
-    double s = 0.0;
+  {
+    // thread (row i, column group g) forms four results; acc is read-only here
+    const int i = tid % BS, g = tid / BS;
+    double s4[4] = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll 8
-    for (int j = 0; j < BS; ++j) s += Lb[i][j] * acc[j][c];
-    if (i < bs) st_agent(Y + r0 + i + (int64_t)c * n, s);
-  }
-  __syncthreads();
-  if (tid == 0) {
-    __threadfence();
-    st_flag(flags + I, tag);
+    for (int j = 0; j < BS; ++j) {
+      const double l = Db[i][j];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) s4[q] += l * acc[j][4 * g + q];
+    }
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int c = 4 * g + q;
+      const uint64_t b = (uint64_t)__double_as_longlong(s4[q]);
+      uint64_t* pw = pub + 2 * (((size_t)I * RC + c) * BS + i);
+      st_word(pw, tagged(tag, (uint32_t)(b >> 32)));
+      st_word(pw + 1, tagged(tag, (uint32_t)b));
+      if (i < bs) Y[r0 + i + (int64_t)c * n] = s4[q];
+    }
   }
 }
 
 // T^{-1} on Y (n x RC) by Gaussian elimination with partial pivoting on the
-// tridiagonal (sub T[i], super -T[i], zero diagonal); lane c owns column c.
-// Rows are streamed; the working bands live in a per-column scratch.
-__global__ void tridiag_kernel(int64_t n, int nr, const double* __restrict__ T, double* __restrict__ Y,
-                               double* __restrict__ scratch, int* status) {
-  const int c = threadIdx.x;
-  if (c >= RC) return;
-  double* y = Y + (int64_t)c * n;
-  double* dd = scratch + (int64_t)c * 3 * n;  // diagonal, super, second super of U
-  double* du = dd + n;
-  double* du2 = du + n;
-  // elimination
-  double d_i = 0.0;                 // current diagonal entry of row i
-  double u_i = (n > 1) ? -T[0] : 0.0;  // current super entry of row i
-  double y_i = y[0];
-  int sing = 0;
-  for (int64_t i = 0; i + 1 < n; ++i) {
-    const double l = T[i];                      // sub entry: row i+1, column i
-    const double d_next = 0.0;                  // row i+1 diagonal
-    const double u_next = (i + 2 < n) ? -T[i + 1] : 0.0;  // row i+1 super
-    const double y_next = y[i + 1];
-    if (fabs(d_i) >= fabs(l)) {
-      if (d_i == 0.0) {
-        sing = (int)(i + 1);
-        break;
+// tridiagonal (sub T[i], super -T[i], zero diagonal), taken two rows at a time.
+// With a zero diagonal the elimination has a fixed shape: entering an even row
+// the running diagonal is exactly 0, so that row is always interchanged with
+// the next (its multiplier is 0) and the running diagonal of the odd row is the
+// previous super entry s; the odd row keeps (|s| >= |T[o]|) or interchanges,
+// and leaves the running diagonal exactly 0 again.  Every row of U therefore
+// has a zero first super entry, only 1/diag and the second super entry are
+// kept, and the back substitution is two interleaved chains x_i <- x_{i+2}.
+// The arithmetic on the nonzero entries is that of the row-by-row elimination,
+// with each division replaced by a product with the reciprocal.
+// The pivot choices depend on T only, so lane c of wave 0 carries column c and
+// all lanes take the same choices.  Inputs are staged through LDS in chunks and
+// results leave through LDS: waves 1..3 fetch chunk k+1 and write chunk k-1 out
+// while wave 0 works on chunk k.  The bands go to `band` (2n doubles).
+constexpr int TR = 128;  // rows per chunk (even)
+
+// 1/x from the hardware estimate refined by two Newton steps (each roughly
+// squares the relative error), a few ulps at most.
+__device__ inline double recip(double x) {
+  double r = __builtin_amdgcn_rcp(x);
+  r = fma(r, fma(-x, r, 1.0), r);
+  r = fma(r, fma(-x, r, 1.0), r);
+  return r;
+}
+
+struct TriBuf {
+  double T[2][TR + 2];        // T[i0 .. i0 + TR + 1] (elimination)
+  double in[2][RC][TR + 2];   // right-hand sides, rows i0 .. i0 + TR + 1 / the chunk (back substitution)
+  double out[2][RC][TR];      // results of the chunk
+  double band[2][2][TR];      // 1/diag and second super entry of U, rows of the chunk
+};
+
+__global__ void __launch_bounds__(256) tridiag_kernel(int64_t n, const double* __restrict__ T,
+                                                      double* __restrict__ Y, double* __restrict__ band) {
+  __shared__ TriBuf sb;
+  __shared__ int s_sing;
+  const int tid = threadIdx.x;
+  const int c = tid;                 // column of a working lane (tid < RC)
+  const bool work = tid < RC;
+  const int ht = tid - 64;           // helper thread index (waves 1..3), 192 of them
+  // ---------------- elimination, rows 0 .. n-2 (n even) ----------------
+  const int64_t nchf = (n - 1 + TR - 1) / TR;
+  auto fwd_load = [&](int b, int64_t i0) {
+    for (int t = ht; t < TR + 2; t += 192) {
+      const int64_t i = i0 + t;
+      sb.T[b][t] = (i <= n - 2) ? T[i] : 0.0;
+    }
+    for (int t = ht; t < RC * (TR + 2); t += 192) {
+      const int cc = t / (TR + 2), r = t % (TR + 2);
+      const int64_t i = i0 + r;
+      sb.in[b][cc][r] = (i <= n - 1) ? Y[i + (int64_t)cc * n] : 0.0;
+    }
+  };
+  auto fwd_flush = [&](int b, int64_t i0) {  // rows i0 .. min(i0 + TR, n - 1) - 1
+    const int rows = (int)min((int64_t)TR, n - 1 - i0);
+    for (int t = ht; t < RC * TR; t += 192) {
+      const int cc = t / TR, r = t % TR;
+      if (r < rows) Y[i0 + r + (int64_t)cc * n] = sb.out[b][cc][r];
+    }
+    for (int t = ht; t < 2 * TR; t += 192) {
+      const int q = t / TR, r = t % TR;
+      if (r < rows) band[(int64_t)q * n + i0 + r] = sb.band[b][q][r];
+    }
+  };
+  double u = (n > 1) ? -T[0] : 0.0;   // super entry carried into the next even row
+  double ys = work ? Y[(int64_t)c * n] : 0.0;  // right-hand side carried with the running row
+  double sd = 0.0;                    // running diagonal entering the last row
+  int64_t sing = 0;                   // uniform across the working lanes
+  if (ht >= 0) fwd_load(0, 0);
+  __syncthreads();
+  for (int64_t ch = 0; ch < nchf; ++ch) {
+    const int cur = (int)(ch & 1);
+    const int64_t i0 = ch * TR;
+    if (ht >= 0) {
+      if (ch >= 1) fwd_flush(cur ^ 1, i0 - TR);
+      if (ch + 1 < nchf) fwd_load(cur ^ 1, i0 + TR);
+    }
+    if (work && !sing) {
+      const int rows = (int)min((int64_t)TR, n - 1 - i0);
+      // the pair's operands are read one pair ahead from the padded buffers
+      // (indices clamped; no read sits behind a branch or on the chain)
+      const double* tb = sb.T[cur];
+      const double* yb = sb.in[cur][c];
+      double le = tb[0], lo = tb[1], t2 = tb[2], ye = yb[1], yo = yb[2];
+      for (int r = 0; r < rows; r += 2) {
+        const int rn = min(r + 2, TR - 2);
+        const double lo_n = tb[rn + 1], t2_n = tb[rn + 2], ye_n = yb[rn + 1], yo_n = yb[rn + 2];
+        // even row e: running diagonal 0, always interchanged with row e+1
+        const int64_t e = i0 + r;
+        if (le == 0.0) {
+          sing = e + 1;
+          break;
+        }
+        sb.out[cur][c][r] = ye;
+        sb.band[cur][0][r] = recip(le);  // every working lane stores the same value
+        sb.band[cur][1][r] = (e + 2 < n) ? -lo : 0.0;
+        const double s = u;  // running diagonal of the odd row
+        if (r + 1 >= rows) {  // e = n-2: the odd row is the last row
+          sd = s;
+          break;
+        }
+        // odd row o = e+1: keep it or interchange it with row o+1
+        const int64_t o = e + 1;
+        const double un = (o + 2 < n) ? -t2 : 0.0;
+        const bool keep = fabs(s) >= fabs(lo);
+        if ((keep ? s : lo) == 0.0) {
+          sing = o + 1;
+          break;
+        }
+        const double rs = recip(s), rl = recip(lo);
+        const double f = keep ? lo * rs : s * rl;
+        sb.out[cur][c][r + 1] = keep ? ys : yo;
+        sb.band[cur][0][r + 1] = keep ? rs : rl;
+        sb.band[cur][1][r + 1] = keep ? 0.0 : un;
+        u = keep ? un : -(s * rl) * un;
+        ys = keep ? yo - f * ys : ys - f * yo;
+        le = t2;
+        lo = lo_n;
+        t2 = t2_n;
+        ye = ye_n;
+        yo = yo_n;
       }
-      const double f = l / d_i;
-      dd[i] = d_i;
-      du[i] = u_i;
-      du2[i] = 0.0;
-      y[i] = y_i;
-      d_i = d_next - f * u_i;
-      u_i = u_next;
-      y_i = y_next - f * y_i;
-    } else {
-      const double f = d_i / l;
-      dd[i] = l;
-      du[i] = d_next;
-      du2[i] = u_next;
-      y[i] = y_next;
-      d_i = u_i - f * d_next;
-      u_i = -f * u_next;
-      y_i = y_i - f * y_next;
+    }
+    __syncthreads();
+  }
+  if (ht >= 0 && nchf >= 1) fwd_flush((int)((nchf - 1) & 1), (nchf - 1) * TR);
+  if (work && !sing) {  // last row n-1: diagonal sd
+    if (sd == 0.0) sing = n;
+    else {
+      if (c == 0) {
+        band[n - 1] = recip(sd);
+        band[2 * n - 1] = 0.0;
+      }
+      Y[n - 1 + (int64_t)c * n] = ys;
     }
   }
-  if (!sing) {
-    if (d_i == 0.0) sing = (int)n;
-    dd[n - 1] = d_i;
-    y[n - 1] = y_i;
+  if (tid == 0) s_sing = sing ? 1 : 0;
+  __syncthreads();  // also orders the global writes above before the reads below
+  if (s_sing) return;  // singular T: the info word reports it from T
+  // ---------------- back substitution, rows n-1 .. 0 ----------------
+  const int64_t nchb = (n + TR - 1) / TR;
+  auto bwd_load = [&](int b, int64_t i1) {  // rows i1 - TR .. i1 - 1 (negative rows padded)
+    for (int t = ht; t < RC * TR; t += 192) {
+      const int cc = t / TR, r = t % TR;
+      const int64_t i = i1 - TR + r;
+      sb.in[b][cc][r] = (i >= 0) ? Y[i + (int64_t)cc * n] : 0.0;
+    }
+    for (int t = ht; t < 2 * TR; t += 192) {
+      const int q = t / TR, r = t % TR;
+      const int64_t i = i1 - TR + r;
+      sb.band[b][q][r] = (i >= 0) ? band[(int64_t)q * n + i] : 0.0;
+    }
+  };
+  auto bwd_flush = [&](int b, int64_t i1) {
+    for (int t = ht; t < RC * TR; t += 192) {
+      const int cc = t / TR, r = t % TR;
+      const int64_t i = i1 - TR + r;
+      if (i >= 0) Y[i + (int64_t)cc * n] = sb.out[b][cc][r];
+    }
+  };
+  double x1 = 0.0, x2 = 0.0;  // solution at rows i+1, i+2
+  if (ht >= 0) bwd_load(0, n);
+  __syncthreads();
+  for (int64_t ch = 0; ch < nchb; ++ch) {
+    const int cur = (int)(ch & 1);
+    const int64_t i1 = n - ch * TR;
+    if (ht >= 0) {
+      if (ch >= 1) bwd_flush(cur ^ 1, i1 + TR);
+      if (ch + 1 < nchb) bwd_load(cur ^ 1, i1 - TR);
+    }
+    if (work) {
+      const int rlo = (int)max((int64_t)0, TR - i1);  // rows below 0 are padding
+      // x_i = (y_i - du2_i x_{i+2}) / d_i  (the first super entry of U is 0);
+      // the row's operands are read one row ahead
+      double a = sb.in[cur][c][TR - 1], b1 = sb.band[cur][1][TR - 1], b0 = sb.band[cur][0][TR - 1];
+      for (int r = TR - 1; r >= rlo; --r) {
+        const int rn = max(r - 1, 0);
+        const double a_n = sb.in[cur][c][rn], b1_n = sb.band[cur][1][rn], b0_n = sb.band[cur][0][rn];
+        const double v = (a - b1 * x2) * b0;
+        sb.out[cur][c][r] = v;
+        x2 = x1;
+        x1 = v;
+        a = a_n;
+        b1 = b1_n;
+        b0 = b0_n;
+      }
+    }
+    __syncthreads();
   }
-  if (sing) return;  // singular T: the info word reports it from T
-  // back substitution
-  y[n - 1] = y[n - 1] / dd[n - 1];
-  if (n >= 2) y[n - 2] = (y[n - 2] - du[n - 2] * y[n - 1]) / dd[n - 2];
-  for (int64_t i = n - 3; i >= 0; --i) y[i] = (y[i] - du[i] * y[i + 1] - du2[i] * y[i + 2]) / dd[i];
-  (void)nr;
+  if (ht >= 0) bwd_flush((int)((nchb - 1) & 1), n - (nchb - 1) * TR);
 }
 
 // info = 1 + first even k with T[k] == 0, or n for odd n, or 0.
@@ -289,13 +507,14 @@ __global__ void solve_info_kernel(int64_t n, const double* __restrict__ T, const
 
 }  // namespace
 
-// Workspace: perm (n int32) | Dinv (nb*BS*BS) | Y (n*RC) | tri scratch (3*n*RC) | flags (2*nb) | status
+// Workspace: perm (n int32) | Dinv (nb*BS*BS) | Y (n*RC) | tridiagonal bands (2*n) | published blocks
+// (2*nb*BS*RC words) | status
 struct SolveWork {
   int32_t* perm;
   double* Dinv;
   double* Y;
   double* tri;
-  uint64_t* flags;
+  uint64_t* pub;
   int* status;
   size_t bytes;
 };
@@ -312,8 +531,8 @@ static SolveWork solve_carve(void* base, int64_t n) {
   w.perm = (int32_t*)take(sizeof(int32_t) * (size_t)std::max<int64_t>(n, 1));
   w.Dinv = (double*)take(sizeof(double) * (size_t)std::max<int64_t>(nb, 1) * BS * BS);
   w.Y = (double*)take(sizeof(double) * (size_t)std::max<int64_t>(n, 1) * RC);
-  w.tri = (double*)take(sizeof(double) * (size_t)std::max<int64_t>(n, 1) * 3 * RC);
-  w.flags = (uint64_t*)take(sizeof(uint64_t) * (size_t)std::max<int64_t>(nb, 1) * 2);
+  w.tri = (double*)take(sizeof(double) * (size_t)std::max<int64_t>(n, 1) * 2);
+  w.pub = (uint64_t*)take(sizeof(uint64_t) * (size_t)std::max<int64_t>(nb, 1) * BS * RC * 2);
   w.status = (int*)take(256);
   w.bytes = off;
   return w;
@@ -339,22 +558,22 @@ int run_solve(int64_t n, int64_t nrhs, const double* LT, int64_t lda, const int3
     SKF_CHECK_LAUNCH("perm");
     hipLaunchKernelGGL(inv_diag_kernel, dim3((unsigned)nb), dim3(BS), 0, s, n, LT, lda, w.Dinv);
     SKF_CHECK_LAUNCH("inv_diag");
-    if ((rc = launch_fill_u64(w.flags, (size_t)nb * 2, 0, s))) return rc;
+    if ((rc = launch_fill_u64(w.pub, (size_t)nb * BS * RC * 2, 0, s))) return rc;
     unsigned gx = (unsigned)std::min<int64_t>((n + 255) / 256, 1024);
-    uint64_t tag = 0;
+    uint32_t tag = 0;
     for (int64_t c0 = 0; c0 < nrhs; c0 += RC) {
       const int nr = (int)std::min<int64_t>(RC, nrhs - c0);
       hipLaunchKernelGGL(gather_kernel, dim3(gx, RC), dim3(256), 0, s, n, nr, w.perm, B + c0 * ldb, ldb, w.Y);
       SKF_CHECK_LAUNCH("gather");
       ++tag;
       hipLaunchKernelGGL(trsv_kernel<false>, dim3((unsigned)nb), dim3(NT), 0, s, n, LT, lda, w.Dinv, w.Y,
-                         w.flags, tag, w.status);
+                         w.pub, tag, w.status);
       SKF_CHECK_LAUNCH("trsv fwd");
-      hipLaunchKernelGGL(tridiag_kernel, dim3(1), dim3(64), 0, s, n, nr, T, w.Y, w.tri, w.status);
+      hipLaunchKernelGGL(tridiag_kernel, dim3(1), dim3(256), 0, s, n, T, w.Y, w.tri);
       SKF_CHECK_LAUNCH("tridiag");
       ++tag;
       hipLaunchKernelGGL(trsv_kernel<true>, dim3((unsigned)nb), dim3(NT), 0, s, n, LT, lda, w.Dinv, w.Y,
-                         w.flags + nb, tag, w.status);
+                         w.pub, tag, w.status);
       SKF_CHECK_LAUNCH("trsv bwd");
       hipLaunchKernelGGL(scatter_kernel, dim3(gx, RC), dim3(256), 0, s, n, nr, w.perm, w.Y, B + c0 * ldb, ldb);
       SKF_CHECK_LAUNCH("scatter");
