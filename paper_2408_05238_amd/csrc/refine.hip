@@ -35,66 +35,101 @@ constexpr int RC = 16;
 constexpr int NT = 256;
 
 // R[:, c0:c0+nr] = B - S X (rows of block I = blockIdx.x); optionally also the
-// absolute row sums of S (||A0||_inf = max of them).
+// absolute row sums of S (||A0||_inf = max of them).  The next block of S and
+// of X are fetched into registers (clamped addresses, masks and signs applied
+// afterwards) while the current one is multiplied, into the other half of a
+// double-buffered LDS tile; the 64 x 16 product keeps four sums per thread.
+constexpr int kPer = BS * BS / NT;  // S elements per thread and block (16)
+constexpr int kPerX = BS * RC / NT;  // X elements per thread and block (4)
+
 __global__ void __launch_bounds__(NT) residual_kernel(int64_t n, int nr, const double* __restrict__ A0, int64_t lda,
                                                       const double* __restrict__ X, int64_t ldx,
                                                       const double* __restrict__ B, int64_t ldb,
                                                       double* __restrict__ R, int64_t ldr,
                                                       double* __restrict__ rowabs) {
-  __shared__ double Ab[BS][BS + 1];
-  __shared__ double xs[BS][RC + 1];
-  __shared__ double acc[BS][RC + 1];
-  __shared__ double ra[BS];
+  static_assert(NT == BS * (RC / 4), "one thread per row and group of four columns");
+  __shared__ double Ab[2][BS][BS + 1];
+  __shared__ double xs[2][BS][RC + 1];
   const int64_t nb = (n + BS - 1) / BS;
   const int64_t I = blockIdx.x;
   const int64_t r0 = I * BS;
   const int bs = (int)min((int64_t)BS, n - r0);
   const int tid = threadIdx.x;
-  for (int t = tid; t < BS * RC; t += NT) {
-    const int i = t % BS, c = t / BS;
-    acc[i][c] = (i < bs && c < nr && B) ? B[r0 + i + (int64_t)c * ldb] : 0.0;
+  const int mi = tid % BS, g = tid / BS;  // product: row mi, columns 4g .. 4g+3
+  double acc[4];
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const int c = 4 * g + q;
+    acc[q] = (mi < bs && c < nr && B) ? B[r0 + mi + (int64_t)c * ldb] : 0.0;
   }
-  if (tid < BS) ra[tid] = 0.0;
-  for (int64_t J = 0; J < nb; ++J) {
+  double ra = 0.0;  // |S| row sum of row mi (threads of column group 0)
+  // element e = tid + NT q: (i, j) = (e % BS, e / BS) for blocks on or left of the
+  // diagonal (stored rows i, consecutive threads down a column), (e / BS, e % BS)
+  // right of it (stored block (J, I) read down its columns)
+  auto fetch = [&](int64_t J, double (&v)[kPer], double (&xv)[kPerX]) {
     const int64_t c0 = J * BS;
-    const int cs = (int)min((int64_t)BS, n - c0);
-    __syncthreads();
-    // S_IJ: J < I stored block (I, J); J > I -(stored block (J, I))^T; J == I skew diagonal block
-    for (int t = tid; t < BS * BS; t += NT) {
-      // consecutive threads walk down a stored column in both orientations
-      const int i = (J <= I) ? t % BS : t / BS, j = (J <= I) ? t / BS : t % BS;
-      double v = 0.0;
-      if (i < bs && j < cs) {
-        const int64_t gi = r0 + i, gj = c0 + j;
-        if (gi > gj) v = A0[gi + gj * lda];
-        else if (gi < gj) v = -A0[gj + gi * lda];
-      }
-      Ab[i][j] = v;
+#pragma unroll
+    for (int q = 0; q < kPer; ++q) {
+      const int e = tid + NT * q;
+      const int i = (J <= I) ? e % BS : e / BS, j = (J <= I) ? e / BS : e % BS;
+      const int64_t gi = r0 + i, gj = c0 + j;
+      const bool ok = gi < n && gj < n && gi != gj;
+      const int64_t a = gi > gj ? gi + gj * lda : gj + gi * lda;
+      v[q] = A0[ok ? a : 0];
     }
-    for (int t = tid; t < BS * RC; t += NT) {
-      const int j = t % BS, c = t / BS;
-      xs[j][c] = (j < cs && c < nr) ? X[c0 + j + (int64_t)c * ldx] : 0.0;
+#pragma unroll
+    for (int q = 0; q < kPerX; ++q) {
+      const int e = tid + NT * q;
+      const int j = e % BS, c = e / BS;
+      const bool ok = c0 + j < n && c < nr;
+      xv[q] = X[ok ? c0 + j + (int64_t)c * ldx : 0];
     }
-    __syncthreads();
-    for (int t = tid; t < BS * RC; t += NT) {
-      const int i = t % BS, c = t / BS;
-      double sum = 0.0;
-#pragma unroll 8
-      for (int j = 0; j < BS; ++j) sum += Ab[i][j] * xs[j][c];
-      acc[i][c] -= sum;
+  };
+  auto put = [&](int buf, int64_t J, const double (&v)[kPer], const double (&xv)[kPerX]) {
+    const int64_t c0 = J * BS;
+#pragma unroll
+    for (int q = 0; q < kPer; ++q) {
+      const int e = tid + NT * q;
+      const int i = (J <= I) ? e % BS : e / BS, j = (J <= I) ? e / BS : e % BS;
+      const int64_t gi = r0 + i, gj = c0 + j;
+      const bool ok = gi < n && gj < n && gi != gj;
+      Ab[buf][i][j] = ok ? (gi > gj ? v[q] : -v[q]) : 0.0;
     }
-    if (rowabs && tid < BS) {
-      double sa = 0.0;
-      for (int j = 0; j < BS; ++j) sa += fabs(Ab[tid][j]);
-      ra[tid] += sa;
+#pragma unroll
+    for (int q = 0; q < kPerX; ++q) {
+      const int e = tid + NT * q;
+      const int j = e % BS, c = e / BS;
+      xs[buf][j][c] = (c0 + j < n && c < nr) ? xv[q] : 0.0;
     }
-  }
+  };
+  double v[kPer], xv[kPerX];
+  fetch(0, v, xv);
+  put(0, 0, v, xv);
   __syncthreads();
-  for (int t = tid; t < BS * RC; t += NT) {
-    const int i = t % BS, c = t / BS;
-    if (i < bs && c < nr) R[r0 + i + (int64_t)c * ldr] = acc[i][c];
+  for (int64_t J = 0; J < nb; ++J) {
+    const int buf = (int)(J & 1);
+    const bool more = J + 1 < nb;
+    if (more) fetch(J + 1, v, xv);
+#pragma unroll 8
+    for (int j = 0; j < BS; ++j) {
+      const double a = Ab[buf][mi][j];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) acc[q] -= a * xs[buf][j][4 * g + q];
+    }
+    if (rowabs && g == 0) {
+      double sa = 0.0;
+      for (int j = 0; j < BS; ++j) sa += fabs(Ab[buf][mi][j]);
+      ra += sa;
+    }
+    if (more) put(buf ^ 1, J + 1, v, xv);  // the other half was last read before the previous barrier
+    __syncthreads();
   }
-  if (rowabs && tid < bs) rowabs[r0 + tid] = ra[tid];
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const int c = 4 * g + q;
+    if (mi < bs && c < nr) R[r0 + mi + (int64_t)c * ldr] = acc[q];
+  }
+  if (rowabs && g == 0 && mi < bs) rowabs[r0 + mi] = ra;
 }
 
 // out[3c + {0,1,2}] = max_i |R[i,c]|, max_i |X[i,c]|, max_i |B[i,c]|; out[3 nrhs] = max rowabs.
