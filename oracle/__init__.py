@@ -3,8 +3,9 @@
 Only ``tests/``, ``__graft_entry__.smoke()`` and the CPU-baseline leg of
 ``bench.py`` may import this package.  The GPU product path never calls it.
 
-The LTL^T factorization, the Pfaffian from the factors and the solve are plain
-C (``ltlt_oracle.c``: the unblocked definition, FP64, no FMA contraction).  The
+The LTL^T factorization, the Pfaffian-only reduction (the same elimination step
+at even steps only), the Pfaffian from the factors and the solve are plain C
+(``ltlt_oracle.c``: the unblocked definition, FP64, no FMA contraction).  The
 remaining references are written here from their definitions:
 
 * ``pfaffian_bruteforce`` -- exact Pfaffian by expansion along the first row,
@@ -64,6 +65,8 @@ def _load():
             lib.oracle_ltlt.argtypes = [i64, dp, i64, ip, dp, dp, i64, ctypes.c_int]
             lib.oracle_logpf.restype = None
             lib.oracle_logpf.argtypes = [i64, ip, dp, dp, ctypes.POINTER(ctypes.c_int)]
+            lib.oracle_pfonly.restype = ctypes.c_int
+            lib.oracle_pfonly.argtypes = [i64, dp, i64, ip, dp, ctypes.c_int]
             lib.oracle_solve.restype = ctypes.c_int
             lib.oracle_solve.argtypes = [i64, i64, dp, i64, ip, dp, dp, i64]
             _lib = lib
@@ -120,6 +123,30 @@ def logpf(A: np.ndarray, nthreads: int = 1):
         return float("nan"), 0, f.info
     la, s = logpf_from_factors(A.shape[0], f.ipiv, f.T)
     return la, s, f.info
+
+
+def pfonly(A: np.ndarray, nthreads: int = 1):
+    """Pfaffian-only reduction (even elimination steps only): (ipiv, T, info).
+
+    ipiv[k+1] (k even) is the interchange of step k, every other ipiv[j] = j;
+    T[k] (k even) are the pivots.  log|Pf| and sign follow from them exactly as
+    from the full factors (``logpf_from_factors``)."""
+    n = A.shape[0]
+    assert A.shape == (n, n)
+    W = np.array(A, dtype=np.float64, order="F")
+    ipiv = np.zeros(max(n, 1), dtype=np.int32)
+    T = np.zeros(max(n - 1, 1), dtype=np.float64)
+    info = _load().oracle_pfonly(n, _dp(W), max(n, 1), _ip(ipiv), _dp(T), nthreads)
+    return ipiv[:n], T[:max(n - 1, 0)], int(info)
+
+
+def logpf_pfonly(A: np.ndarray, nthreads: int = 1):
+    """(log|Pf|, sign, info) by the Pfaffian-only reduction."""
+    ipiv, T, info = pfonly(A, nthreads=nthreads)
+    if info == ENONFINITE:
+        return float("nan"), 0, info
+    la, s = logpf_from_factors(A.shape[0], ipiv, T)
+    return la, s, info
 
 
 def solve(LT: np.ndarray, ipiv: np.ndarray, T: np.ndarray, B: np.ndarray):

@@ -46,6 +46,7 @@ typedef struct {
   int status;
   pthread_barrier_t bar;
   int64_t k;      /* current step, published by thread 0 */
+  int64_t kstep;  /* 1: every step; 2: even steps only (Pfaffian-only reduction) */
   int stop;       /* set by thread 0 to end the loop */
 } orc_ctx;
 
@@ -132,7 +133,7 @@ static void* orc_worker(void* p) {
     if (c->stop) break;
     orc_update(c, c->k, a->tid);
     pthread_barrier_wait(&c->bar);
-    if (a->tid == 0) c->k += 1;
+    if (a->tid == 0) c->k += c->kstep;
   }
   return NULL;
 }
@@ -158,6 +159,7 @@ int oracle_ltlt(int64_t n, double* A, int64_t lda, int32_t* ipiv, double* T, dou
   c.n = n;
   c.nthreads = nthreads;
   c.nsteps = nsteps < 0 ? n : nsteps;
+  c.kstep = 1;
   c.ipiv = ipiv;
   c.T = T;
   c.gap = gap;
@@ -180,6 +182,59 @@ int oracle_ltlt(int64_t n, double* A, int64_t lda, int32_t* ipiv, double* T, dou
     if (!isfinite(T[n - 2])) return ORC_ENONFINITE;
     ipiv[n - 1] = (int32_t)(n - 1);
   }
+  for (int64_t k = 0; k + 1 < n; k += 2)
+    if (T[k] == 0.0) return (int)(k + 1);
+  return 0;
+}
+
+/*
+ * Pfaffian-only reduction: the same elimination step (pivot search, symmetric
+ * interchange, multipliers, rank-2 congruence update) taken at the even steps
+ * k = 0, 2, ..., n-4 only.  Step k leaves rows/columns k and k+1 as the 2 x 2
+ * block [[0, -T[k]], [T[k], 0]] decoupled from the rest (the update is a
+ * congruence with a unit lower triangular matrix, which keeps the Pfaffian),
+ * so the next step may start directly at column k+2: half the pivot steps of
+ * the full factorization, the same n^3/3 flops, and
+ *   Pf(A) = (-1)^{s + n/2} prod_{k even} T[k],  s = #{j : ipiv[j] != j},
+ * exactly as from the full factors (oracle_logpf applies unchanged).
+ * On exit ipiv[k+1] (k even) holds the interchange of step k and every other
+ * ipiv[j] = j; T[k] (k even) holds the pivots and T[k] (k odd) = 0; A is left
+ * as scratch (no L).  n odd: Pf = 0, returns n without touching A.
+ * Returns as oracle_ltlt.
+ */
+int oracle_pfonly(int64_t n, double* A, int64_t lda, int32_t* ipiv, double* T, int nthreads) {
+  if (n < 0 || lda < (n > 1 ? n : 1) || (n > 0 && (!A || !ipiv)) || (n > 1 && !T)) return ORC_EARG;
+  if (n == 0) return 0;
+  for (int64_t j = 0; j < n; ++j) ipiv[j] = (int32_t)j;
+  for (int64_t k = 0; k + 1 < n; ++k) T[k] = 0.0;
+  if (n % 2 == 1) return (int)n;
+  if (nthreads < 1) nthreads = 1;
+  if (nthreads > 64) nthreads = 64;
+  orc_ctx c;
+  memset(&c, 0, sizeof c);
+  c.A = A;
+  c.lda = lda;
+  c.n = n;
+  c.nthreads = nthreads;
+  c.nsteps = n;
+  c.kstep = 2;
+  c.ipiv = ipiv;
+  c.T = T;
+  c.gap = NULL;
+  pthread_barrier_init(&c.bar, NULL, (unsigned)nthreads);
+  pthread_t th[64];
+  orc_arg args[64];
+  for (int t = 0; t < nthreads; ++t) {
+    args[t].c = &c;
+    args[t].tid = t;
+    if (t > 0) pthread_create(&th[t], NULL, orc_worker, &args[t]);
+  }
+  orc_worker(&args[0]);
+  for (int t = 1; t < nthreads; ++t) pthread_join(th[t], NULL);
+  pthread_barrier_destroy(&c.bar);
+  if (c.status != 0) return c.status;
+  T[n - 2] = AT(n - 1, n - 2);
+  if (!isfinite(T[n - 2])) return ORC_ENONFINITE;
   for (int64_t k = 0; k + 1 < n; k += 2)
     if (T[k] == 0.0) return (int)(k + 1);
   return 0;
