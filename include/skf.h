@@ -181,8 +181,29 @@ int skf_ltlt_batched(skf_int batch, const skf_int* n_host, double* const* A, con
                      int32_t* const* ipiv, double* const* T, double* logabs, int* sign, int* info,
                      void* work, size_t lwork, void* stream);
 
-/* log|Pf| and sign of every matrix of the batch.  A is used as scratch: its
- * trailing parts are overwritten and no factor is left in it. */
+/*
+ * Batched Pfaffian-only reduction: the elimination step of skf_ltlt taken at
+ * the even steps only.  Step k pivots on column k (largest |A[i,k]|, i > k,
+ * lowest index on ties), interchanges rows/columns k+1 and p, and adds the
+ * skew rank-2 term l v^T - v l^T to A[k+2:, k+2:]; rows/columns k and k+1 are
+ * then decoupled (a congruence with a unit lower triangular matrix keeps the
+ * Pfaffian), so the next step is k+2: n/2 pivot steps instead of n, the same
+ * n^3/3 flops, and Pf(A) = (-1)^{s + n/2} prod_{k even} T[k] with s the number
+ * of interchanges.  Its pivots differ from skf_ltlt's (the odd steps are
+ * skipped); the Pfaffian is the same.  One persistent launch as
+ * skf_ltlt_batched; A is scratch (no factor is left in it).
+ *   ipiv, T   device arrays [batch] of device pointers, or NULL to skip:
+ *             ipiv[b][k+1] (k even) receives step k's interchange, the other
+ *             entries j; T[b][k] (k even) the pivots, the odd entries 0
+ *   logabs, sign, info  as skf_ltlt_batched (info = n for odd n)
+ * Returns 0 or a negative argument / launch error (-7: logabs or sign NULL).
+ */
+int skf_pfonly_batched(skf_int batch, const skf_int* n_host, double* const* A, const skf_int* lda_host,
+                       int32_t* const* ipiv, double* const* T, double* logabs, int* sign, int* info,
+                       void* work, size_t lwork, void* stream);
+
+/* log|Pf| and sign of every matrix of the batch by the Pfaffian-only reduction
+ * (skf_pfonly_batched without ipiv / T).  A is used as scratch. */
 int skf_logpf_batched(skf_int batch, const skf_int* n_host, double* const* A, const skf_int* lda_host,
                       double* logabs, int* sign, int* info, void* work, size_t lwork, void* stream);
 

@@ -330,6 +330,16 @@ int skf_ltlt_batched(skf_int batch, const skf_int* n_host, double* const* A, con
   return run_batched(batch, n_host, A, lda_host, ipiv, T, logabs, sign, info, work, lwork, true, (hipStream_t)stream);
 }
 
+int skf_pfonly_batched(skf_int batch, const skf_int* n_host, double* const* A, const skf_int* lda_host,
+                       int32_t* const* ipiv, double* const* T, double* logabs, int* sign, int* info,
+                       void* work, size_t lwork, void* stream) {
+  int rc = check_batched(batch, n_host, A, lda_host, work, lwork);
+  if (rc) return rc;
+  if (batch > 0 && (!logabs || !sign)) return -7;
+  return run_batched(batch, n_host, A, lda_host, ipiv, T, logabs, sign, info, work, lwork, false,
+                     (hipStream_t)stream);
+}
+
 int skf_logpf_batched(skf_int batch, const skf_int* n_host, double* const* A, const skf_int* lda_host,
                       double* logabs, int* sign, int* info, void* work, size_t lwork, void* stream) {
   int rc = check_batched(batch, n_host, A, lda_host, work, lwork);

@@ -59,6 +59,7 @@ struct Smem {
   int item;
   int piv;
   double alpha, l0;
+  double akk;  // Pfaffian-only form: A[k+2, k+1] before the step's interchange
   int flag;
 };
 
@@ -347,6 +348,259 @@ __global__ void __launch_bounds__(BT, kWgPerCu) batched_kernel(BatchArgs a) {
   }
 }
 
+// Pfaffian-only form: the elimination step taken at the even steps k only
+// (the reduction the oracle's Pfaffian-only mode defines): step k pivots on
+// column k, interchanges rows/columns k+1 and p, and adds l v^T - v l^T to the
+// trailing matrix (l = multipliers, v = column k+1 after the interchange); rows
+// and columns k, k+1 are then finished, so the next step pivots on column k+2.
+// Half the pivot steps of the full factorization for the same n^3/3 flops.
+// Updates are delayed over a panel of BNP steps as in the full form: each
+// needed column is the stored one plus a skew GEMV with the panel's (l, v).
+// Per step, the stored columns k+1 and k+2 are loaded before the pivot search
+// (their addresses do not depend on it); the interchange then changes column
+// k+2 at one known place (row p), or replaces it by the old column k+1 (p =
+// k+2), which is patched in registers.  ipiv (if given) receives the
+// interchanges (even positions stay j), T the pivots at even k.
+__global__ void __launch_bounds__(BT, kWgPerCu) pfonly_kernel(BatchArgs a) {
+  __shared__ Smem sm;
+  const int tid = threadIdx.x;
+  for (;;) {
+    if (tid == 0) sm.item = atomicAdd(a.queue, 1);
+    __syncthreads();
+    const int64_t it = sm.item;
+    __syncthreads();
+    if (it >= a.batch) return;
+    const int64_t b = a.order[it];
+    const int64_t n = a.nn[b], ld = a.lda[b];
+    double* A = a.A[b];
+    int32_t* ipiv = a.ipiv ? a.ipiv[b] : nullptr;
+    double* Tv = a.T ? a.T[b] : nullptr;
+    if (ipiv == nullptr) ipiv = a.ipiv_scratch + (size_t)blockIdx.x * BR;
+    if (Tv == nullptr) Tv = a.T_scratch + (size_t)blockIdx.x * BR;
+    int status = 0;
+    for (int64_t jj = tid; jj < n; jj += BT) ipiv[jj] = (int32_t)jj;
+    for (int64_t jj = tid; jj + 1 < n; jj += BT) Tv[jj] = 0.0;
+    if (n >= 2 && n % 2 == 0) {
+      for (int r = 0; r < RPT; ++r) {
+        const int i = tid + BT * r;
+        sm.cur[i] = (i >= 1 && i < n) ? A[i] : 0.0;
+      }
+      __syncthreads();
+      for (int64_t k0 = 0; k0 < n - 1 && status == 0; k0 += 2 * BNP) {
+        const int np = (int)min((int64_t)BNP, (n - k0) / 2);
+        for (int q = 0; q < BNP; ++q)
+          for (int r = 0; r < RPT; ++r) sm.LW[q][tid + BT * r] = make_double2(0.0, 0.0);
+        __syncthreads();
+        int done = 0;  // steps of this panel that produced a pair
+        for (int q = 0; q < np; ++q) {
+          const int64_t k = k0 + 2 * q, rr = k + 1, x = k + 2;
+          const bool last = x >= n;  // k = n-2: pivot only
+          // stored columns k+1 (rows > k+1) and k+2 (rows > k+2), before the pivot is known
+          double oldr[RPT], colx[RPT];
+          for (int r = 0; r < RPT; ++r) {
+            const int i = tid + BT * r;
+            oldr[r] = (!last && i > rr && i < n) ? A[i + rr * ld] : 0.0;
+            colx[r] = (!last && i > x && i < n) ? A[i + x * ld] : 0.0;
+            if (!last && i == x) sm.akk = oldr[r];
+          }
+          // pivot over rows >= k+1
+          double bv = -1.0;
+          int bp = INT32_MAX;
+          bool nf = false;
+          for (int r = 0; r < RPT; ++r) {
+            const int i = tid + BT * r;
+            if (i >= rr && i < n) {
+              const double c = sm.cur[i];
+              if (!isfinite(c)) nf = true;
+              if (better(fabs(c), i, bv, bp)) {
+                bv = fabs(c);
+                bp = i;
+              }
+            }
+          }
+          if (tid == 0) sm.flag = 0;
+          __syncthreads();
+          if (nf) sm.flag = 1;
+          double gv;
+          int p;
+          block_argmax(sm, bv, bp, &gv, &p);
+          if (sm.flag) {
+            status = SKF_ENONFINITE;
+            break;
+          }
+          const double alpha = sm.cur[p];
+          // column k+1 after the interchange (rows > k+1), and the interchange in memory
+          double newc[RPT];
+          for (int r = 0; r < RPT; ++r) {
+            const int i = tid + BT * r;
+            double v = 0.0;
+            if (!last && i > rr && i < n) {
+              if (p != rr) v = (i < p) ? -A[p + (int64_t)i * ld] : (i == p ? -A[p + rr * ld] : A[i + (int64_t)p * ld]);
+              else v = oldr[r];
+            }
+            newc[r] = v;
+          }
+          if (!last && p != rr) {
+            for (int r = 0; r < RPT; ++r) {
+              const int i = tid + BT * r;
+              if (i > rr && i < n) {
+                const double old = oldr[r];
+                if (i < p) A[p + (int64_t)i * ld] = -old;
+                else if (i == p) A[p + rr * ld] = -old;
+                else A[i + (int64_t)p * ld] = old;
+              }
+            }
+          }
+          // every thread has read alpha = cur[p] before rows r and p of the LDS
+          // arrays are swapped: an LDS-only barrier (global stores stay in flight)
+          __builtin_amdgcn_s_waitcnt(0xC07F);
+          __builtin_amdgcn_s_barrier();
+          if (p != rr && tid <= BNP) {
+            if (tid < BNP) {
+              const double2 t = sm.LW[tid][rr];
+              sm.LW[tid][rr] = sm.LW[tid][p];
+              sm.LW[tid][p] = t;
+            } else {
+              const double t = sm.cur[rr];
+              sm.cur[rr] = sm.cur[p];
+              sm.cur[p] = t;
+            }
+          }
+          if (tid == 0) {
+            Tv[k] = alpha;
+            ipiv[rr] = (int32_t)p;
+          }
+          __syncthreads();
+          if (last) break;
+          // (l, v) of this step below row k+1: v = stored column k+1 + corrections
+          for (int r = 0; r < RPT; ++r) {
+            const int i = tid + BT * r;
+            if (i > rr && i < n) {
+              const double l = (alpha != 0.0) ? sm.cur[i] / alpha : 0.0;
+              double corr = 0.0;
+              for (int qq = 0; qq < q; ++qq) {
+                const double2 u = sm.LW[qq][i], c = sm.LW[qq][rr];
+                corr += u.x * c.y - u.y * c.x;
+              }
+              sm.LW[q][i] = make_double2(l, newc[r] + corr);
+            }
+          }
+          __syncthreads();
+          // next pivot column k+2 below its diagonal: stored (after the interchange)
+          // + corrections with the pairs so far, this one included
+          const double akk = sm.akk;
+          for (int r = 0; r < RPT; ++r) {
+            const int i = tid + BT * r;
+            if (i > x && i < n) {
+              const double st = (p == x) ? oldr[r] : (i == p ? -akk : colx[r]);
+              double corr = 0.0;
+              for (int qq = 0; qq <= q; ++qq) {
+                const double2 u = sm.LW[qq][i], c = sm.LW[qq][x];
+                corr += u.x * c.y - u.y * c.x;
+              }
+              sm.cur[i] = st + corr;
+            }
+          }
+          ++done;
+          __syncthreads();
+        }
+        if (status) break;
+        // trailing update: A[i,jj] += sum_q (l_i v_jj - v_i l_jj) for i > jj > lo
+        const int64_t lo = k0 + 2 * done;
+        if (done == np && n - lo >= 3) {
+          const int64_t c1 = lo + 1;
+          const int64_t m = n - c1;
+          constexpr int SW = 8, NS = 2;
+          const int64_t nstrip = (m + SW - 1) / SW;
+          for (int64_t s0 = 0; s0 < nstrip; s0 += NS) {
+            const int64_t j0 = c1 + s0 * SW;
+            for (int64_t i = j0 + 1 + tid; i < n; i += BT) {
+              double cv[NS * SW], acc[NS * SW];
+#pragma unroll
+              for (int t = 0; t < NS * SW; ++t) {
+                const int64_t jj = j0 + t;
+                cv[t] = (jj < i) ? A[i + jj * ld] : 0.0;
+                acc[t] = 0.0;
+              }
+              for (int q = 0; q < done; ++q) {
+                const double2 u = sm.LW[q][i];
+#pragma unroll
+                for (int t = 0; t < NS * SW; ++t) {
+                  const double2 v = sm.LW[q][min(j0 + t, (int64_t)BR - 1)];
+                  acc[t] += u.x * v.y - u.y * v.x;
+                }
+              }
+#pragma unroll
+              for (int t = 0; t < NS * SW; ++t) {
+                const int64_t jj = j0 + t;
+                if (jj < i) A[i + jj * ld] = cv[t] + acc[t];
+              }
+            }
+          }
+        }
+        __syncthreads();
+      }
+    }
+    __syncthreads();
+    // Pfaffian: log|Pf| = sum log|T[k even]|, sign from the interchanges and the signs
+    double acc = 0.0;
+    int par = 0;
+    if (status == 0 && n % 2 == 0) {
+      const int64_t np2 = n / 2;
+      const int64_t chunk = (np2 + BT - 1) / BT;
+      for (int64_t q = tid * chunk; q < min(np2, (tid + 1) * chunk); ++q) {
+        const double t = Tv[2 * q];
+        if (t == 0.0) par |= 2;
+        if (t < 0.0) par ^= 1;
+        acc += log(fabs(t));
+      }
+      for (int64_t jj = tid; jj < n; jj += BT)
+        if (ipiv[jj] != (int32_t)jj) par ^= 1;
+    }
+    sm.sum[tid] = acc;
+    sm.par[tid] = par;
+    __syncthreads();
+    for (int s = BT / 2; s > 0; s >>= 1) {
+      if (tid < s) {
+        sm.sum[tid] = sm.sum[tid] + sm.sum[tid + s];
+        sm.par[tid] = (sm.par[tid] ^ (sm.par[tid + s] & 1)) | (sm.par[tid + s] & 2);
+      }
+      __syncthreads();
+    }
+    if (tid == 0) {
+      double la;
+      int sg;
+      int inf = status;
+      if (status != 0) {
+        la = NAN;
+        sg = 0;
+      } else if (n == 0) {
+        la = 0.0;
+        sg = 1;
+      } else if (n % 2 == 1 || (sm.par[0] & 2)) {
+        la = -INFINITY;
+        sg = 0;
+      } else {
+        la = sm.sum[0];
+        sg = (((sm.par[0] & 1) ^ (int)((n / 2) & 1)) != 0) ? -1 : 1;
+      }
+      if (inf == 0) {
+        if (n % 2 == 1) inf = (int)n;
+        else
+          for (int64_t kk = 0; kk + 1 < n; kk += 2)
+            if (Tv[kk] == 0.0) {
+              inf = (int)(kk + 1);
+              break;
+            }
+      }
+      if (a.logabs) a.logabs[b] = la;
+      if (a.sign) a.sign[b] = sg;
+      if (a.info) a.info[b] = inf;
+    }
+    __syncthreads();
+  }
+}
+
 struct BatchedWork {
   int64_t* order;
   int64_t* nn;
@@ -389,6 +643,8 @@ int batched_max_n() { return BR; }
 int run_batched(int64_t batch, const int64_t* n_host, double* const* A, const int64_t* lda_host,
                 int32_t* const* ipiv, double* const* T, double* logabs, int* sign, int* info, void* work,
                 size_t lwork, bool want_L, hipStream_t s) {
+  // want_L: the full factorization (L, T, ipiv); otherwise the Pfaffian-only
+  // reduction (ipiv / T, if given, receive its interchanges and pivots)
   BatchedWork w = batched_carve(work, batch);
   if (lwork < w.bytes) return SKF_EWORK;
   if (batch == 0) return 0;
@@ -405,7 +661,7 @@ int run_batched(int64_t batch, const int64_t* n_host, double* const* A, const in
   if (want_L)
     hipLaunchKernelGGL(batched_kernel<true>, dim3((unsigned)batched_grid()), dim3(BT), 0, s, args);
   else
-    hipLaunchKernelGGL(batched_kernel<false>, dim3((unsigned)batched_grid()), dim3(BT), 0, s, args);
+    hipLaunchKernelGGL(pfonly_kernel, dim3((unsigned)batched_grid()), dim3(BT), 0, s, args);
   SKF_CHECK_LAUNCH("batched");
   return 0;
 }

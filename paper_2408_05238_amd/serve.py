@@ -348,7 +348,7 @@ class GpuExecutor:
                     w = skf.colmajor(r.n, r.n, device=self.device)
                     w.copy_(r.A)
                     mats.append(w)
-                la, sg, info, _, _ = skf.ltlt_batched(mats, with_factors=False, stream=s)
+                la, sg, info = skf.logpf_batched(mats, stream=s)
                 s.synchronize()
                 la, sg, info = la.cpu().tolist(), sg.cpu().tolist(), info.cpu().tolist()
                 out = [Result(r.rid, r.arrival, logabs=la[i], sign=sg[i], info=info[i], batched=len(reqs) > 1)

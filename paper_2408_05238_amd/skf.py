@@ -30,7 +30,7 @@ EXPORTS = [
     "skf_version", "skf_last_error", "skf_ltlt_workspace", "skf_ltlt", "skf_logpf_from_factors",
     "skf_logpf_workspace", "skf_logpf", "skf_pfaffian", "skf_skr2k", "skf_skr2k_f32",
     "skf_solve_workspace", "skf_solve", "skf_refine_workspace", "skf_solve_refine",
-    "skf_batched_workspace", "skf_ltlt_batched", "skf_logpf_batched", "skf_solve_batched",
+    "skf_batched_workspace", "skf_ltlt_batched", "skf_pfonly_batched", "skf_logpf_batched", "skf_solve_batched",
     "skf_profile_enable", "skf_profile_read",
 ]
 
@@ -78,6 +78,7 @@ def _load():
                                           ctypes.POINTER(ci), ctypes.POINTER(d), vp, sz, vp]),
                 "skf_batched_workspace": (sz, [i64, vp]),
                 "skf_ltlt_batched": (ci, [i64, vp, vp, vp, vp, vp, vp, vp, vp, vp, sz, vp]),
+                "skf_pfonly_batched": (ci, [i64, vp, vp, vp, vp, vp, vp, vp, vp, vp, sz, vp]),
                 "skf_logpf_batched": (ci, [i64, vp, vp, vp, vp, vp, vp, vp, sz, vp]),
                 "skf_solve_batched": (ci, [i64, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, sz, vp]),
                 "skf_profile_enable": (ci, [ci]),
@@ -310,10 +311,12 @@ def batched_workspace(n_list) -> int:
 
 
 def ltlt_batched(mats, with_factors: bool = True, work=None, stream=None):
-    """Factor a list of column-major skew matrices (n <= 512) in one persistent launch.
+    """Factor a list of column-major skew matrices (n <= 512) in one persistent launch
+    (L is left in place).
 
     Returns (logabs, sign, info, ipivs, Ts) as device tensors (ipivs / Ts are
-    lists, or None when ``with_factors`` is False).  Asynchronous on the stream.
+    lists, or None when ``with_factors`` is False: then they are not stored).
+    Asynchronous on the stream.  For log|Pf| alone see :func:`logpf_batched`.
     """
     import numpy as np
     torch = _torch()
@@ -339,11 +342,62 @@ def ltlt_batched(mats, with_factors: bool = True, work=None, stream=None):
         ipivs = [ip[:int(n)] for ip, n in zip(ipivs, n_h)]
         Ts = [t[:max(int(n) - 1, 0)] for t, n in zip(Ts, n_h)]
     else:
-        rc = _load().skf_logpf_batched(B, n_h.ctypes.data_as(ctypes.c_void_p), _ptr(aptr),
-                                       lda_h.ctypes.data_as(ctypes.c_void_p), _ptr(logabs), _ptr(sign), _ptr(info),
-                                       _ptr(work), work.numel(), _stream(stream))
+        rc = _load().skf_ltlt_batched(B, n_h.ctypes.data_as(ctypes.c_void_p), _ptr(aptr),
+                                      lda_h.ctypes.data_as(ctypes.c_void_p), None, None, _ptr(logabs),
+                                      _ptr(sign), _ptr(info), _ptr(work), work.numel(), _stream(stream))
     _check(rc, "skf_ltlt_batched")
     return logabs[:B], sign[:B], info[:B], ipivs, Ts
+
+
+def logpf_batched(mats, work=None, stream=None):
+    """log|Pf| and sign of a list of column-major skew matrices (n <= 512) by the
+    Pfaffian-only reduction, one persistent launch; the matrices are scratch.
+    Returns (logabs, sign, info) as device tensors."""
+    import numpy as np
+    torch = _torch()
+    dev = mats[0].device if mats else torch.device("cuda")
+    B = len(mats)
+    n_h = np.array([m.shape[0] for m in mats], dtype=np.int64)
+    lda_h = np.array([_ld(m) if m.shape[0] > 0 else 1 for m in mats], dtype=np.int64)
+    aptr = _ptr_array(mats, dev, stream)
+    logabs = torch.empty(max(B, 1), dtype=torch.float64, device=dev)
+    sign = torch.empty(max(B, 1), dtype=torch.int32, device=dev)
+    info = torch.empty(max(B, 1), dtype=torch.int32, device=dev)
+    if work is None:
+        work = workspace(batched_workspace(n_h), dev)
+    rc = _load().skf_logpf_batched(B, n_h.ctypes.data_as(ctypes.c_void_p), _ptr(aptr),
+                                   lda_h.ctypes.data_as(ctypes.c_void_p), _ptr(logabs), _ptr(sign), _ptr(info),
+                                   _ptr(work), work.numel(), _stream(stream))
+    _check(rc, "skf_logpf_batched")
+    return logabs[:B], sign[:B], info[:B]
+
+
+def pfonly_batched(mats, work=None, stream=None):
+    """Pfaffian-only reduction of a list of column-major skew matrices (n <= 512),
+    one persistent launch.  Returns (logabs, sign, info, ipivs, Ts) as device
+    tensors; the matrices are used as scratch."""
+    import numpy as np
+    torch = _torch()
+    dev = mats[0].device if mats else torch.device("cuda")
+    B = len(mats)
+    n_h = np.array([m.shape[0] for m in mats], dtype=np.int64)
+    lda_h = np.array([_ld(m) if m.shape[0] > 0 else 1 for m in mats], dtype=np.int64)
+    aptr = _ptr_array(mats, dev, stream)
+    logabs = torch.empty(max(B, 1), dtype=torch.float64, device=dev)
+    sign = torch.empty(max(B, 1), dtype=torch.int32, device=dev)
+    info = torch.empty(max(B, 1), dtype=torch.int32, device=dev)
+    if work is None:
+        work = workspace(batched_workspace(n_h), dev)
+    ipivs = [torch.empty(max(int(n), 1), dtype=torch.int32, device=dev) for n in n_h]
+    Ts = [torch.empty(max(int(n) - 1, 1), dtype=torch.float64, device=dev) for n in n_h]
+    pp = _ptr_array(ipivs, dev, stream)
+    tp = _ptr_array(Ts, dev, stream)
+    rc = _load().skf_pfonly_batched(B, n_h.ctypes.data_as(ctypes.c_void_p), _ptr(aptr),
+                                    lda_h.ctypes.data_as(ctypes.c_void_p), _ptr(pp), _ptr(tp), _ptr(logabs),
+                                    _ptr(sign), _ptr(info), _ptr(work), work.numel(), _stream(stream))
+    _check(rc, "skf_pfonly_batched")
+    return (logabs[:B], sign[:B], info[:B], [ip[:int(n)] for ip, n in zip(ipivs, n_h)],
+            [t[:max(int(n) - 1, 0)] for t, n in zip(Ts, n_h)])
 
 
 def logpf_batched_packed(buf, offsets, n_list, work=None, stream=None):

@@ -1,6 +1,6 @@
-"""GPU parity of the batched persistent factorization against the CPU oracle,
-and batch-composition independence (a matrix's result is the same alone and in
-any mix, bit for bit)."""
+"""GPU parity of the batched persistent factorization and of the batched
+Pfaffian-only reduction against the CPU oracle, and batch-composition
+independence (a matrix's result is the same alone and in any mix, bit for bit)."""
 from __future__ import annotations
 
 import numpy as np
@@ -62,7 +62,7 @@ def test_batched_logpf_only_and_nonfinite(skf, oracle_mod, gen):
     mats_h[1] = mats_h[1].copy()
     mats_h[1][50, 3] = np.nan
     mats = [skf.to_device_colmajor(A) for A in mats_h]
-    la, sg, info, _, _ = skf.ltlt_batched(mats, with_factors=False)
+    la, sg, info = skf.logpf_batched(mats)
     la, sg, info = _host(la), _host(sg), _host(info)
     la_r, s_r, _ = oracle_mod.logpf(mats_h[0])
     assert sg[0] == s_r and oracle_mod.isclose_log(la[0], la_r) <= 1e-12
@@ -97,5 +97,58 @@ def test_batched_repeatable_large_mix(skf, gen):
     assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1]) and np.array_equal(a[2], b[2])
     assert all(np.array_equal(x, y) for x, y in zip(a[3], b[3]))
     assert all(np.array_equal(x, y) for x, y in zip(a[4], b[4]))
-    la2, sg2, _, _, _ = skf.ltlt_batched([skf.to_device_colmajor(A) for A in mats_h], with_factors=False)
-    assert np.array_equal(_host(la2), a[0]) and np.array_equal(_host(sg2), a[1])
+    # the Pfaffian-only path: the same bits on every run, the same Pfaffian as the factorization
+    pf = []
+    for _ in range(2):
+        la2, sg2, info2, ip2, _ = skf.pfonly_batched([skf.to_device_colmajor(A) for A in mats_h])
+        pf.append((_host(la2), _host(sg2), _host(info2), [_host(t) for t in ip2]))
+    assert all(np.array_equal(x, y) for x, y in zip(pf[0][:3], pf[1][:3]))
+    assert all(np.array_equal(x, y) for x, y in zip(pf[0][3], pf[1][3]))
+    assert np.array_equal(pf[0][1], a[1])
+    assert np.abs(pf[0][0] - a[0]).max() <= 1e-12 * np.abs(a[0]).max()
+
+
+@pytest.mark.parametrize("seed", [7, 23])
+def test_pfonly_batched_parity(skf, oracle_mod, gen, seed):
+    """The Pfaffian-only reduction against the oracle's: interchanges equal,
+    pivots and log|Pf| within rounding, signs and outcomes equal."""
+    mats_h = [gen.batch_matrix(n, seed, b) for b, n in enumerate(SIZES)]
+    mats = [skf.to_device_colmajor(A) if A.shape[0] > 0 else skf.colmajor(0, 0) for A in mats_h]
+    la, sg, info, ipivs, Ts = skf.pfonly_batched(mats)
+    la, sg, info = _host(la), _host(sg), _host(info)
+    for b, (A, n) in enumerate(zip(mats_h, SIZES)):
+        ip_r, T_r, info_r = oracle_mod.pfonly(A) if n > 0 else (np.zeros(0, np.int32), np.zeros(0), 0)
+        la_r, s_r = oracle_mod.logpf_from_factors(n, ip_r, T_r) if n > 0 else (0.0, 1)
+        assert info[b] == info_r, (b, n, info[b], info_r)
+        assert sg[b] == s_r, (b, n)
+        if n % 2 == 1:
+            assert la[b] == -np.inf
+            continue
+        assert oracle_mod.isclose_log(la[b], la_r) <= 1e-12, (b, n, la[b], la_r)
+        if n >= 2:
+            ip, T = _host(ipivs[b]), _host(Ts[b])
+            assert np.array_equal(ip, ip_r), (b, n)
+            assert np.all(T[1::2] == 0.0)
+            assert np.abs(T[0::2] - T_r[0::2]).max() <= 1e-11 * np.abs(T_r[0::2]).max(), (b, n)
+
+
+def test_pfonly_batched_alone_equals_mixed_and_edges(skf, oracle_mod, gen):
+    mats_h = [gen.batch_matrix(n, 29, b) for b, n in enumerate([300, 64, 512, 130, 2, 256, 18])]
+    # an exactly singular matrix (a zero row/column) and a block-diagonal one with a known Pfaffian
+    Z = gen.batch_matrix(40, 29, 99).copy()
+    Z[:, 5] = 0.0
+    Z[5, :] = 0.0
+    d = np.linspace(0.5, 2.0, 20) * np.where(np.arange(20) % 3 == 0, -1.0, 1.0)
+    J = np.zeros((40, 40))
+    for i in range(20):
+        J[2 * i, 2 * i + 1], J[2 * i + 1, 2 * i] = d[i], -d[i]
+    mats_h += [Z, J]
+    mixed = [skf.to_device_colmajor(A) for A in mats_h]
+    la_m, sg_m, info_m, ip_m, _ = skf.pfonly_batched(mixed)
+    la_m, sg_m, info_m = _host(la_m), _host(sg_m), _host(info_m)
+    for b, A in enumerate(mats_h):
+        la_1, sg_1, info_1, ip_1, _ = skf.pfonly_batched([skf.to_device_colmajor(A)])
+        assert _host(la_1)[0] == la_m[b] and _host(sg_1)[0] == sg_m[b] and _host(info_1)[0] == info_m[b]
+        assert np.array_equal(_host(ip_1[0]), _host(ip_m[b]))
+    assert sg_m[-2] == 0 and la_m[-2] == -np.inf and info_m[-2] > 0
+    assert sg_m[-1] == int(np.sign(np.prod(d))) and abs(la_m[-1] - np.log(np.abs(d)).sum()) <= 1e-13 * 40
