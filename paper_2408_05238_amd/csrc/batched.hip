@@ -93,6 +93,63 @@ __device__ inline void block_argmax(Smem& sm, double v, int p, double* ov, int* 
   __syncthreads();
 }
 
+// Delayed trailing update of a panel: A[i,jj] += sum_q (P_q[i] Q_q[jj] - Q_q[i] P_q[jj])
+// for c1 <= jj < i < n, with (P_q, Q_q) = LW[q] the panel's pairs.  Strips of 8
+// columns; thread t owns rows j0+1+t and j0+1+t+256 of strip j0.  The next
+// strip's 16 elements per thread are loaded (clamped addresses) before the
+// current strip is multiplied and stored, so the loads of one strip overlap the
+// arithmetic of the previous one.
+__device__ inline void trailing_update(double* __restrict__ A, int64_t ld, int64_t n, int64_t c1, int npairs,
+                                       const double2 (&LW)[BNP][BR]) {
+  constexpr int SW = 8;
+  static_assert(2 * BT >= BR, "two rows per thread cover a strip");
+  const int tid = threadIdx.x;
+  const int64_t nstrip = (n - c1 + SW - 1) / SW;
+  double cur[2][SW], nxt[2][SW];
+  auto load = [&](int64_t j0, double (&v)[2][SW]) {
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      const int64_t i = j0 + 1 + tid + BT * h;
+#pragma unroll
+      for (int t = 0; t < SW; ++t) {
+        const int64_t jj = j0 + t;
+        v[h][t] = A[(i < n && jj < i) ? i + jj * ld : 0];
+      }
+    }
+  };
+  if (nstrip > 0) load(c1, cur);
+  for (int64_t s = 0; s < nstrip; ++s) {
+    const int64_t j0 = c1 + s * SW;
+    if (s + 1 < nstrip) load(j0 + SW, nxt);
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      const int64_t i = j0 + 1 + tid + BT * h;
+      if (i < n) {
+        double acc[SW];
+#pragma unroll
+        for (int t = 0; t < SW; ++t) acc[t] = 0.0;
+        for (int q = 0; q < npairs; ++q) {
+          const double2 u = LW[q][i];
+#pragma unroll
+          for (int t = 0; t < SW; ++t) {
+            const double2 v = LW[q][min(j0 + t, (int64_t)BR - 1)];
+            acc[t] += u.x * v.y - u.y * v.x;
+          }
+        }
+#pragma unroll
+        for (int t = 0; t < SW; ++t) {
+          const int64_t jj = j0 + t;
+          if (jj < i) A[i + jj * ld] = cur[h][t] + acc[t];
+        }
+      }
+    }
+#pragma unroll
+    for (int h = 0; h < 2; ++h)
+#pragma unroll
+      for (int t = 0; t < SW; ++t) cur[h][t] = nxt[h][t];
+  }
+}
+
 // kFactors: also leave L in place (the Pfaffian-only form needs neither the
 // finished columns of L nor their row interchanges).
 template <bool kFactors>
@@ -255,39 +312,7 @@ __global__ void __launch_bounds__(BT, kWgPerCu) batched_kernel(BatchArgs a) {
       // trailing update: A[i,jj] += sum_q (l'_i w_jj - w_i l'_jj) for i > jj > lo
       const int64_t lo = k0 + nsteps;
       const int npairs = nsteps / 2;
-      if (nsteps % 2 == 0 && n - lo >= 3) {
-        const int64_t c1 = lo + 1;
-        const int64_t m = n - c1;
-        constexpr int SW = 8, NS = 2;  // strip width; strips per pass (their loads in flight together)
-        const int64_t nstrip = (m + SW - 1) / SW;
-        // work items (pass, row): a thread loads all NS x SW elements of its
-        // row in the pass first, then accumulates from LDS, then stores
-        for (int64_t s0 = 0; s0 < nstrip; s0 += NS) {
-          const int64_t j0 = c1 + s0 * SW;
-          for (int64_t i = j0 + 1 + tid; i < n; i += BT) {
-            double cv[NS * SW], acc[NS * SW];
-#pragma unroll
-            for (int t = 0; t < NS * SW; ++t) {
-              const int64_t jj = j0 + t;
-              cv[t] = (jj < i) ? A[i + jj * ld] : 0.0;
-              acc[t] = 0.0;
-            }
-            for (int q = 0; q < npairs; ++q) {
-              const double2 u = sm.LW[q][i];
-#pragma unroll
-              for (int t = 0; t < NS * SW; ++t) {
-                const double2 v = sm.LW[q][min(j0 + t, (int64_t)BR - 1)];
-                acc[t] += u.x * v.y - u.y * v.x;
-              }
-            }
-#pragma unroll
-            for (int t = 0; t < NS * SW; ++t) {
-              const int64_t jj = j0 + t;
-              if (jj < i) A[i + jj * ld] = cv[t] + acc[t];
-            }
-          }
-        }
-      }
+      if (nsteps % 2 == 0 && n - lo >= 3) trailing_update(A, ld, n, lo + 1, npairs, sm.LW);
       __syncthreads();
     }
     // the last column: T[n-2] was produced by the last step (its pivot search saw one row)
@@ -507,37 +532,7 @@ __global__ void __launch_bounds__(BT, kWgPerCu) pfonly_kernel(BatchArgs a) {
         if (status) break;
         // trailing update: A[i,jj] += sum_q (l_i v_jj - v_i l_jj) for i > jj > lo
         const int64_t lo = k0 + 2 * done;
-        if (done == np && n - lo >= 3) {
-          const int64_t c1 = lo + 1;
-          const int64_t m = n - c1;
-          constexpr int SW = 8, NS = 2;
-          const int64_t nstrip = (m + SW - 1) / SW;
-          for (int64_t s0 = 0; s0 < nstrip; s0 += NS) {
-            const int64_t j0 = c1 + s0 * SW;
-            for (int64_t i = j0 + 1 + tid; i < n; i += BT) {
-              double cv[NS * SW], acc[NS * SW];
-#pragma unroll
-              for (int t = 0; t < NS * SW; ++t) {
-                const int64_t jj = j0 + t;
-                cv[t] = (jj < i) ? A[i + jj * ld] : 0.0;
-                acc[t] = 0.0;
-              }
-              for (int q = 0; q < done; ++q) {
-                const double2 u = sm.LW[q][i];
-#pragma unroll
-                for (int t = 0; t < NS * SW; ++t) {
-                  const double2 v = sm.LW[q][min(j0 + t, (int64_t)BR - 1)];
-                  acc[t] += u.x * v.y - u.y * v.x;
-                }
-              }
-#pragma unroll
-              for (int t = 0; t < NS * SW; ++t) {
-                const int64_t jj = j0 + t;
-                if (jj < i) A[i + jj * ld] = cv[t] + acc[t];
-              }
-            }
-          }
-        }
+        if (done == np && n - lo >= 3) trailing_update(A, ld, n, lo + 1, done, sm.LW);
         __syncthreads();
       }
     }
