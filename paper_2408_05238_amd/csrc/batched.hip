@@ -94,59 +94,77 @@ __device__ inline void block_argmax(Smem& sm, double v, int p, double* ov, int* 
 }
 
 // Delayed trailing update of a panel: A[i,jj] += sum_q (P_q[i] Q_q[jj] - Q_q[i] P_q[jj])
-// for c1 <= jj < i < n, with (P_q, Q_q) = LW[q] the panel's pairs.  Strips of 8
-// columns; thread t owns rows j0+1+t and j0+1+t+256 of strip j0.  The next
-// strip's 16 elements per thread are loaded (clamped addresses) before the
-// current strip is multiplied and stored, so the loads of one strip overlap the
-// arithmetic of the previous one.
+// for c1 <= jj < i < n, with (P_q, Q_q) = LW[q] the panel's pairs.  The work is
+// cut into items (strip of 8 columns, row): strip s (first column j0 = c1 + 8s)
+// has the rows j0+1 .. n-1.  Items are numbered strip by strip and dealt to the
+// threads round-robin, so every thread gets the same number of items whatever
+// the triangle's shape, and consecutive threads take consecutive rows of a strip
+// (coalesced).  Each item's 8 elements are loaded (clamped addresses) before the
+// previous item is multiplied and stored.
+constexpr int kStrip = 8;
+
 __device__ inline void trailing_update(double* __restrict__ A, int64_t ld, int64_t n, int64_t c1, int npairs,
                                        const double2 (&LW)[BNP][BR]) {
-  constexpr int SW = 8;
-  static_assert(2 * BT >= BR, "two rows per thread cover a strip");
+  constexpr int SW = kStrip;
   const int tid = threadIdx.x;
-  const int64_t nstrip = (n - c1 + SW - 1) / SW;
-  double cur[2][SW], nxt[2][SW];
-  auto load = [&](int64_t j0, double (&v)[2][SW]) {
+  const int64_t a = n - 1 - c1;                        // rows of strip 0
+  const int64_t ns = (n - c1 + SW - 1) / SW;           // strips
+  // items before strip s: P(s) = s a - SW s (s - 1) / 2
+  auto P = [&](int64_t st) { return st * a - (int64_t)SW * st * (st - 1) / 2; };
+  const int64_t total = P(ns);
+  auto locate = [&](int64_t x, int64_t* j0, int64_t* row) {
+    // largest s with P(s) <= x: root of the quadratic, then corrected
+    const double b = (double)a + SW / 2.0;
+    const double disc = b * b - 2.0 * SW * (double)x;
+    int64_t st = (int64_t)((b - sqrt(disc > 0.0 ? disc : 0.0)) / SW);
+    st = max((int64_t)0, min(st, ns - 1));
+    while (st > 0 && P(st) > x) --st;
+    while (st + 1 < ns && P(st + 1) <= x) ++st;
+    *j0 = c1 + SW * st;
+    *row = *j0 + 1 + (x - P(st));
+  };
+  auto load = [&](int64_t j0, int64_t row, double (&v)[SW]) {
 #pragma unroll
-    for (int h = 0; h < 2; ++h) {
-      const int64_t i = j0 + 1 + tid + BT * h;
-#pragma unroll
-      for (int t = 0; t < SW; ++t) {
-        const int64_t jj = j0 + t;
-        v[h][t] = A[(i < n && jj < i) ? i + jj * ld : 0];
-      }
+    for (int t = 0; t < SW; ++t) {
+      const int64_t jj = j0 + t;
+      v[t] = A[(row < n && jj < row) ? row + jj * ld : 0];
     }
   };
-  if (nstrip > 0) load(c1, cur);
-  for (int64_t s = 0; s < nstrip; ++s) {
-    const int64_t j0 = c1 + s * SW;
-    if (s + 1 < nstrip) load(j0 + SW, nxt);
+  int64_t x = tid;
+  if (x >= total) return;
+  int64_t j0, row;
+  locate(x, &j0, &row);
+  double cur[SW], nxt[SW];
+  load(j0, row, cur);
+  for (;;) {
+    const int64_t xn = x + BT;
+    int64_t j0n = 0, rown = n;
+    if (xn < total) {
+      locate(xn, &j0n, &rown);
+      load(j0n, rown, nxt);
+    }
+    double acc[SW];
 #pragma unroll
-    for (int h = 0; h < 2; ++h) {
-      const int64_t i = j0 + 1 + tid + BT * h;
-      if (i < n) {
-        double acc[SW];
+    for (int t = 0; t < SW; ++t) acc[t] = 0.0;
+    for (int q = 0; q < npairs; ++q) {
+      const double2 u = LW[q][row];
 #pragma unroll
-        for (int t = 0; t < SW; ++t) acc[t] = 0.0;
-        for (int q = 0; q < npairs; ++q) {
-          const double2 u = LW[q][i];
-#pragma unroll
-          for (int t = 0; t < SW; ++t) {
-            const double2 v = LW[q][min(j0 + t, (int64_t)BR - 1)];
-            acc[t] += u.x * v.y - u.y * v.x;
-          }
-        }
-#pragma unroll
-        for (int t = 0; t < SW; ++t) {
-          const int64_t jj = j0 + t;
-          if (jj < i) A[i + jj * ld] = cur[h][t] + acc[t];
-        }
+      for (int t = 0; t < SW; ++t) {
+        const double2 v = LW[q][min(j0 + t, (int64_t)BR - 1)];
+        acc[t] += u.x * v.y - u.y * v.x;
       }
     }
 #pragma unroll
-    for (int h = 0; h < 2; ++h)
+    for (int t = 0; t < SW; ++t) {
+      const int64_t jj = j0 + t;
+      if (jj < row) A[row + jj * ld] = cur[t] + acc[t];
+    }
+    if (xn >= total) break;
+    x = xn;
+    j0 = j0n;
+    row = rown;
 #pragma unroll
-      for (int t = 0; t < SW; ++t) cur[h][t] = nxt[h][t];
+    for (int t = 0; t < SW; ++t) cur[t] = nxt[t];
   }
 }
 
