@@ -95,13 +95,13 @@ __device__ inline void block_argmax(Smem& sm, double v, int p, double* ov, int* 
 
 // Delayed trailing update of a panel: A[i,jj] += sum_q (P_q[i] Q_q[jj] - Q_q[i] P_q[jj])
 // for c1 <= jj < i < n, with (P_q, Q_q) = LW[q] the panel's pairs.  The work is
-// cut into items (strip of 8 columns, row): strip s (first column j0 = c1 + 8s)
+// cut into items (strip of 4 columns, row): strip s (first column j0 = c1 + 4s)
 // has the rows j0+1 .. n-1.  Items are numbered strip by strip and dealt to the
 // threads round-robin, so every thread gets the same number of items whatever
 // the triangle's shape, and consecutive threads take consecutive rows of a strip
-// (coalesced).  Each item's 8 elements are loaded (clamped addresses) before the
+// (coalesced).  Each item's 4 elements are loaded (clamped addresses) before the
 // previous item is multiplied and stored.
-constexpr int kStrip = 8;
+constexpr int kStrip = 4;
 
 __device__ inline void trailing_update(double* __restrict__ A, int64_t ld, int64_t n, int64_t c1, int npairs,
                                        const double2 (&LW)[BNP][BR]) {
