@@ -315,6 +315,20 @@ __global__ void __launch_bounds__(kPanelThreads) panel_kernel(PanelParams P) {
         z1 = ld_word(lwp + 1);
       };
       load_all();
+      // (E) multipliers below row k+1, alpha at row k+1: formed while the
+      // gather and the coefficient words are in flight
+      if (mine) {
+        double val = 0.0;
+        bool wr = true;
+        if (psi >= k + 2) val = (alpha != 0.0) ? cur / alpha : 0.0;
+        else if (psi == (int32_t)r) val = alpha;
+        else wr = false;
+        if (wr) {
+          if (ph == 0) sm.Le[j][lane] = val;
+          else sm.LW[j][lane].x = val;
+        }
+        if (ph == 0) lj = wr ? val : 0.0;
+      }
       uint64_t t0 = 0;
       for (int it = 0;; ++it) {
         const bool ok = (!hasA | ((tag_of(a0) == tA) & (tag_of(a1) == tA))) &
@@ -341,20 +355,6 @@ __global__ void __launch_bounds__(kPanelThreads) panel_kernel(PanelParams P) {
       }
     }
     const double gat = below ? (lowr ? graw : -graw) : 0.0;
-
-    // (E) multipliers below row k+1, alpha at row k+1
-    if (mine) {
-      double val = 0.0;
-      bool wr = true;
-      if (psi >= k + 2) val = (alpha != 0.0) ? cur / alpha : 0.0;
-      else if (psi == (int32_t)r) val = alpha;
-      else wr = false;
-      if (wr) {
-        if (ph == 0) sm.Le[j][lane] = val;
-        else sm.LW[j][lane].x = val;
-      }
-      if (ph == 0) lj = wr ? val : 0.0;
-    }
 
     // skew GEMV with the pivot row over the pairs so far: eight pairs per pass,
     // their LDS reads issued together (coefficients of pairs >= j are zero)
