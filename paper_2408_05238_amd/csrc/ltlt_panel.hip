@@ -356,21 +356,21 @@ __global__ void __launch_bounds__(kPanelThreads) panel_kernel(PanelParams P) {
     }
     const double gat = below ? (lowr ? graw : -graw) : 0.0;
 
-    // skew GEMV with the pivot row over the pairs so far: eight pairs per pass,
-    // their LDS reads issued together (coefficients of pairs >= j are zero)
+    // skew GEMV with the pivot row over the pairs so far: sixteen pairs per
+    // pass, their LDS reads issued together (coefficients of pairs >= j are zero)
     double corr = 0.0;
     {
       double c0 = 0.0, c1 = 0.0, c2 = 0.0, c3 = 0.0;
-      const int jr = (j + 7) & ~7;
-      for (int q = 0; q < jr; q += 8) {
-        double2 a[8], c[8];
+      const int jr = (j + 15) & ~15;
+      for (int q = 0; q < jr; q += 16) {
+        double2 a[16], c[16];
 #pragma unroll
-        for (int t = 0; t < 8; ++t) {
+        for (int t = 0; t < 16; ++t) {
           a[t] = sm.LW[q + t][lane];
           c[t] = sm.coef[q + t];
         }
 #pragma unroll
-        for (int t = 0; t < 8; t += 4) {
+        for (int t = 0; t < 16; t += 4) {
           c0 += a[t].x * c[t].y - a[t].y * c[t].x;
           c1 += a[t + 1].x * c[t + 1].y - a[t + 1].y * c[t + 1].x;
           c2 += a[t + 2].x * c[t + 2].y - a[t + 2].y * c[t + 2].x;
