@@ -48,9 +48,11 @@ constexpr int kPanelThreads = 64;
 // kRecStride words apart; the candidate's l0 (read only from the winner) is kept
 // in a separate pair of 32-bit-tagged words.
 constexpr int kRecStride = 16;
-// Every record is written in kRecCopies copies; workgroup g polls copy g % kRecCopies
-// (consecutive workgroups are dispatched round-robin over the XCDs), so each
-// record line has G / kRecCopies readers instead of G.
+// Every record and l0 pair is written in kRecCopies copies; workgroup g reads
+// copy g % kRecCopies (consecutive workgroups are dispatched round-robin over
+// the XCDs), so each line has G / kRecCopies readers instead of G.  (Copies of
+// the coefficient mirror were measured too: the extra stores at every pair end
+// delay the next loads, which wait behind them, and the step got slower.)
 constexpr int kRecCopies = 8;
 constexpr uint32_t kFlagNonFinite = 1u << 30;
 constexpr uint32_t kFlagNoCand = 1u << 31;
@@ -176,8 +178,9 @@ __global__ void __launch_bounds__(kPanelThreads) panel_kernel(PanelParams P) {
     const int ph = si & 1;
     const uint32_t tag = P.tag_base + (uint32_t)si + 1u;
     const uint32_t t16 = tag16(tag);
-    uint64_t* const recs0 = P.rec + (size_t)(si & 1) * G * (kRecCopies * kRecStride + 2);
-    uint64_t* const lzs = recs0 + (size_t)kRecCopies * G * kRecStride;  // l0 words of record g at 2g, 2g+1
+    uint64_t* const recs0 = P.rec + (size_t)(si & 1) * G * kRecCopies * (kRecStride + 2);
+    // l0 words of record g, copy c, at 2 (c G + g) and the next word
+    uint64_t* const lzs = recs0 + (size_t)kRecCopies * G * kRecStride;
     uint64_t* const recs = recs0 + (size_t)(g % kRecCopies) * G * kRecStride;  // the copy this workgroup reads
 
     // (A) local candidate: this lane's slot if its current index is >= k+1
@@ -198,12 +201,14 @@ __global__ void __launch_bounds__(kPanelThreads) panel_kernel(PanelParams P) {
       const uint64_t th = (uint64_t)t16 << 48;
       const uint64_t w0 = th | ((uint64_t)meta << 16) | (mag >> 47);
       const uint64_t w1 = th | ((cb >> 63) << 47) | (mag & kLow47);
-      // lanes 0 .. 2 kRecCopies - 1: word lane % 2 of copy lane / 2; the next two lanes: l0
+      // lanes 0 .. 2 kRecCopies - 1: word lane % 2 of record copy lane / 2; the next
+      // 2 kRecCopies lanes: word lane % 2 of l0 copy (lane - kW) / 2
       constexpr int kW = 2 * kRecCopies;
-      const uint64_t v = (lane < kW) ? ((lane & 1) ? w1 : w0) : (lane == kW) ? mk(tag, hi32(lz)) : mk(tag, lo32(lz));
-      uint64_t* const dstw = (lane < kW) ? recs0 + ((size_t)(lane >> 1) * G + g) * kRecStride + (lane & 1)
-                                         : lzs + 2 * g + (lane - kW);
-      if (lane < kW + 2) st_word(dstw, v);
+      const int cw = (lane < kW ? lane : lane - kW) >> 1;
+      const uint64_t v = (lane < kW) ? ((lane & 1) ? w1 : w0) : ((lane & 1) ? mk(tag, lo32(lz)) : mk(tag, hi32(lz)));
+      uint64_t* const dstw = (lane < kW) ? recs0 + ((size_t)cw * G + g) * kRecStride + (lane & 1)
+                                         : lzs + 2 * ((size_t)cw * G + g) + (lane & 1);
+      if (lane < 2 * kW) st_word(dstw, v);
     }
 
     // (C) every workgroup's record (lane t reads records t, t+64, ...) -> global pivot.
@@ -308,7 +313,7 @@ __global__ void __launch_bounds__(kPanelThreads) panel_kernel(PanelParams P) {
       const uint32_t tB = P.tag_base + 2u * (uint32_t)((lane + 64) >> 1) + 2u;
       const bool hasA = lane < nd, hasB = kTwo && lane + 64 < nd;
       const int ia = 2 * lane, ib = kTwo ? 2 * (lane + 64) : 2 * lane;
-      const uint64_t* lwp = lzs + 2 * gs;
+      const uint64_t* lwp = lzs + 2 * ((size_t)(g % kRecCopies) * G + gs);
       uint64_t a0, a1, b0, b1, z0, z1;
       auto load_all = [&]() {
         a0 = ld_word(wm + ia);
@@ -461,7 +466,7 @@ int launch_panel(const PanelParams& p, hipStream_t s) {
   return SKF_ENOTIMPL;
 }
 
-size_t panel_record_words(int G) { return (size_t)2 * G * (kRecCopies * kRecStride + 2); }
+size_t panel_record_words(int G) { return (size_t)2 * G * kRecCopies * (kRecStride + 2); }
 
 size_t panel_mirror_words(int G, int nb) { return (size_t)G * 64 * (nb / 2) * 4; }
 
