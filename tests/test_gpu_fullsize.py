@@ -1,0 +1,94 @@
+"""Parity at the full benchmark size: n = 16384 FP64 with seeds 2, 3 and 4, in
+the launch configuration bench.py times (skf.ltlt, default block size).
+
+The reference is the oracle's own result for the same seeded input, stored in
+tests/golden/ltlt_n16384_s{seed}.npz by tests/golden/make_golden.py (which calls
+only the generator and the oracle): the interchanges are compared bit for bit,
+T and log|Pf| within the stated tolerances.  The reconstruction residual
+||P A P^T - L T L^T||_F / (n ||A||_F) is estimated on the device in FP64 with
+Gaussian probe vectors (E ||R v||^2 = ||R||_F^2 for v with independent N(0,1)
+entries), the interchanges applied on the host.
+"""
+from __future__ import annotations
+
+import os
+
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+N = 16384
+T_TOL = 1e-11        # max |T - T_oracle| / max |T_oracle|
+LOGPF_TOL = 1e-12    # |d log|Pf|| / max(1, |log|Pf||)
+RECON_TOL = 1e-13    # ||PAP^T - LTL^T||_F / (n ||A||_F)
+
+
+@pytest.fixture(scope="module")
+def skf():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2408_05238_amd import skf as s
+    s.lib()
+    return s
+
+
+def _apply_P(x, ipiv, transpose=False):
+    """P x (interchanges j <-> ipiv[j] for j = 1..n-1 in order) or P^T x (reverse order)."""
+    x = x.copy()
+    js = range(len(ipiv) - 1, 0, -1) if transpose else range(1, len(ipiv))
+    for j in js:
+        p = int(ipiv[j])
+        if p != j:
+            x[[j, p]] = x[[p, j]]
+    return x
+
+
+@pytest.mark.parametrize("seed", [2, 3, 4])
+def test_ltlt_n16384_against_stored_oracle(skf, seed):
+    import torch
+    from paper_2408_05238_amd import inputs
+    path = os.path.join(HERE, "golden", f"ltlt_n{N}_s{seed}.npz")
+    assert os.path.exists(path), path
+    g = np.load(path)
+    A = inputs.skew_gaussian(N, seed, inputs.STREAM_A)
+    dA = skf.to_device_colmajor(A)
+    del A
+    A0 = dA.clone()
+    ipiv, T, info = skf.ltlt(dA)
+    torch.cuda.synchronize()
+    assert info == int(g["info"]) == 0
+    ip = ipiv.cpu().numpy()
+    assert np.array_equal(ip, g["ipiv"]), int(np.argmax(ip != g["ipiv"]))
+    Th = T.cpu().numpy()[:N - 1]
+    assert np.abs(Th - g["T"]).max() <= T_TOL * np.abs(g["T"]).max()
+    la, sg = skf.logpf_from_factors(N, ipiv, T)
+    assert sg == int(g["sign"])
+    assert abs(la - float(g["logabs"])) <= LOGPF_TOL * max(1.0, abs(float(g["logabs"])))
+
+    # reconstruction residual by probes: R v = P A P^T v - L T L^T v
+    S = torch.tril(A0, -1)                 # A = S - S^T
+    del A0
+    a_fro = float(torch.sqrt(2.0 * (S * S).sum()))
+    Ls = torch.tril(dA, -2)[:, :-1]        # column j-1 holds L[:, j] below its diagonal, j >= 1
+    t = T[:N - 1]
+    rng = np.random.default_rng(1000 + seed)
+    nprobe = 8
+    acc = 0.0
+    for _ in range(nprobe):
+        v = rng.standard_normal(N)
+        w = torch.from_numpy(_apply_P(v, ip, transpose=True)).to(dA.device)
+        y = (S @ w - S.T @ w).cpu().numpy()
+        y1 = _apply_P(y, ip)
+        vd = torch.from_numpy(v).to(dA.device)
+        u = vd.clone()
+        u[1:] += Ls.T @ vd                 # L^T v
+        tu = torch.zeros_like(u)
+        tu[1:] += t * u[:-1]               # T u: sub-diagonal t, super-diagonal -t
+        tu[:-1] -= t * u[1:]
+        z = tu + Ls @ tu[1:]               # L (T L^T v)
+        acc += float(np.sum((y1 - z.cpu().numpy()) ** 2))
+    rel = np.sqrt(acc / nprobe) / (N * a_fro)
+    assert rel <= RECON_TOL, rel
