@@ -93,6 +93,28 @@ int skf_ltlt(skf_int n, double* A, skf_int lda, int32_t* ipiv, double* T, int pr
              void* work, size_t lwork, int* dinfo, void* stream);
 
 /*
+ * Pfaffian-only reduction of one matrix (the blocked form of the reduction
+ * described at skf_pfonly_batched: Parlett-Reid elimination steps at even k
+ * only, pivot on column k, interchange of rows/columns k+1 and p, skew rank-2
+ * term l v^T - v l^T on A[k+2:, k+2:]).  Panels of nb/2 such steps run on the
+ * device with the pivot search as in skf_ltlt; their nb/2 (l, v) pairs form one
+ * skew rank-nb trailing update on the matrix cores.  Half as many pivot
+ * searches as skf_ltlt for the same flops; no L is formed.
+ *   n, lda, prec, work, lwork, dinfo, stream  as skf_ltlt (same workspace size)
+ *   A      device, lda x n: used as scratch, contents unspecified on return
+ *   ipiv   device int32[n], output: ipiv[k+1] (k even) = step k's interchange,
+ *          the other entries j
+ *   T      device double[max(n-1,1)], output: T[k] (k even) = pivot of step k,
+ *          the odd entries 0
+ * Pf(A) = (-1)^{s + n/2} prod_{k even} T[k] (s = #{j : ipiv[j] != j}), so
+ * skf_logpf_from_factors applies.  Odd n: ipiv = identity, T = 0, info = n.
+ * Otherwise info as skf_ltlt (1 + the first even k with T[k] = 0, or a
+ * negative status).  Returns 0, the info (dinfo NULL) or an argument error.
+ */
+int skf_pfonly(skf_int n, double* A, skf_int lda, int32_t* ipiv, double* T, int prec, void* work,
+               size_t lwork, int* dinfo, void* stream);
+
+/*
  * log|Pf(A)| and sign(Pf(A)) from factors produced by skf_ltlt:
  * log|Pf| = sum_{k even} log|T[k]| (fixed summation order), sign =
  * (-1)^{s + n/2} prod_{k even} sgn T[k], s = #{j : ipiv[j] != j}.
@@ -106,7 +128,8 @@ int skf_logpf_from_factors(skf_int n, const int32_t* ipiv, const double* T, doub
  * workspace plus room for ipiv and T). */
 size_t skf_logpf_workspace(skf_int n, int prec);
 
-/* Factor (destroying A) and reduce to log|Pf| and sign; outputs are device scalars. */
+/* Reduce A by skf_pfonly (destroying A), then to log|Pf| and sign; outputs are
+ * device scalars. */
 int skf_logpf(skf_int n, double* A, skf_int lda, double* logabs, int* sign, int prec, void* work,
               size_t lwork, int* dinfo, void* stream);
 

@@ -161,6 +161,22 @@ int skf_ltlt(skf_int n, double* A, skf_int lda, int32_t* ipiv, double* T, int pr
   return finish_sync(rc, dinfo_int, s);
 }
 
+int skf_pfonly(skf_int n, double* A, skf_int lda, int32_t* ipiv, double* T, int prec, void* work,
+               size_t lwork, int* dinfo, void* stream) {
+  int rc = check_ltlt_args(n, A, lda, ipiv, T, prec, work, lwork);
+  if (rc) return rc;
+  hipStream_t s = (hipStream_t)stream;
+  if (n == 0) {
+    if (dinfo) return launch_fill_i32(dinfo, 1, 0, s);
+    return 0;
+  }
+  const size_t core = ltlt_workspace_bytes(n, prec);
+  int* dinfo_int = (int*)((char*)work + core);
+  rc = run_pfonly(n, A, lda, ipiv, T, prec, work, core, dinfo ? dinfo : dinfo_int, s);
+  if (dinfo) return rc;
+  return finish_sync(rc, dinfo_int, s);
+}
+
 int skf_logpf_from_factors(skf_int n, const int32_t* ipiv, const double* T, double* logabs, int* sign,
                            void* stream) {
   if (n < 0) return -1;
@@ -171,7 +187,8 @@ int skf_logpf_from_factors(skf_int n, const int32_t* ipiv, const double* T, doub
   return launch_logpf(n, ipiv, T, logabs, sign, nullptr, (hipStream_t)stream);
 }
 
-// Factor, then reduce; ipiv and T live at the end of the caller's workspace.
+// Pfaffian-only reduction, then the product; ipiv and T live at the end of the
+// caller's workspace.
 static size_t pf_extra(skf_int n) { return align_up(sizeof(int32_t) * (n + 1), 256) + align_up(sizeof(double) * (n + 1), 256); }
 
 static int logpf_common(skf_int n, double* A, skf_int lda, double* logabs, int* sign, double* pf, int prec,
@@ -190,7 +207,7 @@ static int logpf_common(skf_int n, double* A, skf_int lda, double* logabs, int* 
   if (n > 0) {
     const size_t core = ltlt_workspace_bytes(n, prec);
     int* dinfo_int = (int*)((char*)work + core);
-    rc = run_ltlt(n, A, lda, ipiv, T, prec, work, core, dinfo ? dinfo : dinfo_int, s);
+    rc = run_pfonly(n, A, lda, ipiv, T, prec, work, core, dinfo ? dinfo : dinfo_int, s);
     if (rc) return rc;
     rc = launch_logpf(n, ipiv, T, logabs, sign, pf, s);
     if (rc) return rc;

@@ -19,6 +19,12 @@ __global__ void fill_i32_kernel(int32_t* p, size_t count, int32_t v) {
     p[i] = v;
 }
 
+__global__ void iota_i32_kernel(int32_t* p, size_t count) {
+  for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < count;
+       i += (size_t)gridDim.x * blockDim.x)
+    p[i] = (int32_t)i;
+}
+
 // W[i, k0+c] = Lbuf[i, c] for rows below the subdiagonal of column k0+c.
 __global__ void copy_panel_L_kernel(int64_t n, int64_t k0, int nsteps, const double* __restrict__ Lbuf,
                                     double* __restrict__ W, int64_t ldw) {
@@ -142,6 +148,13 @@ int launch_fill_u64(uint64_t* p, size_t count, uint64_t v, hipStream_t s) {
   if (!count) return 0;
   hipLaunchKernelGGL(fill_u64_kernel, dim3(grid_for(count, 256)), dim3(256), 0, s, p, count, v);
   SKF_CHECK_LAUNCH("fill_u64");
+  return 0;
+}
+
+int launch_iota_i32(int32_t* p, size_t count, hipStream_t s) {
+  if (count == 0) return 0;
+  hipLaunchKernelGGL(iota_i32_kernel, dim3(grid_for(count, 256)), dim3(256), 0, s, p, count);
+  SKF_CHECK_LAUNCH("iota_i32");
   return 0;
 }
 

@@ -71,6 +71,7 @@ static size_t carve(LtltWork* w, char* base, int64_t n, int nb) {
   w->sigma = (int32_t*)take(sizeof(int32_t) * (size_t)std::max<int64_t>(np, 1) * n);
   w->rec = (uint64_t*)take(sizeof(uint64_t) * panel_record_words(gmax));
   w->mirror = (uint64_t*)take(sizeof(uint64_t) * panel_mirror_words(gmax, nb));
+  w->front = (uint64_t*)take(sizeof(uint64_t) * 16);
   w->Lscr = (double*)take(sizeof(double) * panel_scratch_doubles(gmax, nb));
   w->status = (int*)take(256);
   w->bytes = off;
@@ -156,6 +157,71 @@ int run_ltlt(int64_t n, double* A, int64_t lda, int32_t* ipiv, double* T, int pr
   }
   if ((rc = launch_compose_sigma(n, (int)np, w.pis, w.sigma, s))) return rc;
   if ((rc = launch_final_L(n, nb, (int)np, w.W, n, w.sigma, A, lda, s))) return rc;
+  if (dinfo_dev) return launch_ltlt_info(n, T, w.status, dinfo_dev, s);
+  return 0;
+}
+
+// Pfaffian-only reduction: the same panel/update loop with steps at even k only.
+// Panel P covers k0 = P*nb .. k0+nb-1 with nb/2 steps; each step's pair (l, v)
+// enters the same skew rank-nb trailing update.  No L is kept, so there is no
+// write-back or final permutation of L; ipiv starts as the identity (the even
+// entries stay so) and T as zero (the odd entries stay so).
+int run_pfonly(int64_t n, double* A, int64_t lda, int32_t* ipiv, double* T, int prec, void* work,
+               size_t lwork, int* dinfo_dev, hipStream_t s) {
+  if (n == 0) return dinfo_dev ? launch_fill_i32(dinfo_dev, 1, 0, s) : 0;
+  const int nb = ltlt_plan_nb(n);
+  if (nb < 0) return SKF_ENOTIMPL;
+  LtltWork w = ltlt_carve(work, n, prec);
+  if (lwork < w.bytes) return SKF_EWORK;
+  int rc;
+  if ((rc = launch_iota_i32(ipiv, (size_t)n, s))) return rc;
+  if (n > 1 && (rc = launch_fill_u64((uint64_t*)T, (size_t)(n - 1), 0, s))) return rc;
+  if (n % 2 == 1) return dinfo_dev ? launch_fill_i32(dinfo_dev, 1, (int32_t)n, s) : 0;
+  const int gmax = (int)std::max<int64_t>(1, (n - 1 + slots() - 1) / slots());
+  if ((rc = launch_fill_i32(w.status, 1, 0, s))) return rc;
+  if ((rc = launch_fill_u64(w.rec, panel_record_words(gmax), 0, s))) return rc;
+  if ((rc = launch_fill_u64(w.mirror, panel_mirror_words(gmax, nb), 0, s))) return rc;
+  if ((rc = launch_fill_u64(w.front, 16, 0, s))) return rc;
+
+  const int64_t np = (n + nb - 1) / nb;
+  double* buf[2] = {A, w.W};
+  const int64_t ldb[2] = {lda, n};
+  for (int64_t P = 0; P < np; ++P) {
+    const int64_t k0 = P * nb;
+    const int nsteps = (int)std::min<int64_t>(nb / 2, (n - k0) / 2);
+    PanelParams pp{};
+    pp.n = n;
+    pp.k0 = k0;
+    pp.nsteps = nsteps;
+    pp.nb = nb;
+    if ((rc = ltlt_panel_grid(n - k0 - 1, nb, &pp.G, &pp.S))) return rc;
+    pp.src = buf[P % 2];
+    pp.ld = ldb[P % 2];
+    pp.Lp = w.Lp;
+    pp.Wp = w.Wp;
+    pp.NLp = w.NLp;
+    pp.pi = w.pis;
+    pp.cnext = w.cnext;
+    pp.T = T;
+    pp.ipiv = ipiv;
+    pp.rec = w.rec;
+    pp.mirror = w.mirror;
+    pp.front = w.front;
+    pp.status = w.status;
+    pp.tag_base = (uint32_t)k0;
+    prof_begin(s);
+    if ((rc = launch_panel_pf(pp, s))) return rc;
+    prof_end(s, 0, 0.0);
+    const int64_t lo = k0 + 2 * (int64_t)nsteps;
+    if (lo < n) {  // the panel did not reach the last step (k = n-2): n - lo >= 2 and even
+      prof_begin(s);
+      rc = launch_skr2k_perm(n, lo, nsteps, buf[P % 2], ldb[P % 2], buf[(P + 1) % 2], ldb[(P + 1) % 2],
+                             pp.pi, w.Lp, w.Wp, w.NLp, n, w.cnext, prec == SKF_PREC_F32_TRAILING, s);
+      if (rc) return rc;
+      const double mt = (double)(n - lo);
+      prof_end(s, 1, 2.0 * (double)nsteps * mt * (mt - 1.0));
+    }
+  }
   if (dinfo_dev) return launch_ltlt_info(n, T, w.status, dinfo_dev, s);
   return 0;
 }

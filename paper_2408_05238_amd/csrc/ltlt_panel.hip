@@ -439,6 +439,334 @@ __global__ void __launch_bounds__(kPanelThreads) panel_kernel(PanelParams P) {
   if ((P.nsteps & 1) == 0 && psi >= lo + 1) P.cnext[psi] = cur;
 }
 
+// ---------------------------------------------------------------------------
+// Pfaffian-only panel: NB/2 elimination steps at even k only (k = k0, k0+2, ...),
+// each giving one pair (l, v): l = multipliers of column k, v = column k+1 after
+// the interchange, and the trailing change l v^T - v l^T.  The machinery is the
+// full panel's (slots, relabelling, records, mirrors, gathers from the
+// panel-start matrix S plus the panel's pairs); what differs is the next pivot
+// column: it is column k+2, i.e. the row y standing at index k+2 after the
+// interchange (the old row k+1 when p = k+2, else the old row k+2), which is in
+// general not the winner.  So the owners of the rows at indices k+1 and k+2
+// publish (workgroup, slot, current value) in two tagged front entries beside
+// the records, and after the exchange every workgroup fetches the coefficient
+// rows of both x (the winner) and y, gathers S(., x) and S(., y) for its slots,
+// and forms, per slot i with index >= k+2:
+//   l_i = c_i / alpha,  v_i = S(i, x) + sum_{q<s} (l_q[i] v_q[x] - v_q[i] l_q[x]),
+// the scalars l_y = c_y / alpha and v_y = S(y, x) + sum_{q<s} (l_q[y] v_q[x] - v_q[y] l_q[x]),
+// and the next column  c'_i = S(i, y) + sum_{q<s} (l_q[i] v_q[y] - v_q[i] l_q[y])
+//                             + l_i v_y - v_i l_y.
+// Pair q's mirror words carry the tag of step q.  No L is produced.
+template <int NB>
+struct PanelPfSmem {
+  double2 LW[NB / 2][64];  // (l, v) of each step, per slot
+  double2 cx[NB / 2];      // the winner's (l, v) of the steps so far
+  double2 cy[NB / 2];      // the row at index k+2: its (l, v) of the steps so far
+};
+
+template <int NB, int NQ>
+__global__ void __launch_bounds__(kPanelThreads) panel_pf_kernel(PanelParams P) {
+  constexpr int NP = NB / 2;
+  __shared__ PanelPfSmem<NB> sm;
+
+  const int lane = threadIdx.x;
+  const int g = blockIdx.x;
+  const int64_t n = P.n, k0 = P.k0, ld = P.ld;
+  const double* __restrict__ src = P.src;
+  const int64_t rowbase = k0 + 1 + (int64_t)g * P.S;
+  const int nslots = (int)max((int64_t)0, min((int64_t)P.S, n - rowbase));
+  const int G = P.G;
+  const bool mine = lane < nslots;
+  if (g == 0)
+    for (int64_t i = lane; i <= k0; i += kPanelThreads) P.pi[i] = (int32_t)i;
+  if (*P.status != 0) {
+    if (mine) P.pi[rowbase + lane] = (int32_t)(rowbase + lane);
+    return;
+  }
+  uint64_t* const my_mirror = P.mirror + ((size_t)g * 64 + lane) * NP * 4;
+
+  for (int q = 0; q < NP; ++q) sm.LW[q][lane] = make_double2(0.0, 0.0);
+  if (lane < NP) {
+    sm.cx[lane] = make_double2(0.0, 0.0);
+    sm.cy[lane] = make_double2(0.0, 0.0);
+  }
+
+  int32_t psi = mine ? (int32_t)(rowbase + lane) : INT32_MAX;
+  const int32_t hbm = mine ? (int32_t)(rowbase + lane) : 0;
+  double cur = mine ? src[rowbase + lane + k0 * ld] : 0.0;
+  int stop = 0;
+  int done = 0;  // steps that produced a pair
+
+  for (int si = 0; si < P.nsteps; ++si) {
+    const int64_t k = k0 + 2 * si;
+    const int64_t r = k + 1;
+    const bool last = k + 2 > n - 1;  // k = n-2: pivot only
+    const uint32_t tag = P.tag_base + (uint32_t)si + 1u;
+    const uint32_t t16 = tag16(tag);
+    uint64_t* const recs0 = P.rec + (size_t)(si & 1) * G * kRecCopies * (kRecStride + 2);
+    uint64_t* const recs = recs0 + (size_t)(g % kRecCopies) * G * kRecStride;
+    uint64_t* const front = P.front + (size_t)(si & 1) * 8;  // entry e (index k+1+e) at 4e: ws, hi, lo
+
+    // (A) local candidate
+    const bool act = mine && psi >= k + 1;
+    const bool nonfin = __any(act && !isfinite(cur));
+    const int bs = wave_argbest(fabs(cur), (uint32_t)psi, act);
+
+    // (B) record (as the full panel) and, by the owners of indices k+1 and k+2,
+    // the front entries (workgroup << 6 | slot, current value)
+    {
+      const int owner = (bs >= 0) ? bs : 0;
+      const double cval = rld(cur, owner);
+      const uint32_t meta = nonfin ? kFlagNonFinite
+                                   : (bs < 0 ? kFlagNoCand : (rl32((uint32_t)psi, owner) | ((uint32_t)owner << 24)));
+      const uint64_t cb = (uint64_t)__double_as_longlong(cval);
+      const uint64_t mag = cb & ~(1ull << 63);
+      const uint64_t th = (uint64_t)t16 << 48;
+      const uint64_t w0 = th | ((uint64_t)meta << 16) | (mag >> 47);
+      const uint64_t w1 = th | ((cb >> 63) << 47) | (mag & kLow47);
+      constexpr int kW = 2 * kRecCopies;
+      const uint64_t v = (lane & 1) ? w1 : w0;
+      uint64_t* const dstw = recs0 + ((size_t)(lane >> 1) * G + g) * kRecStride + (lane & 1);
+      if (lane < kW) st_word(dstw, v);
+      const int64_t e = (int64_t)psi - (k + 1);
+      if (mine && (e == 0 || (e == 1 && !last))) {
+        uint64_t* fe = front + 4 * e;
+        st_word(fe, mk(tag, ((uint32_t)g << 6) | (uint32_t)lane));
+        st_word(fe + 1, mk(tag, hi32(cur)));
+        st_word(fe + 2, mk(tag, lo32(cur)));
+      }
+    }
+
+    // (C) records -> global pivot; front entries (every lane reads the same words)
+    double gv = -1.0, gc = 0.0;
+    uint32_t gp = kNoCand, gslot = 0;
+    int gs = -1;
+    bool bad = false, tout = false;
+    uint64_t f0a = 0, f0b = 0, f0c = 0, f1a = 0, f1b = 0, f1c = 0;
+    {
+      uint64_t w[NQ][2];
+      const uint64_t* rp[NQ];
+#pragma unroll
+      for (int q = 0; q < NQ; ++q) {
+        const int rr = lane + 64 * q;
+        rp[q] = recs + (size_t)(rr < G ? rr : 0) * kRecStride;
+      }
+      auto load_recs = [&]() {
+#pragma unroll
+        for (int q = 0; q < NQ; ++q) {
+          w[q][0] = ld_word(rp[q]);
+          w[q][1] = ld_word(rp[q] + 1);
+        }
+        f0a = ld_word(front);
+        f0b = ld_word(front + 1);
+        f0c = ld_word(front + 2);
+        f1a = ld_word(front + 4);
+        f1b = ld_word(front + 5);
+        f1c = ld_word(front + 6);
+      };
+      load_recs();
+      uint64_t t0 = 0;
+      for (int it = 0;; ++it) {
+        bool ok = (tag_of(f0a) == tag) & (tag_of(f0b) == tag) & (tag_of(f0c) == tag);
+        ok &= last | ((tag_of(f1a) == tag) & (tag_of(f1b) == tag) & (tag_of(f1c) == tag));
+#pragma unroll
+        for (int q = 0; q < NQ; ++q) {
+          const bool need = lane + 64 * q < G;
+          ok &= !need | ((tag16_of(w[q][0]) == t16) & (tag16_of(w[q][1]) == t16));
+        }
+        if (__all(ok)) break;
+        if ((it & 31) == 0) {
+          const uint64_t now = wall_clock64();
+          if (it == 0) t0 = now;
+          else if (now - t0 > kWaitTicks) {
+            tout = true;
+            break;
+          }
+        }
+        load_recs();
+      }
+#pragma unroll
+      for (int q = 0; q < NQ; ++q) {
+        const int rr = lane + 64 * q;
+        const uint32_t meta = (uint32_t)(w[q][0] >> 16);
+        const bool use = rr < G && !tout;
+        bad |= use && (meta & kFlagNonFinite);
+        if (use && !(meta & (kFlagNonFinite | kFlagNoCand))) {
+          const uint64_t mag = ((w[q][0] & 0xFFFFull) << 47) | (w[q][1] & kLow47);
+          const double a = __longlong_as_double((long long)mag);
+          const uint32_t ps = meta & 0xFFFFFFu;
+          if (better(a, ps, gv, gp)) {
+            gv = a;
+            gc = __longlong_as_double((long long)(mag | (((w[q][1] >> 47) & 1ull) << 63)));
+            gp = ps;
+            gs = rr;
+            gslot = meta >> 24 & 63u;
+          }
+        }
+      }
+    }
+    tout = __any(tout);
+    bad = __any(bad);
+    const int wl = wave_argbest(gv, gp, gs >= 0);
+    stop = tout ? 4 : (bad ? 2 : (wl < 0 ? 4 : 0));
+    if (stop) break;
+
+    const double alpha = rld(gc, wl);
+    gp = rl32(gp, wl);
+    gs = (int)rl32((uint32_t)gs, wl);
+    const int wslot = (int)rl32(gslot, wl);
+    const int64_t hx = k0 + 1 + (int64_t)gs * P.S + wslot;
+    const int64_t pidx = gp;
+
+    // the row at index k+2 after the interchange: the old row k+1 when p = k+2
+    const bool yfrom0 = pidx == k + 2;
+    const uint32_t fws = (uint32_t)(yfrom0 ? f0a : f1a);
+    const int ygs = (int)(fws >> 6), yslot = (int)(fws & 63u);
+    const double ycur = yfrom0 ? from32((uint32_t)f0b, (uint32_t)f0c) : from32((uint32_t)f1b, (uint32_t)f1c);
+    const int64_t hy = k0 + 1 + (int64_t)ygs * P.S + yslot;
+
+    // (D) relabel; record the step
+    if (mine && pidx != r) {
+      if (psi == (int32_t)r) psi = (int32_t)pidx;
+      else if (psi == (int32_t)pidx) psi = (int32_t)r;
+    }
+    if (g == 0 && lane == 0) {
+      P.ipiv[r] = (int32_t)pidx;
+      P.T[k] = alpha;
+    }
+    if (last) break;
+    const bool below = mine && psi >= k + 2;
+
+    // (F) gathers S(i, x), S(i, y), S(y, x) (valid addresses everywhere; signs and
+    // masks afterwards) and the coefficient rows of x and y
+    const bool lowx = (int64_t)hbm > hx, lowy = (int64_t)hbm > hy, lowyx = hy > hx;
+    const double grx = src[lowx ? (int64_t)hbm + hx * ld : hx + (int64_t)hbm * ld];
+    const double gry = src[lowy ? (int64_t)hbm + hy * ld : hy + (int64_t)hbm * ld];
+    const double gyx = src[lowyx ? hy + hx * ld : hx + hy * ld];
+    {
+      constexpr bool kTwo = 2 * NP > 64;
+      const uint64_t* wx = P.mirror + ((size_t)gs * 64 + wslot) * NP * 4;
+      const uint64_t* wy = P.mirror + ((size_t)ygs * 64 + yslot) * NP * 4;
+      const int nd = 2 * si;
+      const uint32_t tA = P.tag_base + (uint32_t)(lane >> 1) + 1u;
+      const uint32_t tB = P.tag_base + (uint32_t)((lane + 64) >> 1) + 1u;
+      const bool hasA = lane < nd, hasB = kTwo && lane + 64 < nd;
+      const int ia = 2 * lane, ib = kTwo ? 2 * (lane + 64) : 2 * lane;
+      uint64_t xa0, xa1, xb0, xb1, ya0, ya1, yb0, yb1;
+      auto load_coef = [&]() {
+        xa0 = ld_word(wx + ia);
+        xa1 = ld_word(wx + ia + 1);
+        ya0 = ld_word(wy + ia);
+        ya1 = ld_word(wy + ia + 1);
+        if constexpr (kTwo) {
+          xb0 = ld_word(wx + ib);
+          xb1 = ld_word(wx + ib + 1);
+          yb0 = ld_word(wy + ib);
+          yb1 = ld_word(wy + ib + 1);
+        } else {
+          xb0 = xb1 = yb0 = yb1 = 0;
+        }
+      };
+      load_coef();
+      uint64_t t0 = 0;
+      for (int it = 0;; ++it) {
+        const bool ok = (!hasA | ((tag_of(xa0) == tA) & (tag_of(xa1) == tA) & (tag_of(ya0) == tA) &
+                                  (tag_of(ya1) == tA))) &
+                        (!hasB | ((tag_of(xb0) == tB) & (tag_of(xb1) == tB) & (tag_of(yb0) == tB) &
+                                  (tag_of(yb1) == tB)));
+        if (__all(ok)) break;
+        if ((it & 31) == 0) {
+          const uint64_t now = wall_clock64();
+          if (it == 0) t0 = now;
+          else if (now - t0 > kWaitTicks) {
+            tout = true;
+            break;
+          }
+        }
+        load_coef();
+      }
+      // coefficient d sits in component d % 2 of step d / 2
+      if (hasA) {
+        reinterpret_cast<double*>(&sm.cx[0])[lane] = from32((uint32_t)xa0, (uint32_t)xa1);
+        reinterpret_cast<double*>(&sm.cy[0])[lane] = from32((uint32_t)ya0, (uint32_t)ya1);
+      }
+      if (hasB) {
+        reinterpret_cast<double*>(&sm.cx[0])[lane + 64] = from32((uint32_t)xb0, (uint32_t)xb1);
+        reinterpret_cast<double*>(&sm.cy[0])[lane + 64] = from32((uint32_t)yb0, (uint32_t)yb1);
+      }
+      if (__any(tout)) {
+        stop = 4;
+        break;
+      }
+    }
+    const double gx = below ? (lowx ? grx : -grx) : 0.0;
+    const double gy = (mine && psi >= k + 3) ? (lowy ? gry : -gry) : 0.0;
+    const double syx = lowyx ? gyx : -gyx;  // S(y, x); y != x (y stands at index k+2, x at k+1)
+
+    // skew GEMVs over the steps so far (coefficients of steps >= si are zero)
+    double ax = 0.0, ay = 0.0, axy = 0.0;
+    {
+      const int jr = (si + 7) & ~7;
+      for (int q = 0; q < jr; q += 8) {
+        double2 a[8], cxv[8], cyv[8];
+#pragma unroll
+        for (int t = 0; t < 8; ++t) {
+          a[t] = sm.LW[q + t][lane];
+          cxv[t] = sm.cx[q + t];
+          cyv[t] = sm.cy[q + t];
+        }
+#pragma unroll
+        for (int t = 0; t < 8; ++t) {
+          ax += a[t].x * cxv[t].y - a[t].y * cxv[t].x;
+          ay += a[t].x * cyv[t].y - a[t].y * cyv[t].x;
+          axy += cyv[t].x * cxv[t].y - cyv[t].y * cxv[t].x;
+        }
+      }
+    }
+    // l_y is formed exactly as its owner forms it, so every workgroup uses the same bits
+    const double li = below ? ((alpha != 0.0) ? cur / alpha : 0.0) : 0.0;
+    const double vi = below ? gx + ax : 0.0;
+    const double ly = (alpha != 0.0) ? ycur / alpha : 0.0;
+    const double vy = syx + axy;
+    sm.LW[si][lane] = make_double2(li, vi);
+    cur = (mine && psi >= k + 3) ? gy + ay + (li * vy - vi * ly) : 0.0;
+    ++done;
+    if (mine) {
+      const uint32_t mt = tag;  // pair si carries the tag of step si
+      uint64_t* m = my_mirror + (size_t)si * 4;
+      st_word(m + 0, mk(mt, hi32(li)));
+      st_word(m + 1, mk(mt, lo32(li)));
+      st_word(m + 2, mk(mt, hi32(vi)));
+      st_word(m + 3, mk(mt, lo32(vi)));
+    }
+  }
+
+  // ---- panel end ----
+  if (stop) {
+    if (lane == 0) atomicMin(P.status, (stop & 4) ? SKF_ETIMEOUT : SKF_ENONFINITE);
+    if (mine) P.pi[psi] = hbm;
+    return;
+  }
+  if (!mine) return;
+  const int64_t lo = k0 + 2 * done;
+  for (int q = 0; q < done; ++q) {
+    const double2 v = sm.LW[q][lane];
+    const double lp = (psi == lo) ? 0.0 : v.x;
+    P.Lp[psi + (int64_t)q * n] = lp;
+    P.Wp[psi + (int64_t)q * n] = (psi == lo) ? 0.0 : v.y;
+    P.NLp[psi + (int64_t)q * n] = -lp;
+  }
+  P.pi[psi] = hbm;
+  if (psi >= lo + 1) P.cnext[psi] = cur;
+}
+
+template <int NB, int NQ>
+int launch_panel_pf_t(const PanelParams& p, hipStream_t s) {
+  hipLaunchKernelGGL((panel_pf_kernel<NB, NQ>), dim3(p.G), dim3(kPanelThreads), 0, s, p);
+  SKF_CHECK_LAUNCH("panel_pf");
+  return 0;
+}
+
 template <int NB, int NQ>
 int launch_panel_t(const PanelParams& p, hipStream_t s) {
   hipLaunchKernelGGL((panel_kernel<NB, NQ>), dim3(p.G), dim3(kPanelThreads), 0, s, p);
@@ -462,6 +790,24 @@ int launch_panel(const PanelParams& p, hipStream_t s) {
     if (nq <= 2) return launch_panel_t<64, 2>(p, s);
     if (nq <= 4) return launch_panel_t<64, 4>(p, s);
     return launch_panel_t<64, 8>(p, s);
+  }
+  return SKF_ENOTIMPL;
+}
+
+int launch_panel_pf(const PanelParams& p, hipStream_t s) {
+  if (p.G > kMaxG || p.S > 64 || p.n >= (1 << 24) || !p.front) return SKF_ENOTIMPL;
+  const int nq = (p.G + 63) / 64;
+  if (p.nb == 128) {
+    if (nq <= 1) return launch_panel_pf_t<128, 1>(p, s);
+    if (nq <= 2) return launch_panel_pf_t<128, 2>(p, s);
+    if (nq <= 4) return launch_panel_pf_t<128, 4>(p, s);
+    return launch_panel_pf_t<128, 8>(p, s);
+  }
+  if (p.nb == 64) {
+    if (nq <= 1) return launch_panel_pf_t<64, 1>(p, s);
+    if (nq <= 2) return launch_panel_pf_t<64, 2>(p, s);
+    if (nq <= 4) return launch_panel_pf_t<64, 4>(p, s);
+    return launch_panel_pf_t<64, 8>(p, s);
   }
   return SKF_ENOTIMPL;
 }

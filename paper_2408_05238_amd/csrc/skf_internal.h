@@ -89,12 +89,14 @@ struct PanelParams {
   int32_t* ipiv;     // global ipiv output
   uint64_t* rec;     // sync records, double-buffered by step parity
   uint64_t* mirror;  // per-workgroup tagged copy of each slot's pair coefficients
+  uint64_t* front;   // Pfaffian-only panel: owners of indices k+1, k+2 (16 words)
   double* Lscr;      // (nb/2) x G x slots: first-step multipliers, slot-indexed
   int* status;       // device status word (0 ok)
   uint32_t tag_base; // tag of step k is tag_base + (k - k0) + 1
 };
 
 int launch_panel(const PanelParams& p, hipStream_t s);
+int launch_panel_pf(const PanelParams& p, hipStream_t s);
 int panel_slots();
 size_t panel_record_words(int G);
 size_t panel_mirror_words(int G, int nb);
@@ -112,6 +114,7 @@ struct LtltWork {
   int32_t* sigma;  // npanels x n: composed later permutations
   uint64_t* rec;   // sync records
   uint64_t* mirror;  // panel coefficient mirrors
+  uint64_t* front;   // Pfaffian-only panel exchange words (16)
   double* Lscr;    // panel multiplier scratch
   int* status;     // 1 int (+ padding)
   size_t bytes;
@@ -124,6 +127,9 @@ LtltWork ltlt_carve(void* work, int64_t n, int prec);
 
 int run_ltlt(int64_t n, double* A, int64_t lda, int32_t* ipiv, double* T, int prec, void* work,
              size_t lwork, int* dinfo_dev, hipStream_t s);
+// Pfaffian-only reduction (interchanges and the even-step pivots), same workspace.
+int run_pfonly(int64_t n, double* A, int64_t lda, int32_t* ipiv, double* T, int prec, void* work,
+               size_t lwork, int* dinfo_dev, hipStream_t s);
 
 // Kernel timing hooks (api.hip): no-ops unless skf_profile_enable(1).
 void prof_begin(hipStream_t s);
@@ -132,6 +138,7 @@ void prof_end(hipStream_t s, int cls, double flops);
 // Helpers (ltlt_aux.hip)
 int launch_fill_u64(uint64_t* p, size_t count, uint64_t v, hipStream_t s);
 int launch_fill_i32(int32_t* p, size_t count, int32_t v, hipStream_t s);
+int launch_iota_i32(int32_t* p, size_t count, hipStream_t s);
 int launch_copy_panel_L(int64_t n, int64_t k0, int nsteps, const double* Lbuf, double* W, int64_t ldw,
                         hipStream_t s);
 int launch_compose_sigma(int64_t n, int npanels, const int32_t* pis, int32_t* sigma, hipStream_t s);

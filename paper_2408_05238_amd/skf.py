@@ -27,7 +27,7 @@ ETIMEOUT = -105
 
 # Every symbol declared in include/skf.h (checked by the CPU test suite).
 EXPORTS = [
-    "skf_version", "skf_last_error", "skf_ltlt_workspace", "skf_ltlt", "skf_logpf_from_factors",
+    "skf_version", "skf_last_error", "skf_ltlt_workspace", "skf_ltlt", "skf_pfonly", "skf_logpf_from_factors",
     "skf_logpf_workspace", "skf_logpf", "skf_pfaffian", "skf_skr2k", "skf_skr2k_f32",
     "skf_solve_workspace", "skf_solve", "skf_refine_workspace", "skf_solve_refine",
     "skf_batched_workspace", "skf_ltlt_batched", "skf_pfonly_batched", "skf_logpf_batched", "skf_solve_batched",
@@ -65,6 +65,7 @@ def _load():
                 "skf_last_error": (ctypes.c_char_p, []),
                 "skf_ltlt_workspace": (sz, [i64, ci]),
                 "skf_ltlt": (ci, [i64, vp, i64, vp, vp, ci, vp, sz, vp, vp]),
+                "skf_pfonly": (ci, [i64, vp, i64, vp, vp, ci, vp, sz, vp, vp]),
                 "skf_logpf_from_factors": (ci, [i64, vp, vp, vp, vp, vp]),
                 "skf_logpf_workspace": (sz, [i64, ci]),
                 "skf_logpf": (ci, [i64, vp, i64, vp, vp, ci, vp, sz, vp, vp]),
@@ -203,6 +204,28 @@ def ltlt(A, ipiv=None, T=None, prec: int = PREC_F64, work=None, dinfo=None, stre
     rc = _load().skf_ltlt(n, _ptr(A), lda, _ptr(ipiv), _ptr(T), prec, _ptr(work), work.numel(),
                           _ptr(dinfo), _stream(stream))
     _check(rc, "skf_ltlt")
+    return ipiv[:n], T[:max(n - 1, 0)], (rc if dinfo is None else dinfo)
+
+
+def pfonly(A, ipiv=None, T=None, prec: int = PREC_F64, work=None, dinfo=None, stream=None):
+    """Pfaffian-only reduction of A (column-major; destroyed).
+
+    Returns (ipiv, T, info) as ``ltlt``: ipiv holds the interchanges of the even
+    steps (at odd positions), T the pivots at even positions (odd entries 0).
+    """
+    torch = _torch()
+    n = A.shape[0]
+    lda = _ld(A)
+    dev = A.device
+    if ipiv is None:
+        ipiv = torch.empty(max(n, 1), dtype=torch.int32, device=dev)
+    if T is None:
+        T = torch.empty(max(n - 1, 1), dtype=torch.float64, device=dev)
+    if work is None:
+        work = workspace(ltlt_workspace(n, prec), dev)
+    rc = _load().skf_pfonly(n, _ptr(A), lda, _ptr(ipiv), _ptr(T), prec, _ptr(work), work.numel(),
+                            _ptr(dinfo), _stream(stream))
+    _check(rc, "skf_pfonly")
     return ipiv[:n], T[:max(n - 1, 0)], (rc if dinfo is None else dinfo)
 
 
