@@ -337,7 +337,6 @@ def main():
         c = skf.colmajor(n, n, device=dev)
         c.copy_(d0)
         copies.append(c)
-    del d0
     work = skf.workspace(skf.ltlt_workspace(n, prec), dev)
     ipiv = torch.empty(n, dtype=torch.int32, device=dev)
     T = torch.empty(max(n - 1, 1), dtype=torch.float64, device=dev)
@@ -374,8 +373,37 @@ def main():
         del a, b
     infos = dinfo.cpu().tolist()
     assert all(v == 0 for v in infos), f"factorization reported info {infos}"
+
     ms_per_step = (t1 - t0) * 1e3 / args.steps
     gflops = (n ** 3 / 3.0) / (ms_per_step * 1e-3) / 1e9
+
+    # the Pfaffian-only reduction of the same matrix (outside the timed region):
+    # one warm-up, then the median of three event-timed runs
+    pf_only = None
+    if prec == skf.PREC_F64:
+        ipiv2 = torch.empty_like(ipiv)
+        T2 = torch.empty_like(T)
+        dinfo2 = torch.zeros(1, dtype=torch.int32, device=dev)
+        times = []
+        for r in range(4):
+            copies[0].copy_(d0)
+            torch.cuda.synchronize()
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            e0.record()
+            skf.pfonly(copies[0], ipiv2, T2, prec, work, dinfo2)
+            e1.record()
+            torch.cuda.synchronize()
+            if r > 0:
+                times.append(e0.elapsed_time(e1))
+        la_f, sg_f = skf.logpf_from_factors(n, ipiv, T)
+        la_p, sg_p = skf.logpf_from_factors(n, ipiv2, T2)
+        la_f, la_p = float(la_f.item()), float(la_p.item())
+        pf_ms = sorted(times)[1]
+        pf_only = {"ms": round(pf_ms, 3), "speedup_vs_ltlt": round(ms_per_step / pf_ms, 3),
+                   "info": int(dinfo2.item()), "sign_equal_ltlt": int(sg_f.item()) == int(sg_p.item()),
+                   "logabs_rel_diff_vs_ltlt": abs(la_p - la_f) / max(1.0, abs(la_f))}
+    del d0
 
     # parity spot check of the last step against the oracle's stored pivots (same seed)
     parity = None
@@ -418,6 +446,7 @@ def main():
         "roofline": roofline,
         "panel": panel,
         "parity": parity,
+        "pfaffian_only": pf_only,
         "input_generation_s": round(t_gen, 2),
     }
     if not args.no_cpu_baseline:
