@@ -403,6 +403,46 @@ def main():
         pf_only = {"ms": round(pf_ms, 3), "speedup_vs_ltlt": round(ms_per_step / pf_ms, 3),
                    "info": int(dinfo2.item()), "sign_equal_ltlt": int(sg_f.item()) == int(sg_p.item()),
                    "logabs_rel_diff_vs_ltlt": abs(la_p - la_f) / max(1.0, abs(la_f))}
+
+    # Pfaffian ratio of a rank-2r skew update through the resident factors of the
+    # last timed step (outside the timed region): median of three event-timed
+    # calls per r after one warm-up; at r = 1 the ratio is checked against the
+    # Pfaffian-only reductions of the updated and the original matrix
+    pf_ratio = None
+    if prec == skf.PREC_F64 and pf_only is not None:
+        LT = copies[nrun - 1]
+        g = torch.Generator(device=dev)
+        g.manual_seed(args.seed)
+        pf_ratio = {}
+        for r in (1, 16):
+            Ud = torch.randn(r, n, device=dev, dtype=torch.float64, generator=g).t()
+            Vd = torch.randn(r, n, device=dev, dtype=torch.float64, generator=g).t()
+            wk = skf.workspace(skf.pf_ratio_workspace(n, r), dev)
+            di = torch.zeros(1, dtype=torch.int32, device=dev)
+            times = []
+            for rep in range(4):
+                e0 = torch.cuda.Event(enable_timing=True)
+                e1 = torch.cuda.Event(enable_timing=True)
+                e0.record()
+                la_r, sg_r, _ = skf.pf_ratio(LT, ipiv, T, Ud, Vd, work=wk, dinfo=di)
+                e1.record()
+                torch.cuda.synchronize()
+                if rep > 0:
+                    times.append(e0.elapsed_time(e1))
+            ent = {"ms": round(sorted(times)[1], 3), "info": int(di.item()),
+                   "speedup_vs_refactorization": round(ms_per_step / sorted(times)[1], 1)}
+            if r == 1:
+                Bm = copies[0]
+                Bm.copy_(d0)
+                Bm.add_(Ud @ Vd.t() - Vd @ Ud.t())
+                skf.pfonly(Bm, ipiv2, T2, prec, work, dinfo2)
+                la_b, sg_b = skf.logpf_from_factors(n, ipiv2, T2)
+                direct = float(la_b.item()) - la_p
+                ent["logabs"] = float(la_r.item())
+                ent["logabs_via_two_pfaffians"] = direct
+                ent["abs_diff"] = abs(float(la_r.item()) - direct)
+                ent["sign_equal"] = int(sg_r.item()) == int(sg_b.item()) * int(sg_p.item())
+            pf_ratio[f"r{r}"] = ent
     del d0
 
     # parity spot check of the last step against the oracle's stored pivots (same seed)
@@ -447,6 +487,7 @@ def main():
         "panel": panel,
         "parity": parity,
         "pfaffian_only": pf_only,
+        "pf_ratio_resident_factors": pf_ratio,
         "input_generation_s": round(t_gen, 2),
     }
     if not args.no_cpu_baseline:

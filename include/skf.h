@@ -165,6 +165,32 @@ int skf_solve(skf_int n, skf_int nrhs, const double* LT, skf_int lda, const int3
               const double* T, double* B, skf_int ldb, void* work, size_t lwork, int* dinfo,
               void* stream);
 
+/* Device workspace (bytes) for skf_pf_ratio (0 if r is out of range). */
+size_t skf_pf_ratio_workspace(skf_int n, skf_int r);
+
+/*
+ * Pfaffian ratio of a low-rank skew update, from the resident factors of A:
+ *   Pf(A + U V^T - V U^T) / Pf(A),  U, V: n x r (device, column-major), 0 <= r <= 32.
+ * With W = [U V] and J = [[0, I_r], [-I_r, 0]] the ratio equals
+ * Pf(W^T A^-1 W - J) / Pf(-J) (the Schur-complement identity of the Pfaffian
+ * for the bordered matrix [[A, W], [-W^T, -J]]), so the call costs one solve
+ * with 2r right-hand sides through the factors (as skf_solve), a 2r x 2r Gram
+ * product and a 2r x 2r Pfaffian, instead of a factorization of the updated
+ * matrix.  The factors (LT, ipiv, T) come from skf_ltlt of A.
+ *   logabs, sign  device scalars: log|ratio| and its sign (0 when the updated
+ *                 matrix is singular: logabs = -inf)
+ *   work          device workspace of skf_pf_ratio_workspace(n, r) bytes (256-aligned)
+ *   dinfo         device int or NULL: 0; the solve's outcome when A is singular
+ *                 (odd n, or a zero even pivot: the ratio is undefined, logabs = NaN,
+ *                 sign = 0); SKF_ENONFINITE for non-finite U, V or factors.
+ * r = 0 (and n = 0) give the ratio 1 without examining the factors.
+ * Returns 0, the outcome (dinfo NULL: the call then synchronizes) or an
+ * argument error (-2: r out of range).
+ */
+int skf_pf_ratio(skf_int n, skf_int r, const double* LT, skf_int lda, const int32_t* ipiv,
+                 const double* T, const double* U, skf_int ldu, const double* V, skf_int ldv,
+                 double* logabs, int* sign, void* work, size_t lwork, int* dinfo, void* stream);
+
 /* Device workspace (bytes) for skf_solve_refine. */
 size_t skf_refine_workspace(skf_int n, skf_int nrhs);
 

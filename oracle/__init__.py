@@ -14,7 +14,10 @@ remaining references are written here from their definitions:
 * ``skr2k`` -- C := beta C + alpha (A B^T - B A^T) on the strict lower triangle,
   with one library matrix product per term;
 * ``reconstruct`` / ``recon_residual`` -- || P A P^T - L T L^T ||_F / (n ||A||_F);
-* ``backward_error`` -- max_j ||b_j - A x_j||_inf / (||A||_inf ||x_j||_inf + ||b_j||_inf).
+* ``backward_error`` -- max_j ||b_j - A x_j||_inf / (||A||_inf ||x_j||_inf + ||b_j||_inf);
+* ``pf_ratio`` -- Pf(A + U V^T - V U^T) / Pf(A) by its definition: the updated
+  matrix is formed (one library product per term) and both Pfaffians are taken
+  with the C factorization.
 
 What pins the oracle (the tests under tests/test_oracle_*.py): a hand-derived
 4x4 example (tests/golden/worked_4x4.txt), brute-force Pfaffians for n <= 10,
@@ -147,6 +150,24 @@ def logpf_pfonly(A: np.ndarray, nthreads: int = 1):
         return float("nan"), 0, info
     la, s = logpf_from_factors(A.shape[0], ipiv, T)
     return la, s, info
+
+
+def pf_ratio(A: np.ndarray, U: np.ndarray, V: np.ndarray, nthreads: int = 1):
+    """(log|ratio|, sign, info) of Pf(B) / Pf(A), B = A + U V^T - V U^T, from two
+    Pfaffians.  Pf(A) = 0 leaves the ratio undefined: (nan, 0, info of A)."""
+    A = np.asarray(A, dtype=np.float64)
+    U = np.asarray(U, dtype=np.float64).reshape(A.shape[0], -1)
+    V = np.asarray(V, dtype=np.float64).reshape(A.shape[0], -1)
+    S = full_from_lower(A)
+    B = S + (U @ V.T - V @ U.T)
+    la_a, s_a, info_a = logpf(S, nthreads=nthreads)
+    if s_a == 0:
+        n = A.shape[0]
+        return float("nan"), 0, (info_a if info_a != 0 else n)
+    la_b, s_b, _ = logpf(B, nthreads=nthreads)
+    if s_b == 0:
+        return float("-inf"), 0, 0
+    return la_b - la_a, s_b * s_a, 0
 
 
 def solve(LT: np.ndarray, ipiv: np.ndarray, T: np.ndarray, B: np.ndarray):

@@ -288,6 +288,37 @@ int skf_solve(skf_int n, skf_int nrhs, const double* LT, skf_int lda, const int3
   return finish_sync(rc, dinfo_int, s);
 }
 
+size_t skf_pf_ratio_workspace(skf_int n, skf_int r) {
+  if (n < 0 || r < 0 || r > pf_ratio_max_rank()) return 0;
+  return pf_ratio_workspace_bytes(n, (int)r) + 256;
+}
+
+int skf_pf_ratio(skf_int n, skf_int r, const double* LT, skf_int lda, const int32_t* ipiv, const double* T,
+                 const double* U, skf_int ldu, const double* V, skf_int ldv, double* logabs, int* sign,
+                 void* work, size_t lwork, int* dinfo, void* stream) {
+  if (n < 0) return -1;
+  if (r < 0 || r > pf_ratio_max_rank()) return -2;
+  if (n > 0 && !LT) return -3;
+  if (lda < (n > 1 ? n : 1)) return -4;
+  if (n > 0 && !ipiv) return -5;
+  if (n > 1 && !T) return -6;
+  if (n > 0 && r > 0 && !U) return -7;
+  if (ldu < (n > 1 ? n : 1)) return -8;
+  if (n > 0 && r > 0 && !V) return -9;
+  if (ldv < (n > 1 ? n : 1)) return -10;
+  if (!logabs) return -11;
+  if (!sign) return -12;
+  if (!work || ((uintptr_t)work & 255)) return -13;
+  if (lwork < skf_pf_ratio_workspace(n, r)) return SKF_EWORK;
+  hipStream_t s = (hipStream_t)stream;
+  const size_t core = pf_ratio_workspace_bytes(n, (int)r);
+  int* dinfo_int = (int*)((char*)work + core);
+  int rc = run_pf_ratio(n, (int)r, LT, lda, ipiv, T, U, ldu, V, ldv, logabs, sign, work, core,
+                        dinfo ? dinfo : dinfo_int, s);
+  if (dinfo) return rc;
+  return finish_sync(rc, dinfo_int, s);
+}
+
 size_t skf_refine_workspace(skf_int n, skf_int nrhs) {
   if (n < 0 || nrhs < 0) return 0;
   return refine_workspace_bytes(n, nrhs);

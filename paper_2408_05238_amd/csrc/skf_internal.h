@@ -131,6 +131,13 @@ int run_ltlt(int64_t n, double* A, int64_t lda, int32_t* ipiv, double* T, int pr
 int run_pfonly(int64_t n, double* A, int64_t lda, int32_t* ipiv, double* T, int prec, void* work,
                size_t lwork, int* dinfo_dev, hipStream_t s);
 
+// Pfaffian ratio of a low-rank skew update with resident factors (ratio.hip).
+int pf_ratio_max_rank();
+size_t pf_ratio_workspace_bytes(int64_t n, int r);
+int run_pf_ratio(int64_t n, int r, const double* LT, int64_t lda, const int32_t* ipiv, const double* T,
+                 const double* U, int64_t ldu, const double* V, int64_t ldv, double* logabs, int* sign,
+                 void* work, size_t lwork, int* dinfo, hipStream_t s);
+
 // Kernel timing hooks (api.hip): no-ops unless skf_profile_enable(1).
 void prof_begin(hipStream_t s);
 void prof_end(hipStream_t s, int cls, double flops);

@@ -29,7 +29,8 @@ ETIMEOUT = -105
 EXPORTS = [
     "skf_version", "skf_last_error", "skf_ltlt_workspace", "skf_ltlt", "skf_pfonly", "skf_logpf_from_factors",
     "skf_logpf_workspace", "skf_logpf", "skf_pfaffian", "skf_skr2k", "skf_skr2k_f32",
-    "skf_solve_workspace", "skf_solve", "skf_refine_workspace", "skf_solve_refine",
+    "skf_solve_workspace", "skf_solve", "skf_pf_ratio_workspace", "skf_pf_ratio", "skf_refine_workspace",
+    "skf_solve_refine",
     "skf_batched_workspace", "skf_ltlt_batched", "skf_pfonly_batched", "skf_logpf_batched", "skf_solve_batched",
     "skf_profile_enable", "skf_profile_read",
 ]
@@ -74,6 +75,8 @@ def _load():
                 "skf_skr2k_f32": (ci, [i64, i64, d, vp, i64, vp, i64, d, vp, i64, vp]),
                 "skf_solve_workspace": (sz, [i64, i64]),
                 "skf_solve": (ci, [i64, i64, vp, i64, vp, vp, vp, i64, vp, sz, vp, vp]),
+                "skf_pf_ratio_workspace": (sz, [i64, i64]),
+                "skf_pf_ratio": (ci, [i64, i64, vp, i64, vp, vp, vp, i64, vp, i64, vp, vp, vp, sz, vp, vp]),
                 "skf_refine_workspace": (sz, [i64, i64]),
                 "skf_solve_refine": (ci, [i64, i64, vp, i64, vp, i64, vp, vp, vp, i64, vp, i64, d, ci,
                                           ctypes.POINTER(ci), ctypes.POINTER(d), vp, sz, vp]),
@@ -302,6 +305,31 @@ def solve(LT, ipiv, T, B, work=None, dinfo=None, stream=None):
                            work.numel(), _ptr(dinfo), _stream(stream))
     _check(rc, "skf_solve")
     return rc if dinfo is None else dinfo
+
+
+def pf_ratio_workspace(n: int, r: int) -> int:
+    return int(_load().skf_pf_ratio_workspace(n, r))
+
+
+def pf_ratio(LT, ipiv, T, U, V, work=None, dinfo=None, stream=None):
+    """(log|ratio|, sign, info) of Pf(A + U V^T - V U^T) / Pf(A) from the factors of A.
+
+    U, V: column-major n x r device tensors (r <= 32).  logabs and sign are device
+    tensors; info is an int when ``dinfo`` is None (synchronous), else ``dinfo``.
+    """
+    torch = _torch()
+    n = LT.shape[0]
+    r = U.shape[1]
+    dev = LT.device
+    la = torch.empty(1, dtype=torch.float64, device=dev)
+    sg = torch.empty(1, dtype=torch.int32, device=dev)
+    if work is None:
+        work = workspace(pf_ratio_workspace(n, r), dev)
+    Tp = T if T.numel() > 0 else torch.zeros(1, dtype=torch.float64, device=dev)
+    rc = _load().skf_pf_ratio(n, r, _ptr(LT), _ld(LT), _ptr(ipiv), _ptr(Tp), _ptr(U), _ld(U), _ptr(V), _ld(V),
+                              _ptr(la), _ptr(sg), _ptr(work), work.numel(), _ptr(dinfo), _stream(stream))
+    _check(rc, "skf_pf_ratio")
+    return la, sg, (rc if dinfo is None else dinfo)
 
 
 def refine_workspace(n: int, nrhs: int) -> int:
