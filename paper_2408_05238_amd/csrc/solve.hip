@@ -319,6 +319,10 @@ struct TriBuf {
   double in[2][RC][TR + 2];   // right-hand sides, rows i0 .. i0 + TR + 1 / the chunk (back substitution)
   double out[2][RC][TR];      // results of the chunk
   double band[2][2][TR];      // 1/diag and second super entry of U, rows of the chunk
+  double plo[TR / 2], pun[TR / 2];  // per pair of the chunk: T[o] and the super entry of row o+1
+  double pc[TR / 2];          // per pair: -(1/T[o]) * (super entry of o+1)
+  double pf[TR / 2];          // per pair: multiplier of the odd row
+  int pk[TR / 2];             // per pair: 1 if the odd row is kept
 };
 
 __global__ void __launch_bounds__(256) tridiag_kernel(int64_t n, const double* __restrict__ T,
@@ -331,26 +335,55 @@ __global__ void __launch_bounds__(256) tridiag_kernel(int64_t n, const double* _
   const int ht = tid - 64;           // helper thread index (waves 1..3), 192 of them
   // ---------------- elimination, rows 0 .. n-2 (n even) ----------------
   const int64_t nchf = (n - 1 + TR - 1) / TR;
+  // Helper copies issue all of a thread's loads before the first LDS write (and
+  // all LDS reads before the first store), so a chunk costs one memory latency.
+  constexpr int kIn = (RC * (TR + 2) + 191) / 192;
+  constexpr int kOut = (RC * TR + 191) / 192;
+  constexpr int kBand = (2 * TR + 191) / 192;
   auto fwd_load = [&](int b, int64_t i0) {
-    for (int t = ht; t < TR + 2; t += 192) {
-      const int64_t i = i0 + t;
-      sb.T[b][t] = (i <= n - 2) ? T[i] : 0.0;
-    }
-    for (int t = ht; t < RC * (TR + 2); t += 192) {
+    const int64_t ti = min(i0 + ht, n - 2);  // clamped: valid for n >= 2
+    const double tv = (ht < TR + 2) ? T[ti < 0 ? 0 : ti] : 0.0;
+    double v[kIn];
+#pragma unroll
+    for (int k = 0; k < kIn; ++k) {
+      const int t = min(ht + 192 * k, RC * (TR + 2) - 1);
       const int cc = t / (TR + 2), r = t % (TR + 2);
-      const int64_t i = i0 + r;
-      sb.in[b][cc][r] = (i <= n - 1) ? Y[i + (int64_t)cc * n] : 0.0;
+      v[k] = Y[min(i0 + r, n - 1) + (int64_t)cc * n];
+    }
+    if (ht < TR + 2) sb.T[b][ht] = (i0 + ht <= n - 2) ? tv : 0.0;
+#pragma unroll
+    for (int k = 0; k < kIn; ++k) {
+      const int t = ht + 192 * k;
+      if (t < RC * (TR + 2)) {
+        const int cc = t / (TR + 2), r = t % (TR + 2);
+        sb.in[b][cc][r] = (i0 + r <= n - 1) ? v[k] : 0.0;
+      }
     }
   };
   auto fwd_flush = [&](int b, int64_t i0) {  // rows i0 .. min(i0 + TR, n - 1) - 1
     const int rows = (int)min((int64_t)TR, n - 1 - i0);
-    for (int t = ht; t < RC * TR; t += 192) {
-      const int cc = t / TR, r = t % TR;
-      if (r < rows) Y[i0 + r + (int64_t)cc * n] = sb.out[b][cc][r];
+    double v[kOut], w[kBand];
+#pragma unroll
+    for (int k = 0; k < kOut; ++k) {
+      const int t = min(ht + 192 * k, RC * TR - 1);
+      v[k] = sb.out[b][t / TR][t % TR];
     }
-    for (int t = ht; t < 2 * TR; t += 192) {
+#pragma unroll
+    for (int k = 0; k < kBand; ++k) {
+      const int t = min(ht + 192 * k, 2 * TR - 1);
+      w[k] = sb.band[b][t / TR][t % TR];
+    }
+#pragma unroll
+    for (int k = 0; k < kOut; ++k) {
+      const int t = ht + 192 * k;
+      const int cc = t / TR, r = t % TR;
+      if (t < RC * TR && r < rows) Y[i0 + r + (int64_t)cc * n] = v[k];
+    }
+#pragma unroll
+    for (int k = 0; k < kBand; ++k) {
+      const int t = ht + 192 * k;
       const int q = t / TR, r = t % TR;
-      if (r < rows) band[(int64_t)q * n + i0 + r] = sb.band[b][q][r];
+      if (t < 2 * TR && r < rows) band[(int64_t)q * n + i0 + r] = w[k];
     }
   };
   double u = (n > 1) ? -T[0] : 0.0;   // super entry carried into the next even row
@@ -366,50 +399,100 @@ __global__ void __launch_bounds__(256) tridiag_kernel(int64_t n, const double* _
       if (ch >= 1) fwd_flush(cur ^ 1, i0 - TR);
       if (ch + 1 < nchf) fwd_load(cur ^ 1, i0 + TR);
     }
-    if (work && !sing) {
+    if (tid < 64 && !sing) {
+      // The pivot choices, multipliers and U depend on T only.  Wave 0 takes
+      // (a) each pair's chain-free part, one pair per lane; (b) the chain
+      // through the running diagonal u alone (uniform, every lane, no branch):
+      // the odd row of pair j has diagonal s_j = u and is kept when |s_j| >=
+      // |T[o]|, then u = kept ? -T[o+1] : s_j * (-(1/T[o]) T[o+1]); (c) per pair
+      // again, the reciprocal pivots, multipliers, U and the first zero pivot;
+      // (d) the working lanes carry the right-hand sides through the choices.
       const int rows = (int)min((int64_t)TR, n - 1 - i0);
-      // the pair's operands are read one pair ahead from the padded buffers
-      // (indices clamped; no read sits behind a branch or on the chain)
+      const int npc = (rows + 1) / 2;            // pairs; with odd rows the last is row n-2 and the last row
+      const int nf = (rows & 1) ? npc - 1 : npc;  // pairs with a full odd row
       const double* tb = sb.T[cur];
-      const double* yb = sb.in[cur][c];
-      double le = tb[0], lo = tb[1], t2 = tb[2], ye = yb[1], yo = yb[2];
-      for (int r = 0; r < rows; r += 2) {
-        const int rn = min(r + 2, TR - 2);
-        const double lo_n = tb[rn + 1], t2_n = tb[rn + 2], ye_n = yb[rn + 1], yo_n = yb[rn + 2];
-        // even row e: running diagonal 0, always interchanged with row e+1
-        const int64_t e = i0 + r;
-        if (le == 0.0) {
-          sing = e + 1;
-          break;
+      const int j = tid, r = 2 * j;
+      const int64_t e = i0 + r;
+      const double le = tb[r], lo_j = tb[r + 1], t2 = tb[r + 2];
+      const double rl_j = recip(lo_j);
+      const double un_j = (e + 3 < n) ? -t2 : 0.0;
+      if (j < npc) {
+        sb.band[cur][0][r] = recip(le);
+        sb.band[cur][1][r] = (e + 2 < n) ? -lo_j : 0.0;
+      }
+      sb.plo[j] = lo_j;
+      sb.pun[j] = un_j;
+      sb.pc[j] = -(rl_j * un_j);
+      double mys = 0.0;
+      {
+        constexpr int G4 = 4;
+        double lo[G4], cf[G4], un[G4];
+#pragma unroll
+        for (int t = 0; t < G4; ++t) {
+          lo[t] = sb.plo[t];
+          cf[t] = sb.pc[t];
+          un[t] = sb.pun[t];
         }
-        sb.out[cur][c][r] = ye;
-        sb.band[cur][0][r] = recip(le);  // every working lane stores the same value
-        sb.band[cur][1][r] = (e + 2 < n) ? -lo : 0.0;
-        const double s = u;  // running diagonal of the odd row
-        if (r + 1 >= rows) {  // e = n-2: the odd row is the last row
-          sd = s;
-          break;
+        for (int jb = 0; jb < nf; jb += G4) {
+          const int jn = min(jb + G4, TR / 2 - G4);
+          double lon[G4], cfn[G4], unn[G4];
+#pragma unroll
+          for (int t = 0; t < G4; ++t) {
+            lon[t] = sb.plo[jn + t];
+            cfn[t] = sb.pc[jn + t];
+            unn[t] = sb.pun[jn + t];
+          }
+#pragma unroll
+          for (int t = 0; t < G4; ++t) {
+            const double s_ = u;
+            const bool keep = fabs(s_) >= fabs(lo[t]);
+            const double un_next = keep ? un[t] : s_ * cf[t];
+            mys = (tid == jb + t) ? s_ : mys;
+            u = (jb + t < nf) ? un_next : u;
+          }
+#pragma unroll
+          for (int t = 0; t < G4; ++t) {
+            lo[t] = lon[t];
+            cf[t] = cfn[t];
+            un[t] = unn[t];
+          }
         }
-        // odd row o = e+1: keep it or interchange it with row o+1
-        const int64_t o = e + 1;
-        const double un = (o + 2 < n) ? -t2 : 0.0;
-        const bool keep = fabs(s) >= fabs(lo);
-        if ((keep ? s : lo) == 0.0) {
-          sing = o + 1;
-          break;
+      }
+      if (rows & 1) sd = u;  // e = n-2: the odd row is the last row, diagonal u
+      // (c) pair j's odd row from s_j; the first zero pivot in row order
+      const bool keep = fabs(mys) >= fabs(lo_j);
+      const double rs = recip(mys);
+      if (j < nf) {
+        sb.band[cur][0][r + 1] = keep ? rs : rl_j;
+        sb.band[cur][1][r + 1] = keep ? 0.0 : un_j;
+        sb.pf[j] = keep ? lo_j * rs : mys * rl_j;
+        sb.pk[j] = (int)keep;
+      }
+      const uint64_t ze = __ballot(j < npc && le == 0.0);
+      const uint64_t zo = __ballot(j < nf && (keep ? mys : lo_j) == 0.0);
+      if (ze | zo) {
+        const int jf = (int)__builtin_ctzll(ze | zo);
+        sing = i0 + 2 * jf + (((ze >> jf) & 1ull) ? 1 : 2);
+      }
+      if (work && !sing) {
+        // even row: always interchanged with the odd row (multiplier 0); odd row:
+        // kept (eliminate the next row with it) or interchanged with the next row
+        const double* yb = sb.in[cur][c];
+        double ye = yb[1], yo = yb[2], f = sb.pf[0];
+        int kp = sb.pk[0];
+        for (int q = 0; q < nf; ++q) {
+          const int qn = min(q + 1, TR / 2 - 1);
+          const double ye_n = yb[2 * qn + 1], yo_n = yb[2 * qn + 2], f_n = sb.pf[qn];
+          const int kp_n = sb.pk[qn];
+          sb.out[cur][c][2 * q] = ye;
+          sb.out[cur][c][2 * q + 1] = kp ? ys : yo;
+          ys = kp ? yo - f * ys : ys - f * yo;
+          ye = ye_n;
+          yo = yo_n;
+          f = f_n;
+          kp = kp_n;
         }
-        const double rs = recip(s), rl = recip(lo);
-        const double f = keep ? lo * rs : s * rl;
-        sb.out[cur][c][r + 1] = keep ? ys : yo;
-        sb.band[cur][0][r + 1] = keep ? rs : rl;
-        sb.band[cur][1][r + 1] = keep ? 0.0 : un;
-        u = keep ? un : -(s * rl) * un;
-        ys = keep ? yo - f * ys : ys - f * yo;
-        le = t2;
-        lo = lo_n;
-        t2 = t2_n;
-        ye = ye_n;
-        yo = yo_n;
+        if (rows & 1) sb.out[cur][c][2 * nf] = yb[2 * nf + 1];  // the last row's right-hand side stays in ys
       }
     }
     __syncthreads();
@@ -431,22 +514,42 @@ __global__ void __launch_bounds__(256) tridiag_kernel(int64_t n, const double* _
   // ---------------- back substitution, rows n-1 .. 0 ----------------
   const int64_t nchb = (n + TR - 1) / TR;
   auto bwd_load = [&](int b, int64_t i1) {  // rows i1 - TR .. i1 - 1 (negative rows padded)
-    for (int t = ht; t < RC * TR; t += 192) {
-      const int cc = t / TR, r = t % TR;
-      const int64_t i = i1 - TR + r;
-      sb.in[b][cc][r] = (i >= 0) ? Y[i + (int64_t)cc * n] : 0.0;
+    double v[kOut], w[kBand];
+#pragma unroll
+    for (int k = 0; k < kOut; ++k) {
+      const int t = min(ht + 192 * k, RC * TR - 1);
+      const int64_t i = i1 - TR + t % TR;
+      v[k] = Y[(i < 0 ? 0 : i) + (int64_t)(t / TR) * n];
     }
-    for (int t = ht; t < 2 * TR; t += 192) {
-      const int q = t / TR, r = t % TR;
-      const int64_t i = i1 - TR + r;
-      sb.band[b][q][r] = (i >= 0) ? band[(int64_t)q * n + i] : 0.0;
+#pragma unroll
+    for (int k = 0; k < kBand; ++k) {
+      const int t = min(ht + 192 * k, 2 * TR - 1);
+      const int64_t i = i1 - TR + t % TR;
+      w[k] = band[(int64_t)(t / TR) * n + (i < 0 ? 0 : i)];
+    }
+#pragma unroll
+    for (int k = 0; k < kOut; ++k) {
+      const int t = ht + 192 * k;
+      if (t < RC * TR) sb.in[b][t / TR][t % TR] = (i1 - TR + t % TR >= 0) ? v[k] : 0.0;
+    }
+#pragma unroll
+    for (int k = 0; k < kBand; ++k) {
+      const int t = ht + 192 * k;
+      if (t < 2 * TR) sb.band[b][t / TR][t % TR] = (i1 - TR + t % TR >= 0) ? w[k] : 0.0;
     }
   };
   auto bwd_flush = [&](int b, int64_t i1) {
-    for (int t = ht; t < RC * TR; t += 192) {
-      const int cc = t / TR, r = t % TR;
-      const int64_t i = i1 - TR + r;
-      if (i >= 0) Y[i + (int64_t)cc * n] = sb.out[b][cc][r];
+    double v[kOut];
+#pragma unroll
+    for (int k = 0; k < kOut; ++k) {
+      const int t = min(ht + 192 * k, RC * TR - 1);
+      v[k] = sb.out[b][t / TR][t % TR];
+    }
+#pragma unroll
+    for (int k = 0; k < kOut; ++k) {
+      const int t = ht + 192 * k;
+      const int64_t i = i1 - TR + t % TR;
+      if (t < RC * TR && i >= 0) Y[i + (int64_t)(t / TR) * n] = v[k];
     }
   };
   double x1 = 0.0, x2 = 0.0;  // solution at rows i+1, i+2
@@ -460,20 +563,42 @@ __global__ void __launch_bounds__(256) tridiag_kernel(int64_t n, const double* _
       if (ch + 1 < nchb) bwd_load(cur ^ 1, i1 - TR);
     }
     if (work) {
-      const int rlo = (int)max((int64_t)0, TR - i1);  // rows below 0 are padding
-      // x_i = (y_i - du2_i x_{i+2}) / d_i  (the first super entry of U is 0);
-      // the row's operands are read one row ahead
-      double a = sb.in[cur][c][TR - 1], b1 = sb.band[cur][1][TR - 1], b0 = sb.band[cur][0][TR - 1];
-      for (int r = TR - 1; r >= rlo; --r) {
-        const int rn = max(r - 1, 0);
-        const double a_n = sb.in[cur][c][rn], b1_n = sb.band[cur][1][rn], b0_n = sb.band[cur][0][rn];
-        const double v = (a - b1 * x2) * b0;
-        sb.out[cur][c][r] = v;
-        x2 = x1;
-        x1 = v;
-        a = a_n;
-        b1 = b1_n;
-        b0 = b0_n;
+      // x_i = (y_i - du2_i x_{i+2}) / d_i  (the first super entry of U is 0),
+      // eight rows at a time with the next eight rows' operands in flight; rows
+      // below 0 are zero padding and give zeros
+      constexpr int G8 = 8;
+      const double* ib = sb.in[cur][c];
+      const double* p0 = sb.band[cur][0];
+      const double* p1 = sb.band[cur][1];
+      double a[G8], b1[G8], b0[G8];
+#pragma unroll
+      for (int t = 0; t < G8; ++t) {
+        a[t] = ib[TR - G8 + t];
+        b1[t] = p1[TR - G8 + t];
+        b0[t] = p0[TR - G8 + t];
+      }
+      for (int rb = TR - G8; rb >= 0; rb -= G8) {
+        const int rn = max(rb - G8, 0);
+        double an[G8], b1n[G8], b0n[G8];
+#pragma unroll
+        for (int t = 0; t < G8; ++t) {
+          an[t] = ib[rn + t];
+          b1n[t] = p1[rn + t];
+          b0n[t] = p0[rn + t];
+        }
+#pragma unroll
+        for (int t = G8 - 1; t >= 0; --t) {
+          const double v = (a[t] - b1[t] * x2) * b0[t];
+          sb.out[cur][c][rb + t] = v;
+          x2 = x1;
+          x1 = v;
+        }
+#pragma unroll
+        for (int t = 0; t < G8; ++t) {
+          a[t] = an[t];
+          b1[t] = b1n[t];
+          b0[t] = b0n[t];
+        }
       }
     }
     __syncthreads();
