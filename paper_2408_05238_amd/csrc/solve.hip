@@ -148,7 +148,8 @@ __global__ void __launch_bounds__(NT) trsv_kernel(int64_t n, const double* __res
                                                   uint64_t* __restrict__ pub, uint32_t tag, int* status) {
   __shared__ double Lb[2][BS][BS + 1];
   __shared__ double Db[BS][BS + 1];  // inv(L_II), or its transpose (backward)
-  __shared__ double yJ[BS][RC + 1];
+  __shared__ double yJ[2][BS][RC + 1];  // double-buffered like Lb: a fast thread may unpack
+                                        // the next block while others still multiply
   __shared__ double acc[BS][RC + 1];
   __shared__ int stop;
   const int64_t nb = (n + BS - 1) / BS;
@@ -203,7 +204,22 @@ __global__ void __launch_bounds__(NT) trsv_kernel(int64_t n, const double* __res
   const int64_t jfirst = kTrans ? nb - 1 : 0;
   const int64_t jstep = kTrans ? -1 : 1;
   double v[kLdPerThread];
+  // Y_J: thread t takes values e = t + NT q, (j, c) = (e % BS, e / BS).  The words
+  // of the next J are loaded while the current J is multiplied (most blocks are
+  // final long before they are needed), then checked and reloaded until all
+  // carry this solve's tag (bounded wait).
+  uint64_t w[4][2];
+  auto load_y = [&](int64_t J) {
+    const uint64_t* pj = pub + (size_t)J * RC * BS * 2;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int e = tid + NT * q;
+      w[q][0] = ld_word(pj + 2 * e);
+      w[q][1] = ld_word(pj + 2 * e + 1);
+    }
+  };
   if (count > 0) {
+    load_y(jfirst);
     fetch(jfirst, v);
     put(0, jfirst, v);
   }
@@ -214,19 +230,7 @@ __global__ void __launch_bounds__(NT) trsv_kernel(int64_t n, const double* __res
     const bool more = idx + 1 < count;
     if (more) fetch(J + jstep, v);
     {
-      // Y_J: thread t takes values e = t + NT q, (j, c) = (e % BS, e / BS); every
-      // word is reloaded until all carry this solve's tag (bounded wait)
-      const uint64_t* pj = pub + (size_t)J * RC * BS * 2;
-      uint64_t w[4][2];
-      auto load_all = [&]() {
-#pragma unroll
-        for (int q = 0; q < 4; ++q) {
-          const int e = tid + NT * q;
-          w[q][0] = ld_word(pj + 2 * e);
-          w[q][1] = ld_word(pj + 2 * e + 1);
-        }
-      };
-      load_all();
+      auto load_all = [&]() { load_y(J); };
       uint64_t t0 = 0;
       for (int it = 0;; ++it) {
         bool ok = true;
@@ -246,12 +250,13 @@ __global__ void __launch_bounds__(NT) trsv_kernel(int64_t n, const double* __res
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
         const int e = tid + NT * q;
-        yJ[e % BS][e / BS] = __longlong_as_double((long long)((w[q][0] << 32) | (uint32_t)w[q][1]));
+        yJ[buf][e % BS][e / BS] = __longlong_as_double((long long)((w[q][0] << 32) | (uint32_t)w[q][1]));
       }
+      if (more) load_y(J + jstep);
     }
     __syncthreads();
     if (stop) break;
-    block_mv(Lb[buf], yJ, acc, tid);
+    block_mv(Lb[buf], yJ[buf], acc, tid);
     // the other buffer was last read before this iteration's barriers
     if (more) put(buf ^ 1, J + jstep, v);
   }
