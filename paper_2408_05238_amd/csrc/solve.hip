@@ -59,7 +59,17 @@ __global__ void __launch_bounds__(256) perm_kernel(int64_t n, const int32_t* __r
   for (int64_t hi = jmax; hi > 1; hi -= CH) {  // chunk covers s in [max(1, hi-CH), hi)
     const int64_t lo = max((int64_t)1, hi - CH);
     __syncthreads();
-    for (int64_t s = lo + threadIdx.x; s < hi; s += blockDim.x) sp[s - lo] = ipiv[s];
+    {  // all of a thread's loads in flight before the first LDS write
+      constexpr int kPer = CH / 256;
+      int32_t v[kPer];
+#pragma unroll
+      for (int q = 0; q < kPer; ++q) v[q] = ipiv[min(lo + (int64_t)threadIdx.x + 256 * q, hi - 1)];
+#pragma unroll
+      for (int q = 0; q < kPer; ++q) {
+        const int64_t s = lo + threadIdx.x + 256 * q;
+        if (s < hi) sp[s - lo] = v[q];
+      }
+    }
     __syncthreads();
     // the scan order matters (the last match wins), the LDS reads do not: unrolled
     // so that they issue in batches ahead of the compare chain
