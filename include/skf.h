@@ -165,6 +165,34 @@ int skf_solve(skf_int n, skf_int nrhs, const double* LT, skf_int lda, const int3
               const double* T, double* B, skf_int ldb, void* work, size_t lwork, int* dinfo,
               void* stream);
 
+/* Device workspace (bytes) for skf_pfonly_c128: a full n x n complex128 copy. */
+size_t skf_pfonly_c128_workspace(skf_int n);
+
+/*
+ * Pfaffian-only reduction of a complex (complex128) skew-symmetric matrix: the
+ * elimination of skf_pfonly at even steps k, with the pivot the largest
+ * |z|^2 = re^2 + im^2 below the diagonal of column k (lowest index on ties).
+ * Pf(A) = (-1)^{s + n/2} prod_{k even} T[k], s = #{j : ipiv[j] != j}.
+ * Unblocked: the strict lower triangle is expanded into a full copy in the
+ * workspace and each step is a few launches (pivot, interchange, l and v,
+ * trailing rank-2 update); n <= 65535.
+ *   A      device, lda x n complex128 (interleaved re, im), strict lower triangle
+ *          read, not modified
+ *   ipiv   device int32[n]: ipiv[k+1] (k even) = step k's interchange, else j
+ *   T      device complex128[max(n-1,1)]: T[k] (k even) pivots, odd entries 0
+ *   work   device workspace of skf_pfonly_c128_workspace(n) bytes (256-aligned)
+ *   dinfo  device int or NULL: 0; n for odd n; 1 + the first even k with
+ *          T[k] = 0; SKF_ENONFINITE for a non-finite pivot column
+ * Returns 0, the outcome (dinfo NULL: synchronous) or an argument error.
+ */
+int skf_pfonly_c128(skf_int n, const double* A, skf_int lda, int32_t* ipiv, double* T, void* work,
+                    size_t lwork, int* dinfo, void* stream);
+
+/* log|Pf| and phase = Pf/|Pf| (device double[2], re and im; 0 when Pf = 0)
+ * from the factors of skf_pfonly_c128, in index order.  n = 0: Pf = 1. */
+int skf_logpf_c128_from_factors(skf_int n, const int32_t* ipiv, const double* T, double* logabs,
+                                double* phase, void* stream);
+
 /* Device workspace (bytes) for skf_pf_ratio (0 if r is out of range). */
 size_t skf_pf_ratio_workspace(skf_int n, skf_int r);
 

@@ -15,6 +15,11 @@ remaining references are written here from their definitions:
   with one library matrix product per term;
 * ``reconstruct`` / ``recon_residual`` -- || P A P^T - L T L^T ||_F / (n ||A||_F);
 * ``backward_error`` -- max_j ||b_j - A x_j||_inf / (||A||_inf ||x_j||_inf + ||b_j||_inf);
+* ``pfonly_c128`` -- the Pfaffian-only reduction of a complex skew matrix, in
+  numpy complex128 on a full copy: per even step the pivot is the largest
+  |z|^2 = re^2 + im^2 (each product rounded, lowest index on ties), rows and
+  columns k+1 and p are interchanged, l = column k / alpha, v = column k+1, and
+  l v^T - v l^T is added to the trailing block;
 * ``pf_ratio`` -- Pf(A + U V^T - V U^T) / Pf(A) by its definition: the updated
   matrix is formed (one library product per term) and both Pfaffians are taken
   with the C factorization.
@@ -150,6 +155,85 @@ def logpf_pfonly(A: np.ndarray, nthreads: int = 1):
         return float("nan"), 0, info
     la, s = logpf_from_factors(A.shape[0], ipiv, T)
     return la, s, info
+
+
+def pfonly_c128(A: np.ndarray):
+    """Pfaffian-only reduction of the complex skew matrix whose strict lower
+    triangle A holds: (ipiv, T, info) with ipiv[k+1] (k even) the interchange of
+    step k, the other ipiv[j] = j, T[k] (k even) the pivots and the odd entries
+    0; info = n for odd n, ENONFINITE for a non-finite pivot column, else
+    1 + the first even k with T[k] = 0, or 0.  Pf(A) = (-1)^{s + n/2} prod T[k]."""
+    n = A.shape[0]
+    Lw = np.tril(np.asarray(A, dtype=np.complex128), -1)
+    W = Lw - Lw.T
+    ipiv = np.arange(n, dtype=np.int32)
+    T = np.zeros(max(n - 1, 0), dtype=np.complex128)
+    if n % 2 == 1:
+        return ipiv, T, n
+    for k in range(0, n - 1, 2):
+        col = W[k + 1:, k]
+        if not np.all(np.isfinite(col)):
+            return ipiv, T, ENONFINITE
+        key = col.real * col.real + col.imag * col.imag
+        p = k + 1 + int(np.argmax(key))
+        ipiv[k + 1] = p
+        if p != k + 1:
+            W[[k + 1, p], :] = W[[p, k + 1], :]
+            W[:, [k + 1, p]] = W[:, [p, k + 1]]
+        alpha = W[k + 1, k]
+        T[k] = alpha
+        if k + 2 < n and alpha != 0:
+            l = W[k + 2:, k] / alpha
+            v = W[k + 2:, k + 1].copy()
+            W[k + 2:, k + 2:] += np.outer(l, v) - np.outer(v, l)
+    for k in range(0, n - 1, 2):
+        if T[k] == 0:
+            return ipiv, T, k + 1
+    return ipiv, T, 0
+
+
+def logpf_c128_from_factors(n: int, ipiv: np.ndarray, T: np.ndarray):
+    """(log|Pf|, phase) with phase = Pf / |Pf| (0 when Pf = 0), in index order."""
+    if n == 0:
+        return 0.0, 1.0 + 0.0j
+    if n % 2 == 1:
+        return float("-inf"), 0.0j
+    s = int(np.count_nonzero(ipiv[:n] != np.arange(n)))
+    ph = -1.0 + 0.0j if (s + n // 2) % 2 else 1.0 + 0.0j
+    la = 0.0
+    for k in range(0, n - 1, 2):
+        t = complex(T[k])
+        if t == 0:
+            return float("-inf"), 0.0j
+        a = abs(t)
+        la += math.log(a)
+        ph *= t / a
+    return la, ph
+
+
+def pfaffian_bruteforce_complex(A) -> complex:
+    """Pfaffian by expansion along the first row, in Python complex arithmetic
+    (exact for small Gaussian-integer entries), for n <= 10."""
+    M = [[complex(x) for x in row] for row in np.asarray(A)]
+    n = len(M)
+
+    def pf(idx):
+        m = len(idx)
+        if m == 0:
+            return 1.0 + 0.0j
+        if m % 2 == 1:
+            return 0.0j
+        i0 = idx[0]
+        total = 0.0j
+        for t in range(1, m):
+            a = M[i0][idx[t]]
+            if a == 0:
+                continue
+            rest = idx[1:t] + idx[t + 1:]
+            total += (-1) ** (t + 1) * a * pf(rest)
+        return total
+
+    return pf(list(range(n)))
 
 
 def pf_ratio(A: np.ndarray, U: np.ndarray, V: np.ndarray, nthreads: int = 1):

@@ -288,6 +288,38 @@ int skf_solve(skf_int n, skf_int nrhs, const double* LT, skf_int lda, const int3
   return finish_sync(rc, dinfo_int, s);
 }
 
+size_t skf_pfonly_c128_workspace(skf_int n) {
+  if (n < 0) return 0;
+  return pfonly_c128_workspace_bytes(n) + 256;
+}
+
+int skf_pfonly_c128(skf_int n, const double* A, skf_int lda, int32_t* ipiv, double* T, void* work, size_t lwork,
+                    int* dinfo, void* stream) {
+  if (n < 0) return -1;
+  if (n > 0 && !A) return -2;
+  if (lda < (n > 1 ? n : 1)) return -3;
+  if (n > 0 && !ipiv) return -4;
+  if (n > 1 && !T) return -5;
+  if (!work || ((uintptr_t)work & 255)) return -6;
+  if (lwork < skf_pfonly_c128_workspace(n)) return SKF_EWORK;
+  hipStream_t s = (hipStream_t)stream;
+  const size_t core = pfonly_c128_workspace_bytes(n);
+  int* dinfo_int = (int*)((char*)work + core);
+  int rc = run_pfonly_c128(n, A, lda, ipiv, T, work, core, dinfo ? dinfo : dinfo_int, s);
+  if (dinfo) return rc;
+  return finish_sync(rc, dinfo_int, s);
+}
+
+int skf_logpf_c128_from_factors(skf_int n, const int32_t* ipiv, const double* T, double* logabs, double* phase,
+                                void* stream) {
+  if (n < 0) return -1;
+  if (n > 0 && !ipiv) return -2;
+  if (n > 1 && !T) return -3;
+  if (!logabs) return -4;
+  if (!phase) return -5;
+  return launch_logpf_c128(n, ipiv, T, logabs, phase, (hipStream_t)stream);
+}
+
 size_t skf_pf_ratio_workspace(skf_int n, skf_int r) {
   if (n < 0 || r < 0 || r > pf_ratio_max_rank()) return 0;
   return pf_ratio_workspace_bytes(n, (int)r) + 256;

@@ -1,0 +1,289 @@
+// Pfaffian-only reduction of a complex (complex128) skew-symmetric matrix.
+//
+// The elimination step is the real one taken at even k only: pivot on column k
+// (largest |z|^2 = re^2 + im^2 below the diagonal, each product rounded, lowest
+// index on ties), interchange rows and columns k+1 and p, l = column k / alpha
+// below row k+1, v = column k+1 there, and add l v^T - v l^T to the trailing
+// block; rows/columns k and k+1 are then decoupled and Pf(A) = (-1)^{s + n/2}
+// prod_k T[k] (Parlett-Reid congruence with a unit lower triangular matrix; the
+// Pfaffian's transformation rule under congruence and interchanges).
+//
+// This first form is unblocked: the input's strict lower triangle is expanded
+// into a full skew copy in the workspace, and every step is five launches
+// (pivot search in one workgroup, row interchange, column interchange, l and v,
+// the trailing rank-2 update over a 2-D grid), each reading the pivot from device
+// memory, so the host only enqueues.  The update is HBM-bound: it reads and
+// writes the trailing square once per step.
+#include <math.h>
+
+#include "skf_internal.h"
+
+// Products are rounded before they are summed (no fused multiply-add), so each
+// complex product and |z|^2 are those of the textbook formulas.
+#pragma clang fp contract(off)
+
+namespace skf {
+namespace {
+
+struct c128 {
+  double re, im;
+};
+
+__device__ inline c128 cmul(c128 a, c128 b) { return {a.re * b.re - a.im * b.im, a.re * b.im + a.im * b.re}; }
+__device__ inline c128 csub(c128 a, c128 b) { return {a.re - b.re, a.im - b.im}; }
+__device__ inline c128 cadd(c128 a, c128 b) { return {a.re + b.re, a.im + b.im}; }
+// a / b by Smith's method (scaled by the larger component of b)
+__device__ inline c128 cdiv(c128 a, c128 b) {
+  if (fabs(b.re) >= fabs(b.im)) {
+    const double r = b.im / b.re, d = b.re + b.im * r;
+    return {(a.re + a.im * r) / d, (a.im - a.re * r) / d};
+  }
+  const double r = b.re / b.im, d = b.re * r + b.im;
+  return {(a.re * r + a.im) / d, (a.im * r - a.re) / d};
+}
+// |z|^2 with each product rounded, so the pivot order is that of the plain definition
+__device__ inline double cnorm2(c128 z) { return z.re * z.re + z.im * z.im; }
+
+// W (n x n, ld n) = the skew matrix whose strict lower triangle A holds.
+__global__ void form_full_kernel(int64_t n, const c128* __restrict__ A, int64_t lda, c128* __restrict__ W) {
+  const int64_t j = blockIdx.y;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+    c128 v = {0.0, 0.0};
+    if (i > j) v = A[i + j * lda];
+    else if (i < j) {
+      const c128 u = A[j + i * lda];
+      v = {-u.re, -u.im};
+    }
+    W[i + j * n] = v;
+  }
+}
+
+// Step k: pivot p = argmax_{i > k} |W[i,k]|^2 (lowest index on ties); records
+// ipiv[k+1] = p and sets *status on a non-finite column.
+__global__ void __launch_bounds__(256) pivot_kernel(int64_t n, int64_t k, const c128* __restrict__ W,
+                                                    int32_t* __restrict__ ipiv, int* __restrict__ piv,
+                                                    int* __restrict__ status) {
+  __shared__ double bv[256];
+  __shared__ int64_t bi[256];
+  __shared__ int bad;
+  if (*status != 0) return;
+  const int t = threadIdx.x;
+  if (t == 0) bad = 0;
+  __syncthreads();
+  double best = -1.0;
+  int64_t at = n;
+  for (int64_t i = k + 1 + t; i < n; i += 256) {
+    const c128 z = W[i + k * n];
+    if (!isfinite(z.re) || !isfinite(z.im)) bad = 1;
+    const double a = cnorm2(z);
+    if (a > best) {  // ascending i per thread: the first of equal values is kept
+      best = a;
+      at = i;
+    }
+  }
+  bv[t] = best;
+  bi[t] = at;
+  __syncthreads();
+  for (int h = 128; h > 0; h >>= 1) {
+    if (t < h) {
+      const double a = bv[t + h];
+      const int64_t ia = bi[t + h];
+      if (a > bv[t] || (a == bv[t] && ia < bi[t])) {
+        bv[t] = a;
+        bi[t] = ia;
+      }
+    }
+    __syncthreads();
+  }
+  if (t == 0) {
+    if (bad) {
+      *status = SKF_ENONFINITE;
+    } else {
+      *piv = (int)bi[0];
+      ipiv[k + 1] = (int32_t)bi[0];
+    }
+  }
+}
+
+// Interchange rows k+1 and p (columns k .. n-1 of the active part), then columns.
+__global__ void swap_rows_kernel(int64_t n, int64_t k, c128* __restrict__ W, const int* __restrict__ piv,
+                                 const int* __restrict__ status) {
+  if (*status != 0) return;
+  const int64_t p = *piv, r = k + 1;
+  if (p == r) return;
+  for (int64_t j = k + (int64_t)blockIdx.x * blockDim.x + threadIdx.x; j < n; j += (int64_t)gridDim.x * blockDim.x) {
+    const c128 a = W[r + j * n], b = W[p + j * n];
+    W[r + j * n] = b;
+    W[p + j * n] = a;
+  }
+}
+__global__ void swap_cols_kernel(int64_t n, int64_t k, c128* __restrict__ W, const int* __restrict__ piv,
+                                 const int* __restrict__ status) {
+  if (*status != 0) return;
+  const int64_t p = *piv, r = k + 1;
+  if (p == r) return;
+  for (int64_t i = k + (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+    const c128 a = W[i + r * n], b = W[i + p * n];
+    W[i + r * n] = b;
+    W[i + p * n] = a;
+  }
+}
+
+// alpha = W[k+1,k] -> T[k]; l = W[k+2:,k] / alpha (0 when alpha = 0), v = W[k+2:,k+1].
+__global__ void lv_kernel(int64_t n, int64_t k, const c128* __restrict__ W, c128* __restrict__ T,
+                          c128* __restrict__ l, c128* __restrict__ v, const int* __restrict__ status) {
+  if (*status != 0) return;
+  const c128 alpha = W[k + 1 + k * n];
+  const bool zero = alpha.re == 0.0 && alpha.im == 0.0;
+  if (blockIdx.x == 0 && threadIdx.x == 0) T[k] = alpha;
+  for (int64_t i = k + 2 + (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    l[i] = zero ? c128{0.0, 0.0} : cdiv(W[i + k * n], alpha);
+    v[i] = W[i + (k + 1) * n];
+  }
+}
+
+// W[i,j] += l_i v_j - v_i l_j for i, j >= k+2: a 64 x 16 tile per block of 64 x 4 threads.
+__global__ void update_kernel(int64_t n, int64_t k, c128* __restrict__ W, const c128* __restrict__ l,
+                              const c128* __restrict__ v, const int* __restrict__ status) {
+  if (*status != 0) return;
+  const int64_t i = k + 2 + (int64_t)blockIdx.x * 64 + threadIdx.x;
+  const int64_t j0 = k + 2 + (int64_t)blockIdx.y * 16;
+  if (i >= n) return;
+  const c128 li = l[i], vi = v[i];
+  for (int jj = threadIdx.y; jj < 16; jj += blockDim.y) {
+    const int64_t j = j0 + jj;
+    if (j >= n) break;
+    const c128 w = W[i + j * n];
+    W[i + j * n] = cadd(w, csub(cmul(li, v[j]), cmul(vi, l[j])));
+  }
+}
+
+// dinfo: status if set; n for odd n; else 1 + the first even k with T[k] = 0, or 0.
+__global__ void info_c128_kernel(int64_t n, const c128* __restrict__ T, const int* __restrict__ status,
+                                 int* __restrict__ dinfo) {
+  if (threadIdx.x != 0) return;
+  int v = *status;
+  if (v == 0 && (n & 1)) v = (int)n;
+  if (v == 0)
+    for (int64_t k = 0; k + 1 < n; k += 2)
+      if (T[k].re == 0.0 && T[k].im == 0.0) {
+        v = (int)(k + 1);
+        break;
+      }
+  *dinfo = v;
+}
+
+// log|Pf| and phase = Pf / |Pf| from (ipiv, T), in index order (one thread).
+__global__ void logpf_c128_kernel(int64_t n, const int32_t* __restrict__ ipiv, const c128* __restrict__ T,
+                                  double* logabs, double* phase) {
+  if (threadIdx.x != 0) return;
+  if (n == 0) {
+    *logabs = 0.0;
+    phase[0] = 1.0;
+    phase[1] = 0.0;
+    return;
+  }
+  if (n & 1) {
+    *logabs = -INFINITY;
+    phase[0] = phase[1] = 0.0;
+    return;
+  }
+  int64_t s = 0;
+  for (int64_t j = 0; j < n; ++j) s += (ipiv[j] != j);
+  c128 ph = {((s + n / 2) & 1) ? -1.0 : 1.0, 0.0};
+  double la = 0.0;
+  for (int64_t k = 0; k + 1 < n; k += 2) {
+    const c128 t = T[k];
+    const double a = hypot(t.re, t.im);
+    if (a == 0.0) {
+      *logabs = -INFINITY;
+      phase[0] = phase[1] = 0.0;
+      return;
+    }
+    la += log(a);
+    ph = cmul(ph, c128{t.re / a, t.im / a});
+  }
+  *logabs = la;
+  phase[0] = ph.re;
+  phase[1] = ph.im;
+}
+
+struct CWork {
+  c128* W;
+  c128* l;
+  c128* v;
+  int* piv;
+  int* status;
+  size_t bytes;
+};
+
+CWork c128_carve(void* base, int64_t n) {
+  CWork w{};
+  size_t off = 0;
+  auto take = [&](size_t b) {
+    size_t o = off;
+    off = align_up(off + b, 256);
+    return base ? (void*)((char*)base + o) : nullptr;
+  };
+  const int64_t m = std::max<int64_t>(n, 1);
+  w.W = (c128*)take(sizeof(c128) * (size_t)m * m);
+  w.l = (c128*)take(sizeof(c128) * (size_t)m);
+  w.v = (c128*)take(sizeof(c128) * (size_t)m);
+  w.piv = (int*)take(256);
+  w.status = (int*)take(256);
+  w.bytes = off;
+  return w;
+}
+
+}  // namespace
+
+size_t pfonly_c128_workspace_bytes(int64_t n) { return c128_carve(nullptr, n).bytes; }
+
+int run_pfonly_c128(int64_t n, const double* A, int64_t lda, int32_t* ipiv, double* T, void* work, size_t lwork,
+                    int* dinfo, hipStream_t s) {
+  CWork w = c128_carve(work, n);
+  if (lwork < w.bytes) return SKF_EWORK;
+  if (n > 65535) return SKF_ENOTIMPL;  // one grid row per column of the copy
+  int rc;
+  if ((rc = launch_fill_i32(w.status, 1, 0, s))) return rc;
+  if (n > 0 && (rc = launch_iota_i32(ipiv, (size_t)n, s))) return rc;
+  if (n > 1 && (rc = launch_fill_u64((uint64_t*)T, (size_t)(n - 1) * 2, 0, s))) return rc;
+  c128* Tc = (c128*)T;
+  if (n >= 2 && n % 2 == 0) {
+    const unsigned gx = (unsigned)std::min<int64_t>((n + 255) / 256, 1024);
+    hipLaunchKernelGGL(form_full_kernel, dim3(gx, (unsigned)n), dim3(256), 0, s, n, (const c128*)A, lda, w.W);
+    SKF_CHECK_LAUNCH("c128 form");
+    for (int64_t k = 0; k + 1 < n; k += 2) {
+      hipLaunchKernelGGL(pivot_kernel, dim3(1), dim3(256), 0, s, n, k, w.W, ipiv, w.piv, w.status);
+      SKF_CHECK_LAUNCH("c128 pivot");
+      const unsigned gs = (unsigned)std::min<int64_t>((n - k + 255) / 256, 1024);
+      hipLaunchKernelGGL(swap_rows_kernel, dim3(gs), dim3(256), 0, s, n, k, w.W, w.piv, w.status);
+      SKF_CHECK_LAUNCH("c128 swap rows");
+      hipLaunchKernelGGL(swap_cols_kernel, dim3(gs), dim3(256), 0, s, n, k, w.W, w.piv, w.status);
+      SKF_CHECK_LAUNCH("c128 swap cols");
+      hipLaunchKernelGGL(lv_kernel, dim3(gs), dim3(256), 0, s, n, k, w.W, Tc, w.l, w.v, w.status);
+      SKF_CHECK_LAUNCH("c128 lv");
+      const int64_t m = n - k - 2;
+      if (m > 0) {
+        hipLaunchKernelGGL(update_kernel, dim3((unsigned)((m + 63) / 64), (unsigned)((m + 15) / 16)), dim3(64, 4), 0,
+                           s, n, k, w.W, w.l, w.v, w.status);
+        SKF_CHECK_LAUNCH("c128 update");
+      }
+    }
+  }
+  if (dinfo) {
+    hipLaunchKernelGGL(info_c128_kernel, dim3(1), dim3(64), 0, s, n, Tc, w.status, dinfo);
+    SKF_CHECK_LAUNCH("c128 info");
+  }
+  return 0;
+}
+
+int launch_logpf_c128(int64_t n, const int32_t* ipiv, const double* T, double* logabs, double* phase,
+                      hipStream_t s) {
+  hipLaunchKernelGGL(logpf_c128_kernel, dim3(1), dim3(64), 0, s, n, ipiv, (const c128*)T, logabs, phase);
+  SKF_CHECK_LAUNCH("c128 logpf");
+  return 0;
+}
+
+}  // namespace skf

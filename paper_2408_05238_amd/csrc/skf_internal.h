@@ -138,6 +138,13 @@ int run_pf_ratio(int64_t n, int r, const double* LT, int64_t lda, const int32_t*
                  const double* U, int64_t ldu, const double* V, int64_t ldv, double* logabs, int* sign,
                  void* work, size_t lwork, int* dinfo, hipStream_t s);
 
+// Complex (complex128) Pfaffian-only reduction (complex.hip); A and T interleaved re, im.
+size_t pfonly_c128_workspace_bytes(int64_t n);
+int run_pfonly_c128(int64_t n, const double* A, int64_t lda, int32_t* ipiv, double* T, void* work, size_t lwork,
+                    int* dinfo, hipStream_t s);
+int launch_logpf_c128(int64_t n, const int32_t* ipiv, const double* T, double* logabs, double* phase,
+                      hipStream_t s);
+
 // Kernel timing hooks (api.hip): no-ops unless skf_profile_enable(1).
 void prof_begin(hipStream_t s);
 void prof_end(hipStream_t s, int cls, double flops);

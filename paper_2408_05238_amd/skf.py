@@ -29,7 +29,8 @@ ETIMEOUT = -105
 EXPORTS = [
     "skf_version", "skf_last_error", "skf_ltlt_workspace", "skf_ltlt", "skf_pfonly", "skf_logpf_from_factors",
     "skf_logpf_workspace", "skf_logpf", "skf_pfaffian", "skf_skr2k", "skf_skr2k_f32",
-    "skf_solve_workspace", "skf_solve", "skf_pf_ratio_workspace", "skf_pf_ratio", "skf_refine_workspace",
+    "skf_solve_workspace", "skf_solve", "skf_pf_ratio_workspace", "skf_pf_ratio", "skf_pfonly_c128_workspace",
+    "skf_pfonly_c128", "skf_logpf_c128_from_factors", "skf_refine_workspace",
     "skf_solve_refine",
     "skf_batched_workspace", "skf_ltlt_batched", "skf_pfonly_batched", "skf_logpf_batched", "skf_solve_batched",
     "skf_profile_enable", "skf_profile_read",
@@ -75,6 +76,9 @@ def _load():
                 "skf_skr2k_f32": (ci, [i64, i64, d, vp, i64, vp, i64, d, vp, i64, vp]),
                 "skf_solve_workspace": (sz, [i64, i64]),
                 "skf_solve": (ci, [i64, i64, vp, i64, vp, vp, vp, i64, vp, sz, vp, vp]),
+                "skf_pfonly_c128_workspace": (sz, [i64]),
+                "skf_pfonly_c128": (ci, [i64, vp, i64, vp, vp, vp, sz, vp, vp]),
+                "skf_logpf_c128_from_factors": (ci, [i64, vp, vp, vp, vp, vp]),
                 "skf_pf_ratio_workspace": (sz, [i64, i64]),
                 "skf_pf_ratio": (ci, [i64, i64, vp, i64, vp, vp, vp, i64, vp, i64, vp, vp, vp, sz, vp, vp]),
                 "skf_refine_workspace": (sz, [i64, i64]),
@@ -305,6 +309,39 @@ def solve(LT, ipiv, T, B, work=None, dinfo=None, stream=None):
                            work.numel(), _ptr(dinfo), _stream(stream))
     _check(rc, "skf_solve")
     return rc if dinfo is None else dinfo
+
+
+def pfonly_c128(A, ipiv=None, T=None, work=None, dinfo=None, stream=None):
+    """Pfaffian-only reduction of a complex128 skew matrix (column-major device
+    tensor, strict lower triangle read, not modified): (ipiv, T, info)."""
+    torch = _torch()
+    n = A.shape[0]
+    lda = _ld(A)
+    dev = A.device
+    if A.dtype != torch.complex128:
+        raise ValueError("expected a complex128 tensor")
+    if ipiv is None:
+        ipiv = torch.empty(max(n, 1), dtype=torch.int32, device=dev)
+    if T is None:
+        T = torch.empty(max(n - 1, 1), dtype=torch.complex128, device=dev)
+    if work is None:
+        work = workspace(int(_load().skf_pfonly_c128_workspace(n)), dev)
+    rc = _load().skf_pfonly_c128(n, _ptr(A), lda, _ptr(ipiv), _ptr(T), _ptr(work), work.numel(), _ptr(dinfo),
+                                 _stream(stream))
+    _check(rc, "skf_pfonly_c128")
+    return ipiv[:n], T[:max(n - 1, 0)], (rc if dinfo is None else dinfo)
+
+
+def logpf_c128_from_factors(n: int, ipiv, T, stream=None):
+    """(logabs, phase) device tensors: log|Pf| and Pf/|Pf| as complex128."""
+    torch = _torch()
+    dev = ipiv.device
+    la = torch.empty(1, dtype=torch.float64, device=dev)
+    ph = torch.empty(1, dtype=torch.complex128, device=dev)
+    Tp = T if T.numel() > 0 else torch.zeros(1, dtype=torch.complex128, device=dev)
+    rc = _load().skf_logpf_c128_from_factors(n, _ptr(ipiv), _ptr(Tp), _ptr(la), _ptr(ph), _stream(stream))
+    _check(rc, "skf_logpf_c128_from_factors")
+    return la, ph
 
 
 def pf_ratio_workspace(n: int, r: int) -> int:
