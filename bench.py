@@ -41,10 +41,10 @@ def parse():
     ap.add_argument("--cpu-seconds", type=float, default=12.0, help="target CPU time of the oracle sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--traffic", default=os.path.join(ROOT, "profiles", "skr2k_perm_n16384_traffic.txt"))
-    ap.add_argument("--workload", choices=["ltlt", "mixed", "batched", "serve"], default="ltlt",
+    ap.add_argument("--workload", choices=["ltlt", "mixed", "batched", "serve", "complex"], default="ltlt",
                     help="ltlt: the headline factorization; mixed: FP32-trailing + refinement vs FP64 solves "
                          "(n=16384, 32768, 16 RHS); batched: 8192 small matrices in one launch; serve: "
-                         "2000-request Poisson trace")
+                         "2000-request Poisson trace; complex: complex128 Pfaffian-only reduction (n=4096)")
     ap.add_argument("--sizes", default="16384,32768", help="orders for --workload mixed")
     ap.add_argument("--count", type=int, default=0, help="matrices (batched) or requests (serve); 0 = default")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -272,6 +272,60 @@ def bench_batched(args):
           f"log|Pf| and sign in one persistent launch (Pfaffian-only reduction)", **extra)
 
 
+def bench_complex(args):
+    """Complex128 Pfaffian-only reduction of one n x n complex skew Gaussian matrix
+    (real part seed/stream A, imaginary part seed/stream IMAG); n defaults to 4096."""
+    import numpy as np
+    import torch
+
+    from paper_2408_05238_amd import inputs, skf
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    skf.lib()
+    n = args.n if args.n != 16384 else 4096
+    dev = torch.device("cuda:0")
+    A = inputs.skew_gaussian_c128(n, args.seed)
+    dA = skf.to_device_colmajor(A, device=dev)
+    work = skf.workspace(int(skf.lib().skf_pfonly_c128_workspace(n)), dev)
+    ipiv = torch.empty(n, dtype=torch.int32, device=dev)
+    T = torch.empty(max(n - 1, 1), dtype=torch.complex128, device=dev)
+    dinfo = torch.zeros(1, dtype=torch.int32, device=dev)
+    for _ in range(args.warmup):
+        skf.pfonly_c128(dA, ipiv, T, work, dinfo)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        skf.pfonly_c128(dA, ipiv, T, work, dinfo)
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1e3 / args.steps
+    assert int(dinfo.item()) == 0
+    la, ph = skf.logpf_c128_from_factors(n, ipiv, T)
+    # algorithmic HBM bytes: each step reads and writes the trailing square once (16 B per entry)
+    nbytes = sum(2.0 * 16.0 * (n - k - 2) ** 2 for k in range(0, n - 1, 2) if n - k - 2 > 0)
+    gbs = nbytes / (ms * 1e-3) / 1e9
+    out = {"metric": f"complex128 Pfaffian-only reduction time at n={n}", "value": round(ms, 3), "unit": "ms",
+           "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms, 3),
+           "higher_is_better": False, "scaling": "weak", "vs_baseline": None, "dtype": "c128",
+           "data": "synthetic",
+           "config": {"workload": f"dense complex skew-symmetric Gaussian matrix n={n} (seed {args.seed}), "
+                                  "unblocked Pfaffian-only reduction", "n": n},
+           "roofline": {"bound": "hbm", "kernel": "whole reduction (trailing rank-2 updates dominate)",
+                        "achieved": round(gbs, 1), "peak": 8000.0, "unit": "GB/s", "frac": round(gbs / 8000.0, 4),
+                        "traffic": None, "algorithmic_bytes": nbytes},
+           "logabs_pf": float(la.item()), "phase": [float(ph.real.item()), float(ph.imag.item())],
+           "launches_per_reduction": 5 * (n // 2) + 1}
+    if not args.no_cpu_baseline:
+        import oracle
+        m = min(n, 1024)
+        t1 = time.perf_counter()
+        oracle.pfonly_c128(inputs.skew_gaussian_c128(m, args.seed))
+        ct = time.perf_counter() - t1
+        out["cpu_baseline"] = {"value": round(ct * 1e3 * (n / m) ** 3, 1), "unit": "ms", "cores": 1, "kind": "oracle",
+                               "sample": f"numpy oracle on the n={m} leading case of the same recipe, {ct:.2f} s, "
+                                         f"scaled by (n/{m})^3"}
+    print(json.dumps(out), flush=True)
+
+
 def bench_serve(args):
     """2000-request Poisson trace (seed 8): saturation run, then 0.7 x saturation."""
     import torch
@@ -314,7 +368,8 @@ def main():
               f"sharded across GPUs in this build.", file=sys.stderr)
         sys.exit(2)
     if args.workload != "ltlt":
-        return {"mixed": bench_mixed, "batched": bench_batched, "serve": bench_serve}[args.workload](args)
+        return {"mixed": bench_mixed, "batched": bench_batched, "serve": bench_serve,
+                "complex": bench_complex}[args.workload](args)
     import numpy as np
     import torch
 

@@ -9,6 +9,7 @@ Stream ids (the second key argument) used by the workloads:
     STREAM_B      = 1      right-hand sides of a solve
     STREAM_SIZES  = 2      sizes of a batch
     STREAM_SERVE  = 3      serving request mix
+    STREAM_IMAG   = 4      imaginary part of a complex skew matrix
     STREAM_BATCH0 = 1000   matrix b of a batch uses stream 1000 + b
 """
 from __future__ import annotations
@@ -23,6 +24,7 @@ STREAM_A = 0
 STREAM_B = 1
 STREAM_SIZES = 2
 STREAM_SERVE = 3
+STREAM_IMAG = 4
 STREAM_BATCH0 = 1000
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
@@ -122,6 +124,13 @@ def skew_gaussian(n: int, seed: int, stream: int = STREAM_A, lda: int | None = N
         for t in ths:
             t.join()
     return buf[:n, :n]
+
+
+def skew_gaussian_c128(n: int, seed: int, threads: int = 8) -> np.ndarray:
+    """Complex skew matrix: real part from STREAM_A, imaginary part from STREAM_IMAG."""
+    re = skew_gaussian(n, seed, STREAM_A, threads=threads)
+    im = skew_gaussian(n, seed, STREAM_IMAG, threads=threads)
+    return re + 1j * im
 
 
 def gaussian(rows: int, cols: int, seed: int, stream: int = STREAM_B) -> np.ndarray:
