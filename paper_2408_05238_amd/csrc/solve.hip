@@ -152,9 +152,49 @@ __device__ inline void block_mv(const double (&Lb)[BS][BS + 1], const double (&y
   for (int q = 0; q < 4; ++q) acc[i][4 * g + q] -= s4[q];
 }
 
+// Fold blocks for the last term of each block's substitution: with Db and Lb
+// the diagonal inverse and the chain-neighbour block exactly as the substitution
+// holds them in LDS (J = I-1 forward, I+1 backward), M_I = Db Lb, stored so that
+// element e of the substitution's load pattern sits at M + I BS^2 + e.
+template <bool kTrans>
+__global__ void __launch_bounds__(NT) fold_kernel(int64_t n, const double* __restrict__ LT, int64_t lda,
+                                                  const double* __restrict__ Dinv, double* __restrict__ M) {
+  __shared__ double Db[BS][BS + 1];
+  __shared__ double Lb[BS][BS + 1];
+  const int64_t nb = (n + BS - 1) / BS;
+  const int64_t I = blockIdx.x;
+  if (kTrans ? I + 1 >= nb : I == 0) return;
+  const int64_t J = kTrans ? I + 1 : I - 1;
+  const int64_t r0 = I * BS, c0 = J * BS;
+  const int tid = threadIdx.x;
+  const double* D = Dinv + I * BS * BS;
+  for (int e = tid; e < BS * BS; e += NT) {
+    const int i = kTrans ? e / BS : e % BS, j = kTrans ? e % BS : e / BS;
+    Db[i][j] = kTrans ? D[j + i * BS] : D[i + j * BS];
+    const int64_t a = kTrans ? c0 + j : r0 + i, b = kTrans ? r0 + i : c0 + j;
+    Lb[i][j] = (a < n && b >= 1) ? LT[a + (b - 1) * lda] : 0.0;
+  }
+  __syncthreads();
+  const int i = tid % BS, g = tid / BS;
+  double m[BS / 4];
+#pragma unroll
+  for (int t = 0; t < BS / 4; ++t) m[t] = 0.0;
+  for (int k = 0; k < BS; ++k) {
+    const double d = Db[i][k];
+#pragma unroll
+    for (int t = 0; t < BS / 4; ++t) m[t] += d * Lb[k][(BS / 4) * g + t];
+  }
+#pragma unroll
+  for (int t = 0; t < BS / 4; ++t) {
+    const int j = (BS / 4) * g + t;
+    M[I * BS * BS + (kTrans ? j + i * BS : i + j * BS)] = m[t];
+  }
+}
+
 template <bool kTrans>
 __global__ void __launch_bounds__(NT) trsv_kernel(int64_t n, const double* __restrict__ LT, int64_t lda,
-                                                  const double* __restrict__ Dinv, double* __restrict__ Y,
+                                                  const double* __restrict__ Dinv,
+                                                  const double* __restrict__ Mfold, double* __restrict__ Y,
                                                   uint64_t* __restrict__ pub, uint32_t tag, int* status) {
   __shared__ double Lb[2][BS][BS + 1];
   __shared__ double Db[BS][BS + 1];  // inv(L_II), or its transpose (backward)
@@ -209,6 +249,19 @@ __global__ void __launch_bounds__(NT) trsv_kernel(int64_t n, const double* __res
       Lb[buf][i][j] = (a < n && b >= 1) ? v[q] : 0.0;
     }
   };
+  // the fold block of I (element e at Mfold + I BS^2 + e, contiguous per thread group)
+  auto fetch_fold = [&](double (&w8)[kLdPerThread]) {
+#pragma unroll
+    for (int q = 0; q < kLdPerThread; ++q) w8[q] = Mfold[I * BS * BS + tid + NT * q];
+  };
+  auto put_fold = [&](int buf, const double (&w8)[kLdPerThread]) {
+#pragma unroll
+    for (int q = 0; q < kLdPerThread; ++q) {
+      int i, j;
+      elem(q, &i, &j);
+      Lb[buf][i][j] = w8[q];
+    }
+  };
   // contributions of the other blocks J (J < I forward, J > I backward), nearest-ready first
   const int64_t count = kTrans ? nb - 1 - I : I;
   const int64_t jfirst = kTrans ? nb - 1 : 0;
@@ -228,17 +281,42 @@ __global__ void __launch_bounds__(NT) trsv_kernel(int64_t n, const double* __res
       w[q][1] = ld_word(pj + 2 * e + 1);
     }
   };
+  // The last block J on the chain (I-1 forward, I+1 backward) is folded into the
+  // diagonal solve: its slot holds M_I = inv(L_II) L_IJ (precomputed), P =
+  // inv(L_II) acc is formed from the other blocks before Y_J is awaited, and then
+  // Y_I = P - M_I Y_J is a single product.
   if (count > 0) {
     load_y(jfirst);
-    fetch(jfirst, v);
-    put(0, jfirst, v);
+    if (count == 1) {
+      fetch_fold(v);
+      put_fold(0, v);
+    } else {
+      fetch(jfirst, v);
+      put(0, jfirst, v);
+    }
   }
   __syncthreads();
+  bool folded = false;
+  double s4[4] = {0.0, 0.0, 0.0, 0.0};
   for (int64_t idx = 0; idx < count; ++idx) {
     const int64_t J = jfirst + idx * jstep;
     const int buf = (int)(idx & 1);
     const bool more = idx + 1 < count;
-    if (more) fetch(J + jstep, v);
+    const bool next_last = idx + 2 == count;
+    if (more) {
+      if (next_last) fetch_fold(v);
+      else fetch(J + jstep, v);
+    }
+    if (!more) {
+      __syncthreads();  // acc complete; Lb[buf] holds M_I
+      const int i = tid % BS, g = tid / BS;
+#pragma unroll 8
+      for (int j = 0; j < BS; ++j) {
+        const double l = Db[i][j];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) s4[q] += l * acc[j][4 * g + q];
+      }
+    }
     {
       auto load_all = [&]() { load_y(J); };
       uint64_t t0 = 0;
@@ -266,9 +344,21 @@ __global__ void __launch_bounds__(NT) trsv_kernel(int64_t n, const double* __res
     }
     __syncthreads();
     if (stop) break;
+    if (!more) {
+      const int i = tid % BS, g = tid / BS;
+#pragma unroll 8
+      for (int j = 0; j < BS; ++j) {
+        const double l = Lb[buf][i][j];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) s4[q] -= l * yJ[buf][j][4 * g + q];
+      }
+      folded = true;
+      break;
+    }
     block_mv(Lb[buf], yJ[buf], acc, tid);
     // the other buffer was last read before this iteration's barriers
-    if (more) put(buf ^ 1, J + jstep, v);
+    if (next_last) put_fold(buf ^ 1, v);
+    else put(buf ^ 1, J + jstep, v);
   }
   __syncthreads();
   if (stop) {
@@ -280,16 +370,17 @@ __global__ void __launch_bounds__(NT) trsv_kernel(int64_t n, const double* __res
     }
     return;
   }
-  // Y_I = inv(L_II) acc  (forward)  or  inv(L_II)^T acc  (backward)
+  // Y_I = inv(L_II) acc  (forward)  or  inv(L_II)^T acc  (backward), unless folded above
   {
     // thread (row i, column group g) forms four results; acc is read-only here
     const int i = tid % BS, g = tid / BS;
-    double s4[4] = {0.0, 0.0, 0.0, 0.0};
+    if (!folded) {
 #pragma unroll 8
-    for (int j = 0; j < BS; ++j) {
-      const double l = Db[i][j];
+      for (int j = 0; j < BS; ++j) {
+        const double l = Db[i][j];
 #pragma unroll
-      for (int q = 0; q < 4; ++q) s4[q] += l * acc[j][4 * g + q];
+        for (int q = 0; q < 4; ++q) s4[q] += l * acc[j][4 * g + q];
+      }
     }
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
@@ -652,6 +743,8 @@ __global__ void solve_info_kernel(int64_t n, const double* __restrict__ T, const
 struct SolveWork {
   int32_t* perm;
   double* Dinv;
+  double* Mf;  // fold blocks, forward (nb*BS*BS)
+  double* Mb;  // fold blocks, backward
   double* Y;
   double* tri;
   uint64_t* pub;
@@ -670,6 +763,8 @@ static SolveWork solve_carve(void* base, int64_t n) {
   const int64_t nb = (n + BS - 1) / BS;
   w.perm = (int32_t*)take(sizeof(int32_t) * (size_t)std::max<int64_t>(n, 1));
   w.Dinv = (double*)take(sizeof(double) * (size_t)std::max<int64_t>(nb, 1) * BS * BS);
+  w.Mf = (double*)take(sizeof(double) * (size_t)std::max<int64_t>(nb, 1) * BS * BS);
+  w.Mb = (double*)take(sizeof(double) * (size_t)std::max<int64_t>(nb, 1) * BS * BS);
   w.Y = (double*)take(sizeof(double) * (size_t)std::max<int64_t>(n, 1) * RC);
   w.tri = (double*)take(sizeof(double) * (size_t)std::max<int64_t>(n, 1) * 2);
   w.pub = (uint64_t*)take(sizeof(uint64_t) * (size_t)std::max<int64_t>(nb, 1) * BS * RC * 2);
@@ -698,6 +793,10 @@ int run_solve(int64_t n, int64_t nrhs, const double* LT, int64_t lda, const int3
     SKF_CHECK_LAUNCH("perm");
     hipLaunchKernelGGL(inv_diag_kernel, dim3((unsigned)nb), dim3(BS), 0, s, n, LT, lda, w.Dinv);
     SKF_CHECK_LAUNCH("inv_diag");
+    hipLaunchKernelGGL(fold_kernel<false>, dim3((unsigned)nb), dim3(NT), 0, s, n, LT, lda, w.Dinv, w.Mf);
+    SKF_CHECK_LAUNCH("fold fwd");
+    hipLaunchKernelGGL(fold_kernel<true>, dim3((unsigned)nb), dim3(NT), 0, s, n, LT, lda, w.Dinv, w.Mb);
+    SKF_CHECK_LAUNCH("fold bwd");
     if ((rc = launch_fill_u64(w.pub, (size_t)nb * BS * RC * 2, 0, s))) return rc;
     unsigned gx = (unsigned)std::min<int64_t>((n + 255) / 256, 1024);
     uint32_t tag = 0;
@@ -706,13 +805,13 @@ int run_solve(int64_t n, int64_t nrhs, const double* LT, int64_t lda, const int3
       hipLaunchKernelGGL(gather_kernel, dim3(gx, RC), dim3(256), 0, s, n, nr, w.perm, B + c0 * ldb, ldb, w.Y);
       SKF_CHECK_LAUNCH("gather");
       ++tag;
-      hipLaunchKernelGGL(trsv_kernel<false>, dim3((unsigned)nb), dim3(NT), 0, s, n, LT, lda, w.Dinv, w.Y,
+      hipLaunchKernelGGL(trsv_kernel<false>, dim3((unsigned)nb), dim3(NT), 0, s, n, LT, lda, w.Dinv, w.Mf, w.Y,
                          w.pub, tag, w.status);
       SKF_CHECK_LAUNCH("trsv fwd");
       hipLaunchKernelGGL(tridiag_kernel, dim3(1), dim3(256), 0, s, n, T, w.Y, w.tri);
       SKF_CHECK_LAUNCH("tridiag");
       ++tag;
-      hipLaunchKernelGGL(trsv_kernel<true>, dim3((unsigned)nb), dim3(NT), 0, s, n, LT, lda, w.Dinv, w.Y,
+      hipLaunchKernelGGL(trsv_kernel<true>, dim3((unsigned)nb), dim3(NT), 0, s, n, LT, lda, w.Dinv, w.Mb, w.Y,
                          w.pub, tag, w.status);
       SKF_CHECK_LAUNCH("trsv bwd");
       hipLaunchKernelGGL(scatter_kernel, dim3(gx, RC), dim3(256), 0, s, n, nr, w.perm, w.Y, B + c0 * ldb, ldb);
