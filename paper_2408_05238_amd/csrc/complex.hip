@@ -9,10 +9,10 @@
 // Pfaffian's transformation rule under congruence and interchanges).
 //
 // This first form is unblocked: the input's strict lower triangle is expanded
-// into a full skew copy in the workspace, and every step is five launches
-// (pivot search in one workgroup, row interchange, column interchange, l and v,
-// the trailing rank-2 update over a 2-D grid), each reading the pivot from device
-// memory, so the host only enqueues.  The update is HBM-bound: it reads and
+// into a full skew copy in the workspace, and every step is three launches (pivot
+// search in one workgroup, the symmetric interchange, the trailing rank-2 update
+// over a 2-D grid with l and v formed on the fly), each reading the pivot from
+// device memory, so the host only enqueues.  The update is HBM-bound: it reads and
 // writes the trailing square once per step.
 #include <math.h>
 
@@ -105,57 +105,61 @@ __global__ void __launch_bounds__(256) pivot_kernel(int64_t n, int64_t k, const 
   }
 }
 
-// Interchange rows k+1 and p (columns k .. n-1 of the active part), then columns.
-__global__ void swap_rows_kernel(int64_t n, int64_t k, c128* __restrict__ W, const int* __restrict__ piv,
-                                 const int* __restrict__ status) {
+// Symmetric interchange of rows/columns k+1 and p over the active part (index
+// t >= k): thread t swaps (k+1, t) <-> (p, t) and (t, k+1) <-> (t, p), four
+// entries no other thread touches when t is neither k+1 nor p; the 2 x 2 block
+// of those two indices is permuted by one thread.  The pivot T[k] = W[k+1, k]
+// after the interchange is recorded by the thread of t = k.
+__global__ void swap_kernel(int64_t n, int64_t k, c128* __restrict__ W, c128* __restrict__ T,
+                            const int* __restrict__ piv, const int* __restrict__ status) {
   if (*status != 0) return;
   const int64_t p = *piv, r = k + 1;
-  if (p == r) return;
-  for (int64_t j = k + (int64_t)blockIdx.x * blockDim.x + threadIdx.x; j < n; j += (int64_t)gridDim.x * blockDim.x) {
-    const c128 a = W[r + j * n], b = W[p + j * n];
-    W[r + j * n] = b;
-    W[p + j * n] = a;
-  }
-}
-__global__ void swap_cols_kernel(int64_t n, int64_t k, c128* __restrict__ W, const int* __restrict__ piv,
-                                 const int* __restrict__ status) {
-  if (*status != 0) return;
-  const int64_t p = *piv, r = k + 1;
-  if (p == r) return;
-  for (int64_t i = k + (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
-    const c128 a = W[i + r * n], b = W[i + p * n];
-    W[i + r * n] = b;
-    W[i + p * n] = a;
+  for (int64_t t = k + (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < n; t += (int64_t)gridDim.x * blockDim.x) {
+    if (p != r) {
+      if (t == r) {
+        const c128 a = W[r + r * n], b = W[r + p * n], c = W[p + r * n], d = W[p + p * n];
+        W[r + r * n] = d;
+        W[r + p * n] = c;
+        W[p + r * n] = b;
+        W[p + p * n] = a;
+      } else if (t != p) {
+        const c128 a = W[r + t * n], b = W[p + t * n];
+        W[r + t * n] = b;
+        W[p + t * n] = a;
+        const c128 c = W[t + r * n], d = W[t + p * n];
+        W[t + r * n] = d;
+        W[t + p * n] = c;
+      }
+    }
+    if (t == k) T[k] = W[r + k * n];  // this thread wrote (k+1, k) itself
   }
 }
 
-// alpha = W[k+1,k] -> T[k]; l = W[k+2:,k] / alpha (0 when alpha = 0), v = W[k+2:,k+1].
-__global__ void lv_kernel(int64_t n, int64_t k, const c128* __restrict__ W, c128* __restrict__ T,
-                          c128* __restrict__ l, c128* __restrict__ v, const int* __restrict__ status) {
+// W[i,j] += l_i v_j - v_i l_j for i, j >= k+2, with l = W[:,k] / alpha (0 when
+// alpha = W[k+1,k] is 0) and v = W[:,k+1] formed on the fly (those two columns are
+// not written here): a 64 x 16 tile per block of 64 x 4 threads, the tile's 16
+// column values of l and v computed once into LDS.
+__global__ void update_kernel(int64_t n, int64_t k, c128* __restrict__ W, const int* __restrict__ status) {
+  __shared__ c128 lj[16], vj[16];
   if (*status != 0) return;
   const c128 alpha = W[k + 1 + k * n];
   const bool zero = alpha.re == 0.0 && alpha.im == 0.0;
-  if (blockIdx.x == 0 && threadIdx.x == 0) T[k] = alpha;
-  for (int64_t i = k + 2 + (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
-       i += (int64_t)gridDim.x * blockDim.x) {
-    l[i] = zero ? c128{0.0, 0.0} : cdiv(W[i + k * n], alpha);
-    v[i] = W[i + (k + 1) * n];
-  }
-}
-
-// W[i,j] += l_i v_j - v_i l_j for i, j >= k+2: a 64 x 16 tile per block of 64 x 4 threads.
-__global__ void update_kernel(int64_t n, int64_t k, c128* __restrict__ W, const c128* __restrict__ l,
-                              const c128* __restrict__ v, const int* __restrict__ status) {
-  if (*status != 0) return;
-  const int64_t i = k + 2 + (int64_t)blockIdx.x * 64 + threadIdx.x;
   const int64_t j0 = k + 2 + (int64_t)blockIdx.y * 16;
+  if (threadIdx.y == 0 && threadIdx.x < 16) {
+    const int64_t j = min(j0 + threadIdx.x, n - 1);
+    lj[threadIdx.x] = zero ? c128{0.0, 0.0} : cdiv(W[j + k * n], alpha);
+    vj[threadIdx.x] = W[j + (k + 1) * n];
+  }
+  __syncthreads();
+  const int64_t i = k + 2 + (int64_t)blockIdx.x * 64 + threadIdx.x;
   if (i >= n) return;
-  const c128 li = l[i], vi = v[i];
+  const c128 li = zero ? c128{0.0, 0.0} : cdiv(W[i + k * n], alpha);
+  const c128 vi = W[i + (k + 1) * n];
   for (int jj = threadIdx.y; jj < 16; jj += blockDim.y) {
     const int64_t j = j0 + jj;
     if (j >= n) break;
     const c128 w = W[i + j * n];
-    W[i + j * n] = cadd(w, csub(cmul(li, v[j]), cmul(vi, l[j])));
+    W[i + j * n] = cadd(w, csub(cmul(li, vj[jj]), cmul(vi, lj[jj])));
   }
 }
 
@@ -211,8 +215,6 @@ __global__ void logpf_c128_kernel(int64_t n, const int32_t* __restrict__ ipiv, c
 
 struct CWork {
   c128* W;
-  c128* l;
-  c128* v;
   int* piv;
   int* status;
   size_t bytes;
@@ -228,8 +230,6 @@ CWork c128_carve(void* base, int64_t n) {
   };
   const int64_t m = std::max<int64_t>(n, 1);
   w.W = (c128*)take(sizeof(c128) * (size_t)m * m);
-  w.l = (c128*)take(sizeof(c128) * (size_t)m);
-  w.v = (c128*)take(sizeof(c128) * (size_t)m);
   w.piv = (int*)take(256);
   w.status = (int*)take(256);
   w.bytes = off;
@@ -258,16 +258,12 @@ int run_pfonly_c128(int64_t n, const double* A, int64_t lda, int32_t* ipiv, doub
       hipLaunchKernelGGL(pivot_kernel, dim3(1), dim3(256), 0, s, n, k, w.W, ipiv, w.piv, w.status);
       SKF_CHECK_LAUNCH("c128 pivot");
       const unsigned gs = (unsigned)std::min<int64_t>((n - k + 255) / 256, 1024);
-      hipLaunchKernelGGL(swap_rows_kernel, dim3(gs), dim3(256), 0, s, n, k, w.W, w.piv, w.status);
-      SKF_CHECK_LAUNCH("c128 swap rows");
-      hipLaunchKernelGGL(swap_cols_kernel, dim3(gs), dim3(256), 0, s, n, k, w.W, w.piv, w.status);
-      SKF_CHECK_LAUNCH("c128 swap cols");
-      hipLaunchKernelGGL(lv_kernel, dim3(gs), dim3(256), 0, s, n, k, w.W, Tc, w.l, w.v, w.status);
-      SKF_CHECK_LAUNCH("c128 lv");
+      hipLaunchKernelGGL(swap_kernel, dim3(gs), dim3(256), 0, s, n, k, w.W, Tc, w.piv, w.status);
+      SKF_CHECK_LAUNCH("c128 swap");
       const int64_t m = n - k - 2;
       if (m > 0) {
         hipLaunchKernelGGL(update_kernel, dim3((unsigned)((m + 63) / 64), (unsigned)((m + 15) / 16)), dim3(64, 4), 0,
-                           s, n, k, w.W, w.l, w.v, w.status);
+                           s, n, k, w.W, w.status);
         SKF_CHECK_LAUNCH("c128 update");
       }
     }
