@@ -313,7 +313,7 @@ def bench_complex(args):
                         "achieved": round(gbs, 1), "peak": 8000.0, "unit": "GB/s", "frac": round(gbs / 8000.0, 4),
                         "traffic": None, "algorithmic_bytes": nbytes},
            "logabs_pf": float(la.item()), "phase": [float(ph.real.item()), float(ph.imag.item())],
-           "launches_per_reduction": 3 * (n // 2) + 1}
+           "launches_per_reduction": 2 * (n // 2) + 1}
     if not args.no_cpu_baseline:
         import oracle
         m = min(n, 1024)

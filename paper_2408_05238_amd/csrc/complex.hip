@@ -9,10 +9,11 @@
 // Pfaffian's transformation rule under congruence and interchanges).
 //
 // This first form is unblocked: the input's strict lower triangle is expanded
-// into a full skew copy in the workspace, and every step is three launches (pivot
-// search in one workgroup, the symmetric interchange, the trailing rank-2 update
-// over a 2-D grid with l and v formed on the fly), each reading the pivot from
-// device memory, so the host only enqueues.  The update is HBM-bound: it reads and
+// into a full skew copy in the workspace, and every step is two launches: the
+// symmetric interchange (which first reduces the pivot search's per-block
+// partials) and the trailing rank-2 update over a 2-D grid, which forms l and v
+// on the fly and leaves the partials of the next pivot column.  The pivot
+// passes through device memory, so the host only enqueues.  The update is HBM-bound: it reads and
 // writes the trailing square once per step.
 #include <math.h>
 
@@ -58,51 +59,44 @@ __global__ void form_full_kernel(int64_t n, const c128* __restrict__ A, int64_t 
   }
 }
 
-// Step k: pivot p = argmax_{i > k} |W[i,k]|^2 (lowest index on ties); records
-// ipiv[k+1] = p and sets *status on a non-finite column.
-__global__ void __launch_bounds__(256) pivot_kernel(int64_t n, int64_t k, const c128* __restrict__ W,
-                                                    int32_t* __restrict__ ipiv, int* __restrict__ piv,
-                                                    int* __restrict__ status) {
-  __shared__ double bv[256];
-  __shared__ int64_t bi[256];
-  __shared__ int bad;
-  if (*status != 0) return;
-  const int t = threadIdx.x;
-  if (t == 0) bad = 0;
-  __syncthreads();
-  double best = -1.0;
-  int64_t at = n;
-  for (int64_t i = k + 1 + t; i < n; i += 256) {
-    const c128 z = W[i + k * n];
-    if (!isfinite(z.re) || !isfinite(z.im)) bad = 1;
-    const double a = cnorm2(z);
-    if (a > best) {  // ascending i per thread: the first of equal values is kept
-      best = a;
-      at = i;
+// Pivot search, split: every 64-row block of the previous step's update (or of
+// an initial pass for column 0) leaves the arg-max of |W[i,c]|^2 over its rows
+// that are candidates (i > c) and a non-finite flag; the interchange kernel
+// reduces those partials.  Ties go to the lowest index at both levels.
+struct Best {
+  double key;
+  int idx;
+  int bad;
+};
+
+__device__ inline void wave_best(double& key, int& idx) {
+  for (int off = 32; off > 0; off >>= 1) {
+    const double k2 = __shfl_xor(key, off);
+    const int i2 = __shfl_xor(idx, off);
+    if (k2 > key || (k2 == key && i2 < idx)) {
+      key = k2;
+      idx = i2;
     }
   }
-  bv[t] = best;
-  bi[t] = at;
-  __syncthreads();
-  for (int h = 128; h > 0; h >>= 1) {
-    if (t < h) {
-      const double a = bv[t + h];
-      const int64_t ia = bi[t + h];
-      if (a > bv[t] || (a == bv[t] && ia < bi[t])) {
-        bv[t] = a;
-        bi[t] = ia;
-      }
-    }
-    __syncthreads();
-  }
-  if (t == 0) {
-    if (bad) {
-      *status = SKF_ENONFINITE;
-    } else {
-      *piv = (int)bi[0];
-      ipiv[k + 1] = (int32_t)bi[0];
-    }
-  }
+}
+
+// one 64-lane wave per block: rows i = base + 64 b + lane of column c (candidates i > c)
+__device__ inline void block_partial(int64_t n, int64_t c, int64_t i, c128 z, Best* __restrict__ part, int b) {
+  const bool cand = i > c && i < n;
+  const bool nonfin = cand && !(isfinite(z.re) && isfinite(z.im));
+  double key = (cand && !nonfin) ? cnorm2(z) : -1.0;
+  int idx = cand ? (int)i : INT32_MAX;
+  const uint64_t badw = __ballot(nonfin);
+  wave_best(key, idx);
+  if ((threadIdx.x & 63) == 0) part[b] = Best{key, idx, badw != 0};
+}
+
+// partials of column 0 (rows 64 b + lane)
+__global__ void __launch_bounds__(64) init_partials_kernel(int64_t n, const c128* __restrict__ W,
+                                                           Best* __restrict__ part) {
+  const int64_t i = (int64_t)blockIdx.x * 64 + threadIdx.x;
+  const c128 z = (i < n) ? W[i] : c128{0.0, 0.0};
+  block_partial(n, 0, i, z, part, (int)blockIdx.x);
 }
 
 // Symmetric interchange of rows/columns k+1 and p over the active part (index
@@ -110,10 +104,44 @@ __global__ void __launch_bounds__(256) pivot_kernel(int64_t n, int64_t k, const 
 // entries no other thread touches when t is neither k+1 nor p; the 2 x 2 block
 // of those two indices is permuted by one thread.  The pivot T[k] = W[k+1, k]
 // after the interchange is recorded by the thread of t = k.
-__global__ void swap_kernel(int64_t n, int64_t k, c128* __restrict__ W, c128* __restrict__ T,
-                            const int* __restrict__ piv, const int* __restrict__ status) {
+__global__ void __launch_bounds__(256) swap_kernel(int64_t n, int64_t k, c128* __restrict__ W,
+                                                   c128* __restrict__ T, int32_t* __restrict__ ipiv,
+                                                   const Best* __restrict__ part, int* __restrict__ status) {
+  __shared__ double bv[256];
+  __shared__ int bi[256];
+  __shared__ int sbad;
   if (*status != 0) return;
-  const int64_t p = *piv, r = k + 1;
+  // reduce the partials of column k: blocks of rows k + 64 b + lane
+  const int nblk = (int)((n - k + 63) / 64);
+  const int tt = threadIdx.x;
+  if (tt == 0) sbad = 0;
+  __syncthreads();
+  double key = -1.0;
+  int idx = INT32_MAX;
+  for (int b = tt; b < nblk; b += 256) {
+    const Best q = part[b];
+    if (q.bad) sbad = 1;
+    if (q.key > key || (q.key == key && q.idx < idx)) {
+      key = q.key;
+      idx = q.idx;
+    }
+  }
+  bv[tt] = key;
+  bi[tt] = idx;
+  __syncthreads();
+  for (int h = 128; h > 0; h >>= 1) {
+    if (tt < h && (bv[tt + h] > bv[tt] || (bv[tt + h] == bv[tt] && bi[tt + h] < bi[tt]))) {
+      bv[tt] = bv[tt + h];
+      bi[tt] = bi[tt + h];
+    }
+    __syncthreads();
+  }
+  if (sbad) {
+    if (blockIdx.x == 0 && tt == 0) atomicMin(status, SKF_ENONFINITE);
+    return;
+  }
+  const int64_t p = bi[0], r = k + 1;
+  if (blockIdx.x == 0 && tt == 0) ipiv[r] = (int32_t)p;
   for (int64_t t = k + (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < n; t += (int64_t)gridDim.x * blockDim.x) {
     if (p != r) {
       if (t == r) {
@@ -139,7 +167,8 @@ __global__ void swap_kernel(int64_t n, int64_t k, c128* __restrict__ W, c128* __
 // alpha = W[k+1,k] is 0) and v = W[:,k+1] formed on the fly (those two columns are
 // not written here): a 64 x 16 tile per block of 64 x 4 threads, the tile's 16
 // column values of l and v computed once into LDS.
-__global__ void update_kernel(int64_t n, int64_t k, c128* __restrict__ W, const int* __restrict__ status) {
+__global__ void __launch_bounds__(256) update_kernel(int64_t n, int64_t k, c128* __restrict__ W,
+                                                     Best* __restrict__ part, const int* __restrict__ status) {
   __shared__ c128 lj[16], vj[16];
   if (*status != 0) return;
   const c128 alpha = W[k + 1 + k * n];
@@ -152,15 +181,21 @@ __global__ void update_kernel(int64_t n, int64_t k, c128* __restrict__ W, const 
   }
   __syncthreads();
   const int64_t i = k + 2 + (int64_t)blockIdx.x * 64 + threadIdx.x;
-  if (i >= n) return;
-  const c128 li = zero ? c128{0.0, 0.0} : cdiv(W[i + k * n], alpha);
-  const c128 vi = W[i + (k + 1) * n];
-  for (int jj = threadIdx.y; jj < 16; jj += blockDim.y) {
-    const int64_t j = j0 + jj;
-    if (j >= n) break;
-    const c128 w = W[i + j * n];
-    W[i + j * n] = cadd(w, csub(cmul(li, vj[jj]), cmul(vi, lj[jj])));
+  c128 first = {0.0, 0.0};  // the new W[i, k+2] (column jj = 0 of the first tile column)
+  if (i < n) {
+    const c128 li = zero ? c128{0.0, 0.0} : cdiv(W[i + k * n], alpha);
+    const c128 vi = W[i + (k + 1) * n];
+    for (int jj = threadIdx.y; jj < 16; jj += blockDim.y) {
+      const int64_t j = j0 + jj;
+      if (j >= n) break;
+      const c128 w = W[i + j * n];
+      const c128 nw = cadd(w, csub(cmul(li, vj[jj]), cmul(vi, lj[jj])));
+      W[i + j * n] = nw;
+      if (jj == 0) first = nw;
+    }
   }
+  // the next step's pivot column is k+2: this block's partial over rows i > k+2
+  if (blockIdx.y == 0 && threadIdx.y == 0) block_partial(n, k + 2, i, first, part, (int)blockIdx.x);
 }
 
 // dinfo: status if set; n for odd n; else 1 + the first even k with T[k] = 0, or 0.
@@ -215,7 +250,7 @@ __global__ void logpf_c128_kernel(int64_t n, const int32_t* __restrict__ ipiv, c
 
 struct CWork {
   c128* W;
-  int* piv;
+  Best* part;
   int* status;
   size_t bytes;
 };
@@ -230,7 +265,7 @@ CWork c128_carve(void* base, int64_t n) {
   };
   const int64_t m = std::max<int64_t>(n, 1);
   w.W = (c128*)take(sizeof(c128) * (size_t)m * m);
-  w.piv = (int*)take(256);
+  w.part = (Best*)take(sizeof(Best) * (size_t)((m + 63) / 64 + 1));
   w.status = (int*)take(256);
   w.bytes = off;
   return w;
@@ -254,16 +289,16 @@ int run_pfonly_c128(int64_t n, const double* A, int64_t lda, int32_t* ipiv, doub
     const unsigned gx = (unsigned)std::min<int64_t>((n + 255) / 256, 1024);
     hipLaunchKernelGGL(form_full_kernel, dim3(gx, (unsigned)n), dim3(256), 0, s, n, (const c128*)A, lda, w.W);
     SKF_CHECK_LAUNCH("c128 form");
+    hipLaunchKernelGGL(init_partials_kernel, dim3((unsigned)((n + 63) / 64)), dim3(64), 0, s, n, w.W, w.part);
+    SKF_CHECK_LAUNCH("c128 partials");
     for (int64_t k = 0; k + 1 < n; k += 2) {
-      hipLaunchKernelGGL(pivot_kernel, dim3(1), dim3(256), 0, s, n, k, w.W, ipiv, w.piv, w.status);
-      SKF_CHECK_LAUNCH("c128 pivot");
       const unsigned gs = (unsigned)std::min<int64_t>((n - k + 255) / 256, 1024);
-      hipLaunchKernelGGL(swap_kernel, dim3(gs), dim3(256), 0, s, n, k, w.W, Tc, w.piv, w.status);
+      hipLaunchKernelGGL(swap_kernel, dim3(gs), dim3(256), 0, s, n, k, w.W, Tc, ipiv, w.part, w.status);
       SKF_CHECK_LAUNCH("c128 swap");
       const int64_t m = n - k - 2;
       if (m > 0) {
         hipLaunchKernelGGL(update_kernel, dim3((unsigned)((m + 63) / 64), (unsigned)((m + 15) / 16)), dim3(64, 4), 0,
-                           s, n, k, w.W, w.status);
+                           s, n, k, w.W, w.part, w.status);
         SKF_CHECK_LAUNCH("c128 update");
       }
     }
