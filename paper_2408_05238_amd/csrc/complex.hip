@@ -99,8 +99,9 @@ __global__ void __launch_bounds__(64) init_partials_kernel(int64_t n, const c128
   block_partial(n, 0, i, z, part, (int)blockIdx.x);
 }
 
-// Symmetric interchange of rows/columns k+1 and p over the active part (index
-// t >= k): thread t swaps (k+1, t) <-> (p, t) and (t, k+1) <-> (t, p), four
+// Step k's pivot p from the partials of column k (every workgroup reduces them
+// the same way; ipiv[k+1] = p), then the symmetric interchange of rows/columns
+// k+1 and p over the active part (index t >= k): thread t swaps (k+1, t) <-> (p, t) and (t, k+1) <-> (t, p), four
 // entries no other thread touches when t is neither k+1 nor p; the 2 x 2 block
 // of those two indices is permuted by one thread.  The pivot T[k] = W[k+1, k]
 // after the interchange is recorded by the thread of t = k.
