@@ -49,14 +49,22 @@ __global__ void compose_sigma_kernel(int64_t n, int npanels, const int32_t* __re
   }
 }
 
-// A[i, c] = W[sigma_P(i), c] for i > c, P = panel of column c.
+// A[i, c] = W[sigma_P(i), c] for i > c, P = panel of column c.  The reads of a
+// column are scattered by the permutation, so all kFinalSubs workgroups of one
+// column run on one XCD (workgroups are dealt to the eight XCDs round-robin by
+// linear index): index g 8 kFinalSubs + s 8 + cc -> column 8 g + cc, part s; the
+// column's cache lines are then fetched into one L2 only.
+constexpr int kFinalSubs = 32;
 __global__ void final_L_kernel(int64_t n, int nb, const double* __restrict__ W, int64_t ldw,
                                const int32_t* __restrict__ sigma, double* __restrict__ A, int64_t lda) {
-  const int64_t c = blockIdx.y;
+  const int64_t id = blockIdx.x;
+  const int64_t g = id / (8 * kFinalSubs), rem = id % (8 * kFinalSubs);
+  const int sub = (int)(rem / 8);
+  const int64_t c = 8 * g + rem % 8;
+  if (c >= n - 1) return;
   const int64_t P = c / nb;
   const int32_t* sg = sigma + P * n;
-  for (int64_t i = c + 1 + blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
-       i += (int64_t)gridDim.x * blockDim.x)
+  for (int64_t i = c + 1 + (int64_t)sub * blockDim.x + threadIdx.x; i < n; i += (int64_t)kFinalSubs * blockDim.x)
     A[i + c * lda] = W[(int64_t)sg[i] + c * ldw];
 }
 
@@ -187,8 +195,9 @@ int launch_final_L(int64_t n, int nb, int npanels, const double* W, int64_t ldw,
                    double* A, int64_t lda, hipStream_t s) {
   (void)npanels;
   if (n < 2) return 0;
-  dim3 grid(grid_for((size_t)n, 256) > 32 ? 32 : grid_for((size_t)n, 256), (unsigned)(n - 1));
-  hipLaunchKernelGGL(final_L_kernel, grid, dim3(256), 0, s, n, nb, W, ldw, sigma, A, lda);
+  const int64_t groups = (n - 1 + 7) / 8;
+  hipLaunchKernelGGL(final_L_kernel, dim3((unsigned)(groups * 8 * kFinalSubs)), dim3(256), 0, s, n, nb, W, ldw,
+                     sigma, A, lda);
   SKF_CHECK_LAUNCH("final_L");
   return 0;
 }
