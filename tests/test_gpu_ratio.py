@@ -147,3 +147,35 @@ def test_ratio_undefined_for_singular_a(skf, gen):
     fac = _factors(skf, Z)
     la, sg, info = _ratio(skf, fac, np.ones((64, 1)), np.arange(64.0).reshape(64, 1))
     assert info == fac[3] > 0 and sg == 0 and math.isnan(la)
+
+
+def test_ratio_n16384_property(skf):
+    """At n = 16384 (beyond the oracle's reach) the ratio through the resident
+    factors equals the quotient of two Pfaffian-only reductions on the GPU, the
+    updated matrix formed explicitly: both sides are parity-tested paths, and
+    the log difference of two Pfaffians near e^35000 carries their rounding,
+    64 u (|log|Pf(A)|| + |log|Pf(B)||) at most."""
+    import torch
+    from paper_2408_05238_amd import inputs
+    n = 16384
+    A = inputs.skew_gaussian(n, 2, inputs.STREAM_A)
+    d0 = skf.to_device_colmajor(A)
+    del A
+    LT = d0.clone()
+    ipiv, T, info = skf.ltlt(LT)
+    assert info == 0
+    g = torch.Generator(device="cuda")
+    g.manual_seed(11)
+    U = torch.randn(1, n, device="cuda", dtype=torch.float64, generator=g).t()
+    V = torch.randn(1, n, device="cuda", dtype=torch.float64, generator=g).t()
+    la_r, sg_r, info_r = skf.pf_ratio(LT, ipiv, T, U, V)
+    del LT
+    Bm = d0.clone()
+    Bm.add_(U @ V.t() - V @ U.t())
+    la_b, sg_b, _ = skf.logpf(Bm)
+    del Bm
+    la_a, sg_a, _ = skf.logpf(d0)
+    la_r, la_b, la_a = float(la_r.item()), float(la_b.item()), float(la_a.item())
+    print(f"log|ratio| {la_r!r} vs {la_b - la_a!r}")
+    assert info_r == 0 and int(sg_r.item()) == int(sg_b.item()) * int(sg_a.item())
+    assert abs(la_r - (la_b - la_a)) <= 64 * U_RND * (abs(la_a) + abs(la_b))
