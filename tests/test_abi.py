@@ -64,3 +64,32 @@ def test_workspace_queries(lib):
     assert lib.skf_ltlt_workspace(-1, 0) == 0
     assert lib.skf_solve_workspace(100, 16) > 0
     assert lib.skf_refine_workspace(100, 16) > lib.skf_solve_workspace(100, 16)
+
+
+def test_argument_errors_of_the_pfaffian_paths(lib):
+    vp = ctypes.c_void_p
+    # skf_pfonly: same checks as skf_ltlt
+    assert lib.skf_pfonly(-1, vp(0), 1, vp(0), vp(0), 0, vp(0), 0, vp(0), vp(0)) == -1
+    assert lib.skf_pfonly(10, vp(8), 9, vp(8), vp(8), 0, vp(256), 1 << 30, vp(0), vp(0)) == -3
+    assert lib.skf_pfonly(10, vp(8), 10, vp(8), vp(8), 0, vp(256), 16, vp(0), vp(0)) == -104
+    # skf_pf_ratio: rank beyond the maximum, missing outputs, misaligned workspace
+    args = [vp(8), 100, vp(8), vp(8), vp(8), 100, vp(8), 100]
+    assert lib.skf_pf_ratio(100, 33, *args, vp(8), vp(8), vp(256), 1 << 30, vp(0), vp(0)) == -2
+    assert lib.skf_pf_ratio(100, 2, *args, vp(0), vp(8), vp(256), 1 << 30, vp(0), vp(0)) == -11
+    assert lib.skf_pf_ratio(100, 2, *args, vp(8), vp(8), vp(260), 1 << 30, vp(0), vp(0)) == -13
+    assert lib.skf_pf_ratio_workspace(100, 33) == 0
+    assert lib.skf_pf_ratio_workspace(100, 32) > 0
+    # complex: short lda, null T, small workspace
+    assert lib.skf_pfonly_c128(10, vp(8), 9, vp(8), vp(8), vp(256), 1 << 30, vp(0), vp(0)) == -3
+    assert lib.skf_pfonly_c128(10, vp(8), 10, vp(8), vp(0), vp(256), 1 << 30, vp(0), vp(0)) == -5
+    assert lib.skf_pfonly_c128(10, vp(8), 10, vp(8), vp(8), vp(256), 16, vp(0), vp(0)) == -104
+    assert lib.skf_pfonly_c128_workspace(1000) >= 1000 * 1000 * 16
+    assert lib.skf_logpf_c128_from_factors(4, vp(8), vp(8), vp(0), vp(8), vp(0)) == -4
+
+
+def test_bench_refuses_more_than_one_gpu():
+    import subprocess
+    import sys
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"], capture_output=True,
+                       text=True, timeout=120)
+    assert r.returncode == 2 and "one GPU" in r.stderr
