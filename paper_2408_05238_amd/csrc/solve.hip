@@ -52,7 +52,7 @@ __device__ inline double Lij(const double* __restrict__ LT, int64_t lda, int64_t
 __global__ void __launch_bounds__(256) perm_kernel(int64_t n, const int32_t* __restrict__ ipiv,
                                                    int32_t* __restrict__ perm) {
   constexpr int CH = 4096;
-  __shared__ int32_t sp[CH];
+  __shared__ __align__(16) int32_t sp[CH];
   const int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   const int64_t jmax = min(n - 1, (int64_t)(blockIdx.x + 1) * blockDim.x - 1);
   int64_t pos = (j < n) ? ipiv[j] : 0;
@@ -71,12 +71,23 @@ __global__ void __launch_bounds__(256) perm_kernel(int64_t n, const int32_t* __r
       }
     }
     __syncthreads();
-    // the scan order matters (the last match wins), the LDS reads do not: unrolled
-    // so that they issue in batches ahead of the compare chain
+    // the scan order matters (the last match wins), the LDS reads do not: four
+    // interchanges per 16-byte read once the index is aligned, unrolled so that
+    // the reads issue in batches ahead of the compare chain
     const int64_t top = min(hi, j);  // only interchanges before j count
-#pragma unroll 16
-    for (int64_t s = top - 1; s >= lo; --s)
-      if (sp[s - lo] == pos) pos = s;
+    int idx = (int)(top - lo) - 1;   // s = lo + idx
+    for (; idx >= 0 && (idx & 3) != 3; --idx)
+      if (sp[idx] == pos) pos = lo + idx;
+#pragma unroll 4
+    for (; idx >= 3; idx -= 4) {
+      const int4 q = *reinterpret_cast<const int4*>(&sp[idx - 3]);
+      if (q.w == pos) pos = lo + idx;
+      if (q.z == pos) pos = lo + idx - 1;
+      if (q.y == pos) pos = lo + idx - 2;
+      if (q.x == pos) pos = lo + idx - 3;
+    }
+    for (; idx >= 0; --idx)
+      if (sp[idx] == pos) pos = lo + idx;
   }
   if (j < n) perm[j] = (int32_t)pos;
 }
