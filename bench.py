@@ -47,6 +47,8 @@ def parse():
                          "2000-request Poisson trace; complex: complex128 Pfaffian-only reduction (n=4096)")
     ap.add_argument("--sizes", default="16384,32768", help="orders for --workload mixed")
     ap.add_argument("--count", type=int, default=0, help="matrices (batched) or requests (serve); 0 = default")
+    ap.add_argument("--no-side", action="store_true",
+                    help="ltlt workload: skip the Pfaffian-only and low-rank ratio measurements after the timed steps")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="after the timed steps, run three plain device copies of 1 GiB (reference for HBM counters)")
     return ap.parse_args()
@@ -435,7 +437,7 @@ def main():
     # the Pfaffian-only reduction of the same matrix (outside the timed region):
     # one warm-up, then the median of three event-timed runs
     pf_only = None
-    if prec == skf.PREC_F64:
+    if prec == skf.PREC_F64 and not args.no_side:
         ipiv2 = torch.empty_like(ipiv)
         T2 = torch.empty_like(T)
         dinfo2 = torch.zeros(1, dtype=torch.int32, device=dev)
