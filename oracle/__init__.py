@@ -73,8 +73,12 @@ def _load():
             lib.oracle_ltlt.argtypes = [i64, dp, i64, ip, dp, dp, i64, ctypes.c_int]
             lib.oracle_logpf.restype = None
             lib.oracle_logpf.argtypes = [i64, ip, dp, dp, ctypes.POINTER(ctypes.c_int)]
+            lib.oracle_ltlt_mag.restype = ctypes.c_int
+            lib.oracle_ltlt_mag.argtypes = [i64, dp, i64, ip, dp, dp, dp, i64, i64, ctypes.c_int]
             lib.oracle_pfonly.restype = ctypes.c_int
             lib.oracle_pfonly.argtypes = [i64, dp, i64, ip, dp, ctypes.c_int]
+            lib.oracle_pfonly_mag.restype = ctypes.c_int
+            lib.oracle_pfonly_mag.argtypes = [i64, dp, i64, ip, dp, dp, i64, ctypes.c_int]
             lib.oracle_solve.restype = ctypes.c_int
             lib.oracle_solve.argtypes = [i64, i64, dp, i64, ip, dp, dp, i64]
             _lib = lib
@@ -90,15 +94,25 @@ def _ip(a):
 
 
 class Factors:
-    """Result of ``ltlt``: factored array (L below the subdiagonal), ipiv, T, info, gaps."""
+    """Result of ``ltlt``: factored array (L below the subdiagonal), ipiv, T, info,
+    gaps and (optionally) the per-entry magnitude sums ``M``."""
 
-    def __init__(self, LT, ipiv, T, info, gap):
-        self.LT, self.ipiv, self.T, self.info, self.gap = LT, ipiv, T, info, gap
+    def __init__(self, LT, ipiv, T, info, gap, M=None):
+        self.LT, self.ipiv, self.T, self.info, self.gap, self.M = LT, ipiv, T, info, gap, M
+
+    def T_mag(self) -> np.ndarray:
+        """Magnitude sum of each T[k]: M[k+1, k]."""
+        n = self.LT.shape[0]
+        return np.array([self.M[k + 1, k] for k in range(n - 1)]) if n > 1 else np.zeros(0)
 
 
 def ltlt(A: np.ndarray, nthreads: int = 1, nsteps: int = -1, want_gap: bool = True,
-         inplace: bool = False) -> Factors:
-    """Unblocked partially pivoted LTL^T of the strict lower triangle of A (FP64)."""
+         inplace: bool = False, want_mag: bool = False) -> Factors:
+    """Unblocked partially pivoted LTL^T of the strict lower triangle of A (FP64).
+
+    want_mag: also return ``M`` (n x n), where M[i,j] (i > j) is the sum of the
+    magnitudes of the terms entry (i,j) accumulated (the input plus |l_i v_j| +
+    |v_i l_j| per update, moved with the entry by the interchanges)."""
     n = A.shape[0]
     assert A.shape == (n, n)
     LT = A if (inplace and A.flags.f_contiguous and A.dtype == np.float64) else np.array(A, dtype=np.float64, order="F")
@@ -106,9 +120,49 @@ def ltlt(A: np.ndarray, nthreads: int = 1, nsteps: int = -1, want_gap: bool = Tr
     T = np.zeros(max(n - 1, 1), dtype=np.float64)
     gap = np.ones(max(n, 1), dtype=np.float64) if want_gap else None
     lda = max(LT.strides[1] // 8, 1) if n > 0 else 1
-    info = _load().oracle_ltlt(n, _dp(LT), lda, _ip(ipiv), _dp(T),
-                               _dp(gap) if gap is not None else None, nsteps, nthreads)
-    return Factors(LT, ipiv[:n], T[:max(n - 1, 0)], int(info), gap[:max(n - 2, 0)] if gap is not None else None)
+    M = np.zeros((n, n), dtype=np.float64, order="F") if (want_mag and n > 0) else None
+    info = _load().oracle_ltlt_mag(n, _dp(LT), lda, _ip(ipiv), _dp(T),
+                                   _dp(gap) if gap is not None else None,
+                                   _dp(M) if M is not None else None, max(n, 1), nsteps, nthreads)
+    return Factors(LT, ipiv[:n], T[:max(n - 1, 0)], int(info),
+                   gap[:max(n - 2, 0)] if gap is not None else None, M)
+
+
+U_F64 = 2.0 ** -53
+
+
+def gamma(m, u: float = U_F64):
+    """gamma_m = m u / (1 - m u): a recursive sum of m rounded products (or m
+    fused multiply-adds) differs from the exact sum by at most gamma_m times the
+    sum of the magnitudes of its terms (Higham, Accuracy and Stability of
+    Numerical Algorithms, section 3.1)."""
+    m = np.asarray(m, dtype=np.float64)
+    return m * u / (1.0 - m * u)
+
+
+def t_tolerance(T_mag: np.ndarray, full: bool = True) -> np.ndarray:
+    """Per-entry bound for |T_a[k] - T_b[k]| between two evaluations of the
+    factorization along the same pivot sequence.  T[k] is the input entry plus
+    the terms of every earlier update that reached it: at most 2k + 1 terms in
+    the full factorization (2 products per step), k + 1 in the Pfaffian-only
+    reduction (2 products per even step).  Each evaluation is within
+    gamma_(terms + 1) * T_mag[k] of the exact sum of its terms, so the two
+    differ by at most twice that."""
+    k = np.arange(T_mag.size, dtype=np.float64)
+    m = (2.0 * k + 2.0) if full else (k + 2.0)
+    return 2.0 * gamma(m) * T_mag
+
+
+def l_tolerance(L: np.ndarray, num_mag: np.ndarray, alpha: np.ndarray, alpha_mag: np.ndarray,
+                col: np.ndarray) -> np.ndarray:
+    """Per-entry bound for |L_a[i,j] - L_b[i,j]|: L[i,j] = c_i / alpha with the
+    numerator c_i and the pivot alpha of step j-1 each within the bound of
+    ``t_tolerance`` (2 gamma_(2j) times their magnitude sums), plus the rounding
+    of the two divisions."""
+    m = 2.0 * np.asarray(col, dtype=np.float64)
+    g = 2.0 * gamma(m)
+    a = np.abs(alpha)
+    return (g * num_mag + np.abs(L) * g * alpha_mag) / a + 2.0 * U_F64 * np.abs(L)
 
 
 def logpf_from_factors(n: int, ipiv: np.ndarray, T: np.ndarray):
@@ -133,8 +187,10 @@ def logpf(A: np.ndarray, nthreads: int = 1):
     return la, s, f.info
 
 
-def pfonly(A: np.ndarray, nthreads: int = 1):
-    """Pfaffian-only reduction (even elimination steps only): (ipiv, T, info).
+def pfonly(A: np.ndarray, nthreads: int = 1, want_mag: bool = False):
+    """Pfaffian-only reduction (even elimination steps only): (ipiv, T, info),
+    and with want_mag a fourth item, the magnitude sum of each T[k] (as in
+    ``ltlt``; zero at the odd entries).
 
     ipiv[k+1] (k even) is the interchange of step k, every other ipiv[j] = j;
     T[k] (k even) are the pivots.  log|Pf| and sign follow from them exactly as
@@ -144,8 +200,13 @@ def pfonly(A: np.ndarray, nthreads: int = 1):
     W = np.array(A, dtype=np.float64, order="F")
     ipiv = np.zeros(max(n, 1), dtype=np.int32)
     T = np.zeros(max(n - 1, 1), dtype=np.float64)
-    info = _load().oracle_pfonly(n, _dp(W), max(n, 1), _ip(ipiv), _dp(T), nthreads)
-    return ipiv[:n], T[:max(n - 1, 0)], int(info)
+    if not want_mag:
+        info = _load().oracle_pfonly(n, _dp(W), max(n, 1), _ip(ipiv), _dp(T), nthreads)
+        return ipiv[:n], T[:max(n - 1, 0)], int(info)
+    M = np.zeros((max(n, 1), max(n, 1)), dtype=np.float64, order="F")
+    info = _load().oracle_pfonly_mag(n, _dp(W), max(n, 1), _ip(ipiv), _dp(T), _dp(M), max(n, 1), nthreads)
+    Tm = np.array([M[k + 1, k] if k % 2 == 0 else 0.0 for k in range(n - 1)]) if n > 1 else np.zeros(0)
+    return ipiv[:n], T[:max(n - 1, 0)], int(info), Tm
 
 
 def logpf_pfonly(A: np.ndarray, nthreads: int = 1):
@@ -157,39 +218,67 @@ def logpf_pfonly(A: np.ndarray, nthreads: int = 1):
     return la, s, info
 
 
-def pfonly_c128(A: np.ndarray):
+def pfonly_c128(A: np.ndarray, want_mag: bool = False):
     """Pfaffian-only reduction of the complex skew matrix whose strict lower
     triangle A holds: (ipiv, T, info) with ipiv[k+1] (k even) the interchange of
     step k, the other ipiv[j] = j, T[k] (k even) the pivots and the odd entries
     0; info = n for odd n, ENONFINITE for a non-finite pivot column, else
-    1 + the first even k with T[k] = 0, or 0.  Pf(A) = (-1)^{s + n/2} prod T[k]."""
+    1 + the first even k with T[k] = 0, or 0.  Pf(A) = (-1)^{s + n/2} prod T[k].
+
+    want_mag: a fourth item, the magnitude sum of each T[k] (|input| plus
+    |l_i v_j| + |v_i l_j| per update that reached it, moved with the entry by
+    the interchanges; 0 at the odd entries), as ``ltlt`` gives for real input."""
     n = A.shape[0]
     Lw = np.tril(np.asarray(A, dtype=np.complex128), -1)
     W = Lw - Lw.T
+    M = np.abs(W) if want_mag else None
     ipiv = np.arange(n, dtype=np.int32)
     T = np.zeros(max(n - 1, 0), dtype=np.complex128)
+    Tm = np.zeros(max(n - 1, 0))
+
+    def out(info):
+        return (ipiv, T, info, Tm) if want_mag else (ipiv, T, info)
+
     if n % 2 == 1:
-        return ipiv, T, n
+        return out(n)
     for k in range(0, n - 1, 2):
         col = W[k + 1:, k]
         if not np.all(np.isfinite(col)):
-            return ipiv, T, ENONFINITE
+            return out(ENONFINITE)
         key = col.real * col.real + col.imag * col.imag
         p = k + 1 + int(np.argmax(key))
         ipiv[k + 1] = p
         if p != k + 1:
             W[[k + 1, p], :] = W[[p, k + 1], :]
             W[:, [k + 1, p]] = W[:, [p, k + 1]]
+            if want_mag:
+                M[[k + 1, p], :] = M[[p, k + 1], :]
+                M[:, [k + 1, p]] = M[:, [p, k + 1]]
         alpha = W[k + 1, k]
         T[k] = alpha
+        if want_mag:
+            Tm[k] = M[k + 1, k]
         if k + 2 < n and alpha != 0:
             l = W[k + 2:, k] / alpha
             v = W[k + 2:, k + 1].copy()
             W[k + 2:, k + 2:] += np.outer(l, v) - np.outer(v, l)
+            if want_mag:
+                al, av = np.abs(l), np.abs(v)
+                M[k + 2:, k + 2:] += np.outer(al, av) + np.outer(av, al)
     for k in range(0, n - 1, 2):
         if T[k] == 0:
-            return ipiv, T, k + 1
-    return ipiv, T, 0
+            return out(k + 1)
+    return out(0)
+
+
+def t_tolerance_c128(T_mag: np.ndarray) -> np.ndarray:
+    """Per-entry bound for |T_a[k] - T_b[k]| between two complex Pfaffian-only
+    reductions along the same interchanges: a sum of m complex products formed
+    with real arithmetic is within sqrt(2) gamma_(m+2) of its magnitude sum
+    (Higham, section 3.6); T[k] (k even) collects at most k + 1 terms; twice
+    that for the two evaluations."""
+    k = np.arange(T_mag.size, dtype=np.float64)
+    return 2.0 * np.sqrt(2.0) * gamma(k + 3.0) * T_mag
 
 
 def logpf_c128_from_factors(n: int, ipiv: np.ndarray, T: np.ndarray):

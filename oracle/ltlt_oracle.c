@@ -43,6 +43,8 @@ typedef struct {
   int32_t* ipiv;
   double* T;
   double* gap;
+  double* M;      /* optional: running sums of |terms| per entry (same layout, ldm) */
+  int64_t ldm;
   int status;
   pthread_barrier_t bar;
   int64_t k;      /* current step, published by thread 0 */
@@ -54,6 +56,30 @@ typedef struct {
   orc_ctx* c;
   int tid;
 } orc_arg;
+
+#define MT(i, j) M[(i) + (int64_t)(j) * ldm]
+
+/* The symmetric interchange of rows/columns r < p applied to the magnitude
+ * sums: the same moves as the entries, without the sign changes. */
+static void orc_swap_mag(orc_ctx* c, int64_t r, int64_t p) {
+  double* M = c->M;
+  int64_t ldm = c->ldm, n = c->n;
+  for (int64_t j = 0; j < r; ++j) {
+    double t = MT(r, j);
+    MT(r, j) = MT(p, j);
+    MT(p, j) = t;
+  }
+  for (int64_t j = r + 1; j < p; ++j) {
+    double t = MT(j, r);
+    MT(j, r) = MT(p, j);
+    MT(p, j) = t;
+  }
+  for (int64_t j = p + 1; j < n; ++j) {
+    double t = MT(j, r);
+    MT(j, r) = MT(j, p);
+    MT(j, p) = t;
+  }
+}
 
 /* Steps 1-3 for column k; returns 0, or ORC_ENONFINITE. */
 static int orc_pivot_swap_scale(orc_ctx* c, int64_t k) {
@@ -75,6 +101,7 @@ static int orc_pivot_swap_scale(orc_ctx* c, int64_t k) {
   }
   if (c->gap) c->gap[k] = (best > 0.0 && second >= 0.0) ? (best - second) / best : 1.0;
   int64_t r = k + 1;
+  if (p != r && c->M) orc_swap_mag(c, r, p);
   if (p != r) {
     for (int64_t j = 0; j < r; ++j) {          /* row segments left of r */
       double t = AT(r, j);
@@ -111,6 +138,25 @@ static void orc_update(orc_ctx* c, int64_t k, int tid) {
     double* col = &AT(0, j);
     for (int64_t i = j + 1; i < n; ++i) col[i] = (col[i] + l[i] * vj) - v[i] * lj;
   }
+  if (c->M) {
+    /* each entry's sum of the magnitudes of the terms it has accumulated */
+    double* M = c->M;
+    int64_t ldm = c->ldm;
+    for (int64_t j = k + 2 + tid; j < n; j += c->nthreads) {
+      double lj = fabs(l[j]), vj = fabs(v[j]);
+      double* mc = &MT(0, j);
+      for (int64_t i = j + 1; i < n; ++i) mc[i] = mc[i] + (fabs(l[i]) * vj + fabs(v[i]) * lj);
+    }
+  }
+}
+
+/* M[i,j] := |A[i,j]| on the strict lower triangle (the input's own term). */
+static void orc_init_mag(orc_ctx* c) {
+  double* A = c->A;
+  double* M = c->M;
+  int64_t lda = c->lda, ldm = c->ldm, n = c->n;
+  for (int64_t j = 0; j < n; ++j)
+    for (int64_t i = j + 1; i < n; ++i) MT(i, j) = fabs(AT(i, j));
 }
 
 static void* orc_worker(void* p) {
@@ -143,12 +189,19 @@ static void* orc_worker(void* p) {
  * whole factorization; otherwise only the first nsteps elimination steps are
  * done (a bounded sample for timing; T[nsteps..] and the tail are then not set).
  * gap (optional, length n) receives per step (|c|_(1) - |c|_(2)) / |c|_(1).
+ * M (optional, n x n, ldm): on exit M[i,j] (i > j) is the sum of the magnitudes
+ * of every term the entry A[i,j] accumulated before it was last used: |input|
+ * plus |l_i v_j| + |v_i l_j| per update, moved with the entry by the
+ * interchanges.  So M[k+1,k] belongs to T[k], and M[i,j-1] (i > j) to the
+ * numerator of L[i,j] (its pivot's sum is M[j,j-1]).  A recursive sum of m
+ * rounded products carries an error of at most gamma_m times this sum.
  * Returns 0, 1+k for the first even k with T[k] == 0 (exactly singular),
  * or ORC_ENONFINITE if a pivot column held a NaN or an infinity.
  */
-int oracle_ltlt(int64_t n, double* A, int64_t lda, int32_t* ipiv, double* T, double* gap,
-                int64_t nsteps, int nthreads) {
+int oracle_ltlt_mag(int64_t n, double* A, int64_t lda, int32_t* ipiv, double* T, double* gap,
+                    double* M, int64_t ldm, int64_t nsteps, int nthreads) {
   if (n < 0 || lda < (n > 1 ? n : 1) || (n > 0 && (!A || !ipiv)) || (n > 1 && !T)) return ORC_EARG;
+  if (M && ldm < (n > 1 ? n : 1)) return ORC_EARG;
   if (n == 0) return 0;
   if (nthreads < 1) nthreads = 1;
   if (nthreads > 64) nthreads = 64;
@@ -163,6 +216,9 @@ int oracle_ltlt(int64_t n, double* A, int64_t lda, int32_t* ipiv, double* T, dou
   c.ipiv = ipiv;
   c.T = T;
   c.gap = gap;
+  c.M = M;
+  c.ldm = ldm;
+  if (M) orc_init_mag(&c);
   ipiv[0] = 0;
   pthread_barrier_init(&c.bar, NULL, (unsigned)nthreads);
   pthread_t th[64];
@@ -187,6 +243,11 @@ int oracle_ltlt(int64_t n, double* A, int64_t lda, int32_t* ipiv, double* T, dou
   return 0;
 }
 
+int oracle_ltlt(int64_t n, double* A, int64_t lda, int32_t* ipiv, double* T, double* gap,
+                int64_t nsteps, int nthreads) {
+  return oracle_ltlt_mag(n, A, lda, ipiv, T, gap, NULL, 0, nsteps, nthreads);
+}
+
 /*
  * Pfaffian-only reduction: the same elimination step (pivot search, symmetric
  * interchange, multipliers, rank-2 congruence update) taken at the even steps
@@ -200,10 +261,13 @@ int oracle_ltlt(int64_t n, double* A, int64_t lda, int32_t* ipiv, double* T, dou
  * On exit ipiv[k+1] (k even) holds the interchange of step k and every other
  * ipiv[j] = j; T[k] (k even) holds the pivots and T[k] (k odd) = 0; A is left
  * as scratch (no L).  n odd: Pf = 0, returns n without touching A.
+ * M (optional) as for oracle_ltlt_mag: M[k+1,k] is the magnitude sum of T[k].
  * Returns as oracle_ltlt.
  */
-int oracle_pfonly(int64_t n, double* A, int64_t lda, int32_t* ipiv, double* T, int nthreads) {
+int oracle_pfonly_mag(int64_t n, double* A, int64_t lda, int32_t* ipiv, double* T, double* M,
+                      int64_t ldm, int nthreads) {
   if (n < 0 || lda < (n > 1 ? n : 1) || (n > 0 && (!A || !ipiv)) || (n > 1 && !T)) return ORC_EARG;
+  if (M && ldm < (n > 1 ? n : 1)) return ORC_EARG;
   if (n == 0) return 0;
   for (int64_t j = 0; j < n; ++j) ipiv[j] = (int32_t)j;
   for (int64_t k = 0; k + 1 < n; ++k) T[k] = 0.0;
@@ -221,6 +285,9 @@ int oracle_pfonly(int64_t n, double* A, int64_t lda, int32_t* ipiv, double* T, i
   c.ipiv = ipiv;
   c.T = T;
   c.gap = NULL;
+  c.M = M;
+  c.ldm = ldm;
+  if (M) orc_init_mag(&c);
   pthread_barrier_init(&c.bar, NULL, (unsigned)nthreads);
   pthread_t th[64];
   orc_arg args[64];
@@ -238,6 +305,10 @@ int oracle_pfonly(int64_t n, double* A, int64_t lda, int32_t* ipiv, double* T, i
   for (int64_t k = 0; k + 1 < n; k += 2)
     if (T[k] == 0.0) return (int)(k + 1);
   return 0;
+}
+
+int oracle_pfonly(int64_t n, double* A, int64_t lda, int32_t* ipiv, double* T, int nthreads) {
+  return oracle_pfonly_mag(n, A, lda, ipiv, T, NULL, 0, nthreads);
 }
 
 /*

@@ -98,3 +98,19 @@ def test_complex_odd_zero_and_nonfinite(oracle_mod):
     N = _skew_cint(10, rng).astype(np.complex128)
     N[6, 0] = complex(np.nan, 0.0)
     assert oracle_mod.pfonly_c128(N)[2] == oracle_mod.ENONFINITE
+
+
+@pytest.mark.parametrize("n", [8, 64, 200])
+def test_complex_magnitudes_match_real_and_rotation(oracle_mod, gen, n):
+    """The magnitude sums that set the complex tolerance: for a real matrix they
+    are those of the real Pfaffian-only reduction, and multiplying the matrix by
+    a unit complex number leaves every magnitude unchanged."""
+    R = gen.skew_gaussian(n, 400 + n)
+    _, _, _, tm_real = oracle_mod.pfonly(R, want_mag=True)
+    _, _, _, tm_c = oracle_mod.pfonly_c128(R.astype(np.complex128), want_mag=True)
+    np.testing.assert_allclose(tm_c, tm_real, rtol=1e-13, atol=0)
+    Z = R + 1j * gen.skew_gaussian(n, 500 + n)
+    _, T1, _, m1 = oracle_mod.pfonly_c128(Z, want_mag=True)
+    _, T2, _, m2 = oracle_mod.pfonly_c128(Z * 1j, want_mag=True)
+    np.testing.assert_allclose(m2, m1, rtol=1e-13, atol=0)
+    np.testing.assert_allclose(T2, 1j * T1, rtol=1e-12, atol=0)
