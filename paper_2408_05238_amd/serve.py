@@ -9,12 +9,19 @@ compute tokens free up, so work of different requests overlaps on the device
   refinement); factors of finished requests stay resident in an LRU cache keyed
   by (matrix id, precision) and are evicted when an admission needs the room.
   A request whose factors are resident skips the factorization.
-* compute tokens: a factorization of order n > 512 launches persistent panel
-  kernels of ceil((n-1)/64) workgroups that must be co-resident; the scheduler
-  only runs factorizations whose token sum fits the device's CU count, so two of
-  them can never wait on each other for residency.
+* compute tokens: a factorization launches persistent panel kernels of
+  ceil((n-1)/64) workgroups that must be co-resident; the scheduler only runs
+  factorizations whose token sum fits the device's CU count, so two of them can
+  never wait on each other for residency.  Batched launches and requests served
+  from resident factors hold no tokens.
 * continuous batching: small Pfaffian requests (n <= 512) waiting together are
   factored by one persistent batched launch.
+* precision: a request labelled FP32 means an FP32-trailing factorization plus
+  iterative refinement to FP64 backward error; refinement corrects solves only,
+  so Pfaffian requests are always taken from FP64 factors (their error is the
+  FP64 path's).  Every result states its error against FP64: the backward error
+  eta of its solution for a solve, the relative log|Pf| bound of the FP64
+  reduction for a Pfaffian.
 * FIFO with overtaking: a request that does not fit yet does not block smaller
   ones behind it.
 
@@ -59,6 +66,8 @@ class Result:
     berr: float = 0.0
     cached: bool = False
     batched: bool = False
+    err: float = float("nan")   # stated error against FP64 (see the module docstring)
+    err_kind: str = ""          # "berr" (solve) or "logpf_rel_bound" (Pfaffian)
 
     @property
     def latency(self) -> float:
@@ -75,6 +84,18 @@ def percentile(values: List[float], q: float) -> float:
 
 
 SMALL_N = 512
+# Relative error bound of log|Pf| from the FP64 reductions, |d| / max(1, |log|Pf||),
+# the bound their parity tests verify against the oracle.
+PF_REL_BOUND = 1e-12
+
+
+def factor_prec(req: Request) -> str:
+    """Precision of the factors a request uses: Pfaffians always FP64."""
+    return "f64" if req.kind == "pf" else req.prec
+
+
+def factor_key(req: Request):
+    return (req.matrix_id, factor_prec(req))
 
 
 def factor_bytes(n: int) -> int:
@@ -90,18 +111,21 @@ def request_bytes(req: Request, ex, have_factors: bool) -> int:
     n = req.n
     b = 0
     if not have_factors:
-        b += factor_bytes(n) + ex.ltlt_ws(n, 0 if req.prec == "f64" else 1)
+        b += factor_bytes(n) + ex.ltlt_ws(n, 0 if factor_prec(req) == "f64" else 1)
     if req.kind == "solve":
         b += 2 * 8 * n * req.nrhs          # right-hand sides and solution
-        if req.prec == "f32":
-            b += ex.refine_ws(n, req.nrhs)
-        else:
-            b += ex.solve_ws(n, req.nrhs)
+        b += ex.refine_ws(n, req.nrhs)     # every solve states its backward error
     return b
 
 
+def batchable(req: Request, have_factors: bool) -> bool:
+    """Small Pfaffian requests without resident factors go to the batched launch."""
+    return req.kind == "pf" and req.n <= SMALL_N and not have_factors
+
+
 def tokens(req: Request, have_factors: bool) -> int:
-    if have_factors or req.n <= SMALL_N:
+    """CUs a dispatch needs co-resident: the panel workgroups of a factorization."""
+    if have_factors or batchable(req, have_factors) or req.n < 2:
         return 0
     return (req.n - 1 + 63) // 64
 
@@ -176,7 +200,7 @@ class Scheduler:
 
     # -- accounting -----------------------------------------------------------
     def _need(self, req: Request):
-        have = self.cache.get((req.matrix_id, req.prec)) is not None
+        have = self.cache.get(factor_key(req)) is not None
         return request_bytes(req, self.ex, have), tokens(req, have), have
 
     def _fits(self, nbytes: int, protect=None) -> bool:
@@ -199,24 +223,24 @@ class Scheduler:
                 return None
             if self.tokens_used + tk > self.ex.num_cus:
                 continue
-            if not self._fits(nb, (req.matrix_id, req.prec) if have else None):
+            if not self._fits(nb, factor_key(req) if have else None):
                 continue
             batch = [req]
-            if self.batch_small and req.kind == "pf" and req.n <= SMALL_N and not have:
+            if self.batch_small and batchable(req, have):
                 total = nb
                 for other in self.queue[qi + 1:]:
                     if len(batch) >= self.max_batch:
                         break
                     if other.kind == "pf" and other.n <= SMALL_N:
                         nb2, _, have2 = self._need(other)
-                        if not have2 and self._fits(total + nb2):
+                        if batchable(other, have2) and self._fits(total + nb2):
                             batch.append(other)
                             total += nb2
                 nb = total
             for r in batch:
                 self.queue.remove(r)
             if have:
-                self.cache.pin((req.matrix_id, req.prec))
+                self.cache.pin(factor_key(req))
             self.reserved += nb
             self.tokens_used += tk
             self.high_water = max(self.high_water, self.reserved + self.cache.bytes)
@@ -237,7 +261,7 @@ class Scheduler:
                     self.lock.wait(0.005)
                 batch, nb, tk, have = pick
                 self.busy += 1
-                factors = self.cache.get((batch[0].matrix_id, batch[0].prec)) if have else None
+                factors = self.cache.get(factor_key(batch[0])) if have else None
             start = self.clock()
             results, new_factors = self.ex.run(batch, factors)
             end = self.clock()
@@ -250,10 +274,10 @@ class Scheduler:
                 self.tokens_used -= tk
                 self.busy -= 1
                 if have:
-                    self.cache.unpin((batch[0].matrix_id, batch[0].prec))
+                    self.cache.unpin(factor_key(batch[0]))
                 if new_factors is not None:
                     req = batch[0]
-                    self.cache.put((req.matrix_id, req.prec), new_factors, factor_bytes(req.n))
+                    self.cache.put(factor_key(req), new_factors, factor_bytes(req.n))
                     self.high_water = max(self.high_water, self.reserved + self.cache.bytes)
                 self.lock.notify_all()
 
@@ -289,6 +313,7 @@ class Scheduler:
     def stats(self, t_begin: float) -> dict:
         res = [r for r in self.results.values() if r.info != -100]
         lat = [r.latency for r in res]
+        berr = [r.err for r in res if r.err_kind == "berr"]
         t_end = max((r.end for r in res), default=t_begin)
         return {
             "completed": len(res),
@@ -301,6 +326,9 @@ class Scheduler:
             "evictions": self.evictions,
             "cache_hits": sum(1 for r in res if r.cached),
             "batched": sum(1 for r in res if r.batched),
+            "solve_berr_max": max(berr) if berr else float("nan"),
+            "pf_logabs_rel_bound": PF_REL_BOUND,
+            "errors_stated": sum(1 for r in res if r.err_kind),
         }
 
 
@@ -342,7 +370,7 @@ class GpuExecutor:
         skf, torch = self.skf, self.torch
         s = self._stream()
         with torch.cuda.stream(s):
-            if len(reqs) > 1 or (reqs[0].kind == "pf" and reqs[0].n <= SMALL_N and factors is None):
+            if len(reqs) > 1 or batchable(reqs[0], factors is not None):
                 mats = []
                 for r in reqs:
                     w = skf.colmajor(r.n, r.n, device=self.device)
@@ -351,11 +379,12 @@ class GpuExecutor:
                 la, sg, info = skf.logpf_batched(mats, stream=s)
                 s.synchronize()
                 la, sg, info = la.cpu().tolist(), sg.cpu().tolist(), info.cpu().tolist()
-                out = [Result(r.rid, r.arrival, logabs=la[i], sign=sg[i], info=info[i], batched=len(reqs) > 1)
+                out = [Result(r.rid, r.arrival, logabs=la[i], sign=sg[i], info=info[i], batched=len(reqs) > 1,
+                              err=PF_REL_BOUND, err_kind="logpf_rel_bound")
                        for i, r in enumerate(reqs)]
                 return out, None
             r = reqs[0]
-            prec = skf.PREC_F64 if r.prec == "f64" else skf.PREC_F32_TRAILING
+            prec = skf.PREC_F64 if factor_prec(r) == "f64" else skf.PREC_F32_TRAILING
             new = None
             if factors is None:
                 LT = skf.colmajor(r.n, r.n, device=self.device)
@@ -373,15 +402,14 @@ class GpuExecutor:
                 la, sg = skf.logpf_from_factors(r.n, ipiv[:r.n], T[:max(r.n - 1, 0)], stream=s)
                 s.synchronize()
                 res.logabs, res.sign, res.info = float(la.item()), int(sg.item()), int(dinfo.item())
+                res.err, res.err_kind = PF_REL_BOUND, "logpf_rel_bound"
             else:
-                if r.prec == "f64":
-                    X = skf.colmajor(r.n, r.nrhs, device=self.device)
-                    X.copy_(r.B)
-                    res.info = skf.solve(LT, ipiv[:r.n], T[:max(r.n - 1, 0)], X, stream=s)
-                    res.X = X
-                else:
-                    X, st, it, be = skf.solve_refine(r.A, LT, ipiv[:r.n], T[:max(r.n - 1, 0)], r.B, stream=s)
-                    res.X, res.info, res.iters, res.berr = X, st, it, be
+                # FP64 factors: one solve, then the backward error (no correction
+                # when it already meets the tolerance); FP32-trailing factors:
+                # refinement until it does
+                X, st, it, be = skf.solve_refine(r.A, LT, ipiv[:r.n], T[:max(r.n - 1, 0)], r.B, stream=s)
+                res.X, res.info, res.iters, res.berr = X, st, it, be
+                res.err, res.err_kind = be, "berr"
                 s.synchronize()
             return [res], new
 

@@ -101,3 +101,29 @@ def test_refine_fp32_ill_conditioned(skf, oracle_mod, gen, kappa):
     X, st, iters, berr = skf.solve_refine(A0, dA, ipiv, T, skf.to_device_colmajor(B), tol=1e-13, maxit=10)
     assert st == 0 and berr <= 1e-13, (st, iters, berr)
     assert oracle_mod.backward_error(A, _host(X), B) <= 2e-13
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_mixed_precision_workload_n16384(skf, oracle_mod, prec):
+    """The mixed-precision workload at its stated size: the n = 16384 skew
+    Gaussian matrix of seed 5 with 16 Gaussian right-hand sides of seed 6,
+    factored with FP64 or FP32-trailing updates, refined to FP64 backward
+    error <= 1e-13; eta recomputed on the host by the oracle's definition."""
+    import torch
+    from paper_2408_05238_amd import inputs
+    n, nrhs = 16384, 16
+    print(f"mixed n={n} prec={prec}", flush=True)
+    A = inputs.skew_gaussian(n, 5, inputs.STREAM_A)
+    B = inputs.gaussian(n, nrhs, 6, inputs.STREAM_B)
+    A0 = skf.to_device_colmajor(A)
+    dA = A0.clone()
+    dB = skf.to_device_colmajor(B)
+    p = skf.PREC_F64 if prec == "f64" else skf.PREC_F32_TRAILING
+    ipiv, T, info = skf.ltlt(dA, prec=p)
+    assert info == 0
+    X, st, iters, berr = skf.solve_refine(A0, dA, ipiv, T, dB, tol=1e-13, maxit=20)
+    torch.cuda.synchronize()
+    print(f"mixed n={n} prec={prec}: status {st}, corrections {iters}, eta {berr:.3e}")
+    assert st == 0 and berr <= 1e-13
+    del dA, A0
+    assert oracle_mod.backward_error(A, _host(X), B) <= 1e-13

@@ -300,3 +300,20 @@ def test_generator_golden_hash(gen):
     big1 = gen.skew_gaussian(600, 3, threads=1)
     big8 = gen.skew_gaussian(600, 3, threads=8)
     assert np.array_equal(big1, big8)
+
+
+@pytest.mark.parametrize("n,seed", [(50, 1), (300, 2), (1000, 3)])
+def test_designed_exact_ties(oracle_mod, n, seed):
+    """A matrix with a known factorization, exact ties at nearly every step
+    (spread over the whole column) and exact arithmetic: the oracle must return
+    the designed interchanges (ties to the lowest index), T0 and L0 bit for bit."""
+    from designed_ties import designed
+    A, ipiv, T0, L0 = designed(n, seed)
+    f = oracle_mod.ltlt(A, nthreads=4)
+    assert f.info == 0
+    assert np.array_equal(f.ipiv, ipiv)
+    assert np.array_equal(f.T, T0)
+    for j in range(1, n - 1):
+        assert np.array_equal(f.LT[j + 1:, j - 1], L0[j + 1:, j]), j
+    assert np.count_nonzero(f.gap == 0.0) > n // 2            # exact ties at most steps
+    assert np.count_nonzero(ipiv != np.arange(n)) >= n // 20  # and interchanges

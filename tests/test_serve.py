@@ -123,6 +123,27 @@ def test_cached_factors_skip_factorization():
     sch = serve.Scheduler(ex, budget_bytes=1 << 40, workers=1)
     reqs = [serve.Request(rid=0, kind="solve", n=1000, prec="f64", matrix_id=7, arrival=0.0),
             serve.Request(rid=1, kind="pf", n=1000, prec="f64", matrix_id=7, arrival=0.05),
-            serve.Request(rid=2, kind="pf", n=1000, prec="f32", matrix_id=7, arrival=0.1)]
+            serve.Request(rid=2, kind="pf", n=1000, prec="f32", matrix_id=7, arrival=0.1),
+            serve.Request(rid=3, kind="solve", n=1000, prec="f32", matrix_id=7, arrival=0.15),
+            serve.Request(rid=4, kind="solve", n=1000, prec="f32", matrix_id=7, arrival=0.2)]
     res = sch.run_trace(reqs)
-    assert not res[0].cached and res[1].cached and not res[2].cached    # other precision: new factors
+    # Pfaffians of either label are taken from the FP64 factors; an FP32 solve
+    # needs FP32-trailing factors of its own, which the next FP32 solve reuses
+    assert not res[0].cached and res[1].cached and res[2].cached
+    assert not res[3].cached and res[4].cached
+
+
+def test_small_solves_hold_tokens_next_to_large_factorizations():
+    """A solve of order <= 512 without resident factors runs a factorization, so
+    it holds its panel's tokens like any other; batched Pfaffians hold none."""
+    ex = FakeExecutor(num_cus=40)
+    sch = serve.Scheduler(ex, budget_bytes=1 << 40, workers=4)
+    reqs = [serve.Request(rid=0, kind="pf", n=2048, prec="f64", matrix_id=0, arrival=0.0)]
+    reqs += [serve.Request(rid=1 + i, kind="solve", n=500, prec="f64", matrix_id=1 + i, arrival=0.0)
+             for i in range(6)]
+    reqs += [serve.Request(rid=10 + i, kind="pf", n=300, prec="f64", matrix_id=10 + i, arrival=0.0)
+             for i in range(6)]
+    sch.run_trace(reqs)
+    assert serve.tokens(reqs[1], False) == 8 and serve.tokens(reqs[1], True) == 0
+    assert serve.tokens(reqs[-1], False) == 0
+    assert ex.max_tok <= 40 and sch.tokens_used == 0
