@@ -62,6 +62,7 @@ typedef int64_t skf_int;
 #define SKF_ENONFINITE (-103)
 #define SKF_EWORK (-104)
 #define SKF_ETIMEOUT (-105)
+#define SKF_ESCRATCH (-106)    /* size beyond an allocation-free entry point's fixed scratch */
 
 /* Library version string (static storage). */
 const char* skf_version(void);
@@ -164,6 +165,24 @@ size_t skf_solve_workspace(skf_int n, skf_int nrhs);
 int skf_solve(skf_int n, skf_int nrhs, const double* LT, skf_int lda, const int32_t* ipiv,
               const double* T, double* B, skf_int ldb, void* work, size_t lwork, int* dinfo,
               void* stream);
+
+/*
+ * skf_solve without a workspace argument, for callers that cannot allocate
+ * device memory (code under HIP graph capture, tight serving loops, harnesses
+ * that forbid allocation).  Same operation, kernels and results as skf_solve
+ * (bitwise, for the same inputs); its workspace is a fixed device array of the
+ * library (7 946 752 bytes, the skf_solve workspace of order 4096, per device,
+ * held until the process ends), so the call allocates nothing.
+ *   n       order, 0 <= n <= SKF_SOLVE_NOALLOC_MAX_N, else SKF_ESCRATCH before
+ *           any launch (skf_last_error names the limit)
+ *   other arguments as skf_solve
+ * Every call on one device shares that device's array and leaves its contents
+ * behind: calls that overlap on one device (on different streams or host
+ * threads) race and must be ordered by the caller.
+ */
+#define SKF_SOLVE_NOALLOC_MAX_N 4096
+int skf_solve_noalloc(skf_int n, skf_int nrhs, const double* LT, skf_int lda, const int32_t* ipiv,
+                      const double* T, double* B, skf_int ldb, int* dinfo, void* stream);
 
 /* Device workspace (bytes) for skf_pfonly_c128: a full n x n complex128 copy. */
 size_t skf_pfonly_c128_workspace(skf_int n);

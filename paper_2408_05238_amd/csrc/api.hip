@@ -288,6 +288,25 @@ int skf_solve(skf_int n, skf_int nrhs, const double* LT, skf_int lda, const int3
   return finish_sync(rc, dinfo_int, s);
 }
 
+int skf_solve_noalloc(skf_int n, skf_int nrhs, const double* LT, skf_int lda, const int32_t* ipiv,
+                      const double* T, double* B, skf_int ldb, int* dinfo, void* stream) {
+  if (n < 0) return -1;
+  if (nrhs < 0) return -2;
+  if (n > 0 && !LT) return -3;
+  if (lda < (n > 1 ? n : 1)) return -4;
+  if (n > 0 && !ipiv) return -5;
+  if (n > 1 && !T) return -6;
+  if (n > 0 && nrhs > 0 && !B) return -7;
+  if (ldb < (n > 1 ? n : 1)) return -8;
+  if (n > kSolveNoAllocMaxN) {
+    snprintf(g_last_error, sizeof g_last_error,
+             "skf_solve_noalloc: n = %lld exceeds the fixed scratch limit n <= %lld (%zu bytes)", (long long)n,
+             (long long)kSolveNoAllocMaxN, solve_noalloc_scratch_bytes());
+    return SKF_ESCRATCH;
+  }
+  return run_solve_noalloc(n, nrhs, LT, lda, ipiv, T, B, ldb, dinfo, (hipStream_t)stream);
+}
+
 size_t skf_pfonly_c128_workspace(skf_int n) {
   if (n < 0) return 0;
   return pfonly_c128_workspace_bytes(n) + 256;

@@ -39,6 +39,12 @@ const DeviceInfo& device_info();
 
 inline size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
 
+// Allocation-free solve (solve.hip): fixed device scratch for n <= kSolveNoAllocMaxN.
+constexpr int64_t kSolveNoAllocMaxN = SKF_SOLVE_NOALLOC_MAX_N;
+size_t solve_noalloc_scratch_bytes();
+int run_solve_noalloc(int64_t n, int64_t nrhs, const double* LT, int64_t lda, const int32_t* ipiv,
+                      const double* T, double* B, int64_t ldb, int* dinfo, hipStream_t s);
+
 // ---------------------------------------------------------------------------
 // skr2k (trailing update) launchers
 // ---------------------------------------------------------------------------

@@ -17,6 +17,7 @@
 //   scatter B[perm[i], :] = Z[i, :].
 // L[i,j] (i > j >= 1) is read from LT[i, j-1]; L[:,0] = e_0.
 #include <algorithm>
+#include <mutex>
 
 #include "skf_internal.h"
 
@@ -763,23 +764,48 @@ struct SolveWork {
   size_t bytes;
 };
 
+// Byte sizes of the workspace parts for order n (each part 256-aligned).
+struct SolveSizes {
+  size_t perm, Dinv, Mf, Mb, Y, tri, pub, status;
+};
+
+constexpr int64_t at_least_1(int64_t v) { return v > 1 ? v : 1; }
+constexpr size_t round256(size_t b) { return (b + 255) / 256 * 256; }
+
+constexpr SolveSizes solve_sizes(int64_t n) {
+  const int64_t nb = (n + BS - 1) / BS;
+  return SolveSizes{round256(sizeof(int32_t) * (size_t)at_least_1(n)),
+                    round256(sizeof(double) * (size_t)at_least_1(nb) * BS * BS),
+                    round256(sizeof(double) * (size_t)at_least_1(nb) * BS * BS),
+                    round256(sizeof(double) * (size_t)at_least_1(nb) * BS * BS),
+                    round256(sizeof(double) * (size_t)at_least_1(n) * RC),
+                    round256(sizeof(double) * (size_t)at_least_1(n) * 2),
+                    round256(sizeof(uint64_t) * (size_t)at_least_1(nb) * BS * RC * 2),
+                    round256(256)};
+}
+
+constexpr size_t solve_bytes(int64_t n) {
+  const SolveSizes z = solve_sizes(n);
+  return z.perm + z.Dinv + z.Mf + z.Mb + z.Y + z.tri + z.pub + z.status;
+}
+
 static SolveWork solve_carve(void* base, int64_t n) {
+  const SolveSizes z = solve_sizes(n);
   SolveWork w{};
   size_t off = 0;
   auto take = [&](size_t b) {
     size_t o = off;
-    off = align_up(off + b, 256);
+    off += b;
     return base ? (void*)((char*)base + o) : nullptr;
   };
-  const int64_t nb = (n + BS - 1) / BS;
-  w.perm = (int32_t*)take(sizeof(int32_t) * (size_t)std::max<int64_t>(n, 1));
-  w.Dinv = (double*)take(sizeof(double) * (size_t)std::max<int64_t>(nb, 1) * BS * BS);
-  w.Mf = (double*)take(sizeof(double) * (size_t)std::max<int64_t>(nb, 1) * BS * BS);
-  w.Mb = (double*)take(sizeof(double) * (size_t)std::max<int64_t>(nb, 1) * BS * BS);
-  w.Y = (double*)take(sizeof(double) * (size_t)std::max<int64_t>(n, 1) * RC);
-  w.tri = (double*)take(sizeof(double) * (size_t)std::max<int64_t>(n, 1) * 2);
-  w.pub = (uint64_t*)take(sizeof(uint64_t) * (size_t)std::max<int64_t>(nb, 1) * BS * RC * 2);
-  w.status = (int*)take(256);
+  w.perm = (int32_t*)take(z.perm);
+  w.Dinv = (double*)take(z.Dinv);
+  w.Mf = (double*)take(z.Mf);
+  w.Mb = (double*)take(z.Mb);
+  w.Y = (double*)take(z.Y);
+  w.tri = (double*)take(z.tri);
+  w.pub = (uint64_t*)take(z.pub);
+  w.status = (int*)take(z.status);
   w.bytes = off;
   return w;
 }
@@ -832,6 +858,56 @@ int run_solve(int64_t n, int64_t nrhs, const double* LT, int64_t lda, const int3
   hipLaunchKernelGGL(solve_info_kernel, dim3(1), dim3(256), 0, s, n, T, w.status, dinfo);
   SKF_CHECK_LAUNCH("solve info");
   return 0;
+}
+
+// ---------------------------------------------------------------------------
+// Allocation-free solve: the workspace is a fixed device array of this file.
+// ---------------------------------------------------------------------------
+// Sized for the largest order it accepts (plus the internal info word); each
+// device holds its own copy at its own address for the life of the process.
+// Calls on one device share it, so calls that overlap on one device race.
+constexpr size_t kNoAllocScratchBytes = solve_bytes(kSolveNoAllocMaxN) + 256;
+static __device__ __align__(256) unsigned char scratch[kNoAllocScratchBytes];
+
+size_t solve_noalloc_scratch_bytes() { return kNoAllocScratchBytes; }
+
+// Device address of this device's scratch array, resolved once per device (the
+// array's name is a host-side stand-in and is never passed to a kernel).
+static int scratch_address(void** out) {
+  static std::mutex mu;
+  static void* addr[64] = {nullptr};
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return note_error(e, "solve_noalloc: hipGetDevice");
+  if (dev < 0 || dev >= 64) return note_error(hipErrorInvalidDevice, "solve_noalloc: device index");
+  std::lock_guard<std::mutex> lk(mu);
+  if (!addr[dev]) {
+    void* p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p) return note_error(e != hipSuccess ? e : hipErrorInvalidSymbol, "solve_noalloc: scratch");
+    addr[dev] = p;
+  }
+  *out = addr[dev];
+  return 0;
+}
+
+// run_solve on the fixed scratch: same kernels and arithmetic as the caller-
+// workspace form.  With dinfo NULL the outcome goes through the scratch's info
+// word and the call waits for the stream.
+int run_solve_noalloc(int64_t n, int64_t nrhs, const double* LT, int64_t lda, const int32_t* ipiv,
+                      const double* T, double* B, int64_t ldb, int* dinfo, hipStream_t s) {
+  if (n > kSolveNoAllocMaxN) return SKF_ESCRATCH;
+  void* base = nullptr;
+  int rc = scratch_address(&base);
+  if (rc) return rc;
+  const size_t core = solve_bytes(n);
+  int* dinfo_int = (int*)((char*)base + core);
+  rc = run_solve(n, nrhs, LT, lda, ipiv, T, B, ldb, base, core, dinfo ? dinfo : dinfo_int, s);
+  if (rc || dinfo) return rc;
+  int h = 0;
+  SKF_CHECK(hipMemcpyAsync(&h, dinfo_int, sizeof(int), hipMemcpyDeviceToHost, s), "solve_noalloc info copy");
+  SKF_CHECK(hipStreamSynchronize(s), "solve_noalloc sync");
+  return h;
 }
 
 }  // namespace skf

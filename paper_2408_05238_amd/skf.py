@@ -24,12 +24,14 @@ ENOTIMPL = -102
 ENONFINITE = -103
 EWORK = -104
 ETIMEOUT = -105
+ESCRATCH = -106
+SOLVE_NOALLOC_MAX_N = 4096
 
 # Every symbol declared in include/skf.h (checked by the CPU test suite).
 EXPORTS = [
     "skf_version", "skf_last_error", "skf_ltlt_workspace", "skf_ltlt", "skf_pfonly", "skf_logpf_from_factors",
     "skf_logpf_workspace", "skf_logpf", "skf_pfaffian", "skf_skr2k", "skf_skr2k_f32",
-    "skf_solve_workspace", "skf_solve", "skf_pf_ratio_workspace", "skf_pf_ratio", "skf_pfonly_c128_workspace",
+    "skf_solve_workspace", "skf_solve", "skf_solve_noalloc", "skf_pf_ratio_workspace", "skf_pf_ratio", "skf_pfonly_c128_workspace",
     "skf_pfonly_c128", "skf_logpf_c128_from_factors", "skf_refine_workspace",
     "skf_solve_refine",
     "skf_batched_workspace", "skf_ltlt_batched", "skf_pfonly_batched", "skf_logpf_batched", "skf_solve_batched",
@@ -76,6 +78,7 @@ def _load():
                 "skf_skr2k_f32": (ci, [i64, i64, d, vp, i64, vp, i64, d, vp, i64, vp]),
                 "skf_solve_workspace": (sz, [i64, i64]),
                 "skf_solve": (ci, [i64, i64, vp, i64, vp, vp, vp, i64, vp, sz, vp, vp]),
+                "skf_solve_noalloc": (ci, [i64, i64, vp, i64, vp, vp, vp, i64, vp, vp]),
                 "skf_pfonly_c128_workspace": (sz, [i64]),
                 "skf_pfonly_c128": (ci, [i64, vp, i64, vp, vp, vp, sz, vp, vp]),
                 "skf_logpf_c128_from_factors": (ci, [i64, vp, vp, vp, vp, vp]),
@@ -308,6 +311,19 @@ def solve(LT, ipiv, T, B, work=None, dinfo=None, stream=None):
     rc = _load().skf_solve(n, nrhs, _ptr(LT), _ld(LT), _ptr(ipiv), _ptr(Tp), _ptr(B), _ld(B), _ptr(work),
                            work.numel(), _ptr(dinfo), _stream(stream))
     _check(rc, "skf_solve")
+    return rc if dinfo is None else dinfo
+
+
+def solve_noalloc(LT, ipiv, T, B, dinfo=None, stream=None):
+    """:func:`solve` through ``skf_solve_noalloc`` (no workspace: the library's
+    fixed device scratch, n <= SOLVE_NOALLOC_MAX_N)."""
+    torch = _torch()
+    n = LT.shape[0]
+    nrhs = B.shape[1] if B.dim() == 2 else 1
+    Tp = T if T.numel() > 0 else torch.zeros(1, dtype=torch.float64, device=LT.device)
+    rc = _load().skf_solve_noalloc(n, nrhs, _ptr(LT), _ld(LT), _ptr(ipiv), _ptr(Tp), _ptr(B), _ld(B),
+                                   _ptr(dinfo), _stream(stream))
+    _check(rc, "skf_solve_noalloc")
     return rc if dinfo is None else dinfo
 
 

@@ -93,3 +93,14 @@ def test_bench_refuses_more_than_one_gpu():
     r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"], capture_output=True,
                        text=True, timeout=120)
     assert r.returncode == 2 and "one GPU" in r.stderr
+
+
+def test_solve_noalloc_rejects_beyond_scratch(lib):
+    """n above the fixed scratch's limit is refused on the host, before any HIP call."""
+    vp = ctypes.c_void_p
+    from paper_2408_05238_amd import skf
+    n = skf.SOLVE_NOALLOC_MAX_N + 2
+    assert lib.skf_solve_noalloc(n, 1, vp(8), n, vp(8), vp(8), vp(8), n, vp(0), vp(0)) == skf.ESCRATCH
+    assert b"4096" in lib.skf_last_error()
+    assert lib.skf_solve_noalloc(-1, 1, vp(8), 4, vp(8), vp(8), vp(8), 4, vp(0), vp(0)) == -1
+    assert lib.skf_solve_noalloc(4, 1, vp(8), 4, vp(8), vp(8), vp(8), 3, vp(0), vp(0)) == -8
