@@ -76,11 +76,11 @@ def read_traffic(path: str):
         return None
 
 
-def cpu_baseline(A_host, n: int, target_s: float):
-    """Oracle on the first S elimination steps of the same matrix (bounded sample)."""
+def _oracle_sample(A_host, n: int, target_s: float, threads: int):
+    """Oracle on the first S elimination steps of the matrix, S grown until the
+    run takes about target_s: (S, seconds, nominal flops sum (n-k-1)^2)."""
     import numpy as np
     import oracle
-    threads = max(1, min(16, os.cpu_count() or 1))
     S = 4
     while True:
         Ac = np.array(A_host, order="F", copy=True)
@@ -91,10 +91,20 @@ def cpu_baseline(A_host, n: int, target_s: float):
         if dt >= 0.5 * target_s or S >= n - 2:
             break
         S = min(n - 2, max(S * 2, int(S * target_s / max(dt, 1e-3))))
-    flops = float(sum((n - k - 1) ** 2 for k in range(S)))
+    return S, dt, float(sum((n - k - 1) ** 2 for k in range(S)))
+
+
+def cpu_baseline(A_host, n: int, target_s: float):
+    """Oracle on a bounded sample of the same matrix (its first S elimination
+    steps), with the host's threads (at most 16) and with one thread."""
+    threads = max(1, min(16, os.cpu_count() or 1))
+    S, dt, flops = _oracle_sample(A_host, n, target_s, threads)
+    S1, dt1, flops1 = _oracle_sample(A_host, n, 0.5 * target_s, 1)
     return {"value": round(flops / dt / 1e9, 3), "unit": "GFLOP/s", "cores": threads, "kind": "oracle",
             "sample": f"first {S} elimination steps of the n={n} matrix (unblocked FP64 oracle), "
-                      f"nominal flops sum_k (n-k-1)^2 = {flops:.3e}, {dt:.2f} s"}
+                      f"nominal flops sum_k (n-k-1)^2 = {flops:.3e}, {dt:.2f} s",
+            "single_thread": {"value": round(flops1 / dt1 / 1e9, 3), "unit": "GFLOP/s", "cores": 1,
+                              "sample": f"first {S1} elimination steps, nominal flops {flops1:.3e}, {dt1:.2f} s"}}
 
 
 def _device():
@@ -539,6 +549,9 @@ def main():
         "config": {"workload": f"dense skew-symmetric Gaussian matrix n={n} (seed {args.seed}), blocked "
                                f"partially pivoted LTL^T, {'FP64' if prec == skf.PREC_F64 else 'FP32-trailing'}",
                    "n": n, "prec": args.prec},
+        "tuning": {"ltlt_nb": skf.tune_get("ltlt_nb", n), "pfonly_nb": skf.tune_get("pfonly_nb", n),
+                   "skr2k_band": skf.tune_get("skr2k_band", n),
+                   "table": os.path.relpath(skf.TUNING_PATH, ROOT) if os.path.exists(skf.TUNING_PATH) else None},
         "fraction_of_fp64_peak": round(gflops / 1e3 / FP64_MFMA_PEAK_TFLOPS, 4),
         "roofline": roofline,
         "panel": panel,

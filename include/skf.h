@@ -64,6 +64,30 @@ typedef int64_t skf_int;
 #define SKF_ETIMEOUT (-105)
 #define SKF_ESCRATCH (-106)    /* size beyond an allocation-free entry point's fixed scratch */
 
+/*
+ * Tuning table: parameters chosen by measurement on the device.  The package's
+ * tuner (paper_2408_05238_amd/tune.py) times the candidates, stores its choices
+ * as JSON and the Python binding loads them here when the library is first
+ * used.  Each entry covers the orders n_lo <= n <= n_hi; a later entry covering
+ * the same order wins over an earlier one.  Without an entry the built-in rule
+ * applies (panel width 128 when its workgroups fit on the device, else 64; band
+ * of 8 block rows).  The environment variable SKF_NB=64|128 overrides both
+ * panel widths.  A table value that is infeasible for a given n (too many panel
+ * workgroups to be resident) is ignored for that n.  Host-only; thread-safe;
+ * takes effect for calls made afterwards (workspace sizes cover every width).
+ */
+#define SKF_TUNE_LTLT_NB 0    /* panel width of skf_ltlt and skf_ltlt-based calls: 64 or 128 */
+#define SKF_TUNE_PFONLY_NB 1  /* panel width (twice the steps per panel) of skf_pfonly / skf_logpf: 64 or 128 */
+#define SKF_TUNE_SKR2K_BAND 2 /* block rows per band of the trailing update's tile walk, by trailing order: 1..64 */
+#define SKF_TUNE_NPARAMS 3
+/* Add an entry; returns 0, or -1 (param), -2 (n_lo < 0), -3 (n_hi < n_lo), -4 (value not allowed). */
+int skf_tune_set(int param, skf_int n_lo, skf_int n_hi, int value);
+/* The value in effect for order n (entry, environment override or built-in rule); -1 for a bad param,
+ * 0 when no panel width is feasible for n. */
+int skf_tune_get(int param, skf_int n);
+/* Remove every entry (the built-in rules apply again). */
+int skf_tune_clear(void);
+
 /* Library version string (static storage). */
 const char* skf_version(void);
 

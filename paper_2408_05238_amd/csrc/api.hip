@@ -517,4 +517,28 @@ int skf_profile_read(double* ms, double* flops, int64_t* launches, int reset) {
   return 0;
 }
 
+int skf_tune_set(int param, skf_int n_lo, skf_int n_hi, int value) { return tune_set(param, n_lo, n_hi, value); }
+
+int skf_tune_get(int param, skf_int n) {
+  switch (param) {
+    case SKF_TUNE_LTLT_NB: {
+      const int nb = ltlt_plan_nb(n);
+      return nb < 0 ? 0 : nb;
+    }
+    case SKF_TUNE_PFONLY_NB: {
+      const int nb = pfonly_plan_nb(n);
+      return nb < 0 ? 0 : nb;
+    }
+    case SKF_TUNE_SKR2K_BAND:
+      return skr2k_band(n);
+    default:
+      return -1;
+  }
+}
+
+int skf_tune_clear(void) {
+  tune_clear();
+  return 0;
+}
+
 }  // extern "C"

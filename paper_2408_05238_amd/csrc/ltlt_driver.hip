@@ -30,17 +30,24 @@ static int64_t max_panel_groups(int nb) {
   return std::min<int64_t>(kMaxPanelG, per_cu * device_info().num_cus);
 }
 
-int ltlt_plan_nb(int64_t n) {
+// Panel width for order n: SKF_NB override, else the tuning table's entry,
+// else 128 when its workgroups fit on the device, else 64; an infeasible choice
+// falls through to the next rule.  -1: no width fits.
+static int plan_nb(int64_t n, int param) {
   const int64_t g0 = std::max<int64_t>(1, (n - 1 + slots() - 1) / slots());
-  // override for tests and tuning: SKF_NB=64 or 128 (ignored when infeasible)
   if (const char* e = getenv("SKF_NB")) {
     const int want = atoi(e);
     if ((want == 64 || want == 128) && g0 <= max_panel_groups(want)) return want;
   }
+  const int t = tune_lookup(param, n);
+  if ((t == 64 || t == 128) && g0 <= max_panel_groups(t)) return t;
   if (g0 <= max_panel_groups(128)) return 128;
   if (g0 <= max_panel_groups(64)) return 64;
   return -1;
 }
+
+int ltlt_plan_nb(int64_t n) { return plan_nb(n, SKF_TUNE_LTLT_NB); }
+int pfonly_plan_nb(int64_t n) { return plan_nb(n, SKF_TUNE_PFONLY_NB); }
 
 int ltlt_panel_grid(int64_t m, int nb, int* G, int* S) {
   const int64_t g = std::max<int64_t>(1, (m + slots() - 1) / slots());
@@ -78,20 +85,31 @@ static size_t carve(LtltWork* w, char* base, int64_t n, int nb) {
   return off;
 }
 
+// Workspace for order n: the larger of the two panel widths' layouts (when
+// feasible), so a workspace sized once stays valid whichever width the tuning
+// table or the environment selects later.
 size_t ltlt_workspace_bytes(int64_t n, int prec) {
   (void)prec;
-  const int nb = ltlt_plan_nb(n);
-  if (nb < 0) return 0;
-  LtltWork w;
-  return carve(&w, nullptr, n, nb);
+  if (ltlt_plan_nb(n) < 0) return 0;
+  const int64_t g0 = std::max<int64_t>(1, (n - 1 + slots() - 1) / slots());
+  size_t b = 0;
+  for (int nb : {64, 128}) {
+    if (g0 > max_panel_groups(nb)) continue;
+    LtltWork w;
+    b = std::max(b, carve(&w, nullptr, n, nb));
+  }
+  return b;
+}
+
+static LtltWork carve_nb(void* work, int64_t n, int nb) {
+  LtltWork w{};
+  carve(&w, (char*)work, n, nb);
+  return w;
 }
 
 LtltWork ltlt_carve(void* work, int64_t n, int prec) {
   (void)prec;
-  LtltWork w{};
-  const int nb = ltlt_plan_nb(n);
-  carve(&w, (char*)work, n, nb);
-  return w;
+  return carve_nb(work, n, ltlt_plan_nb(n));
 }
 
 int run_ltlt(int64_t n, double* A, int64_t lda, int32_t* ipiv, double* T, int prec, void* work,
@@ -169,9 +187,9 @@ int run_ltlt(int64_t n, double* A, int64_t lda, int32_t* ipiv, double* T, int pr
 int run_pfonly(int64_t n, double* A, int64_t lda, int32_t* ipiv, double* T, int prec, void* work,
                size_t lwork, int* dinfo_dev, hipStream_t s) {
   if (n == 0) return dinfo_dev ? launch_fill_i32(dinfo_dev, 1, 0, s) : 0;
-  const int nb = ltlt_plan_nb(n);
+  const int nb = pfonly_plan_nb(n);
   if (nb < 0) return SKF_ENOTIMPL;
-  LtltWork w = ltlt_carve(work, n, prec);
+  LtltWork w = carve_nb(work, n, nb);
   if (lwork < w.bytes) return SKF_EWORK;
   int rc;
   if ((rc = launch_iota_i32(ipiv, (size_t)n, s))) return rc;

@@ -39,6 +39,13 @@ const DeviceInfo& device_info();
 
 inline size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
 
+// Tuning table (tune.hip)
+int tune_lookup(int param, int64_t n);
+int tune_set(int param, int64_t lo, int64_t hi, int value);
+void tune_clear();
+int pfonly_plan_nb(int64_t n);
+int skr2k_band(int64_t m);
+
 // Allocation-free solve (solve.hip): fixed device scratch for n <= kSolveNoAllocMaxN.
 constexpr int64_t kSolveNoAllocMaxN = SKF_SOLVE_NOALLOC_MAX_N;
 size_t solve_noalloc_scratch_bytes();

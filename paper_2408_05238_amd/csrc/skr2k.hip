@@ -72,9 +72,9 @@ __device__ inline void tri_tile(int64_t x, int64_t* bi, int64_t* bj) {
 // Tile of linear index x when the lower triangle of nt x nt tiles is walked in
 // bands of kBand block rows: inside a band, column block by column block, the
 // band's rows at or below the diagonal.  Tiles running together then share a
-// few row and column blocks of the operands, which stay in L2.
-constexpr int64_t kBand = 8;
-__device__ inline void band_tile(int64_t x, int64_t ntiles, int64_t* bi, int64_t* bj) {
+// few row and column blocks of the operands, which stay in L2.  The band height
+// comes from the tuning table (8 without an entry).
+__device__ inline void band_tile(int64_t x, int64_t ntiles, int64_t kBand, int64_t* bi, int64_t* bj) {
   int64_t nt, r, c0;
   tri_tile(ntiles - 1, &nt, &c0);
   ++nt;
@@ -259,11 +259,11 @@ __device__ inline void tile_mainloop(const Operands& o, int64_t rI, int64_t rJ, 
 // ---------------------------------------------------------------------------
 template <typename T, int VEC>
 __global__ void __launch_bounds__(NTHR, 2) skr2k_kernel(Operands o, double alpha, double beta, double* C,
-                                                        int64_t ldc, int64_t ntiles) {
+                                                        int64_t ldc, int64_t ntiles, int64_t band) {
   __shared__ Stage st[NSTG];
   const int64_t n = o.n;
   int64_t bi, bj;
-  band_tile(xcd_remap(blockIdx.x, ntiles), ntiles, &bi, &bj);
+  band_tile(xcd_remap(blockIdx.x, ntiles), ntiles, band, &bi, &bj);
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int wm = wave >> 1, wn = wave & 1;
   const int64_t rI = bi * TM, rJ = bj * TM;
@@ -317,11 +317,11 @@ __global__ void __launch_bounds__(NTHR, 2) skr2k_perm_kernel(Operands o, int64_t
                                                              double* __restrict__ dst, int64_t ldd,
                                                              const int32_t* __restrict__ pi,
                                                              const double* __restrict__ cnext,
-                                                             int64_t ntiles) {
+                                                             int64_t ntiles, int64_t band) {
   __shared__ Stage st[NSTG];
   const int64_t n = o.n;
   int64_t bi, bj;
-  band_tile(xcd_remap(blockIdx.x, ntiles), ntiles, &bi, &bj);
+  band_tile(xcd_remap(blockIdx.x, ntiles), ntiles, band, &bi, &bj);
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int wm = wave >> 1, wn = wave & 1;
   const int64_t rI = lo + bi * TM, rJ = lo + bj * TM;
@@ -441,6 +441,12 @@ __global__ void __launch_bounds__(NTHR, 2) skr2k_perm_kernel(Operands o, int64_t
 
 }  // namespace
 
+// Band height of the tile walk for a trailing order m.
+int skr2k_band(int64_t m) {
+  const int t = tune_lookup(SKF_TUNE_SKR2K_BAND, m);
+  return t > 0 ? t : 8;
+}
+
 // 16-byte copies need 16-byte aligned operand bases, even leading dimensions and
 // a readable padding row when n is odd (rows are copied in pairs).
 static bool vec16_ok(const double* p, int64_t ld, int64_t n) {
@@ -457,10 +463,10 @@ static int launch_plain(int64_t n, int64_t k, double alpha, const double* X, int
   Operands o{X, Y, nullptr, ldx, ldy, (alpha == 0.0) ? 0 : k, n};
   if (o.k > 0 && vec16_ok(X, ldx, n) && vec16_ok(Y, ldy, n))
     hipLaunchKernelGGL((skr2k_kernel<T, 16>), dim3((unsigned)ntiles), dim3(NTHR), 0, s, o, alpha, beta, C, ldc,
-                       ntiles);
+                       ntiles, (int64_t)skr2k_band(n));
   else
     hipLaunchKernelGGL((skr2k_kernel<T, 4>), dim3((unsigned)ntiles), dim3(NTHR), 0, s, o, alpha, beta, C, ldc,
-                       ntiles);
+                       ntiles, (int64_t)skr2k_band(n));
   SKF_CHECK_LAUNCH("skr2k");
   return 0;
 }
@@ -481,7 +487,7 @@ template <typename T, int VEC, bool kPlain>
 static void launch_perm_t(const Operands& o, int64_t lo, const double* src, int64_t ld_src, double* dst,
                           int64_t ld_dst, const int32_t* pi, const double* cnext, int64_t ntiles, hipStream_t s) {
   hipLaunchKernelGGL((skr2k_perm_kernel<T, VEC, kPlain>), dim3((unsigned)ntiles), dim3(NTHR), 0, s, o, lo, src,
-                     ld_src, dst, ld_dst, pi, cnext, ntiles);
+                     ld_src, dst, ld_dst, pi, cnext, ntiles, (int64_t)skr2k_band(o.n - lo));
 }
 
 template <typename T>

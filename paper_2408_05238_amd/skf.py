@@ -35,7 +35,7 @@ EXPORTS = [
     "skf_pfonly_c128", "skf_logpf_c128_from_factors", "skf_refine_workspace",
     "skf_solve_refine",
     "skf_batched_workspace", "skf_ltlt_batched", "skf_pfonly_batched", "skf_logpf_batched", "skf_solve_batched",
-    "skf_profile_enable", "skf_profile_read",
+    "skf_profile_enable", "skf_profile_read", "skf_tune_set", "skf_tune_get", "skf_tune_clear",
 ]
 
 _lib = None
@@ -92,6 +92,9 @@ def _load():
                 "skf_pfonly_batched": (ci, [i64, vp, vp, vp, vp, vp, vp, vp, vp, vp, sz, vp]),
                 "skf_logpf_batched": (ci, [i64, vp, vp, vp, vp, vp, vp, vp, sz, vp]),
                 "skf_solve_batched": (ci, [i64, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, sz, vp]),
+                "skf_tune_set": (ci, [ci, i64, i64, ci]),
+                "skf_tune_get": (ci, [ci, i64]),
+                "skf_tune_clear": (ci, []),
                 "skf_profile_enable": (ci, [ci]),
                 "skf_profile_read": (ci, [vp, vp, vp, ci]),
             }
@@ -100,8 +103,42 @@ def _load():
                     f = getattr(lib, name)
                     f.restype = res
                     f.argtypes = args
+            load_tuning(lib=lib)
             _lib = lib
     return _lib
+
+
+# Tuning table persisted by tune.py; SKF_TUNING=<path> selects another file,
+# SKF_TUNING=off keeps the built-in rules.
+TUNE_PARAMS = {"ltlt_nb": 0, "pfonly_nb": 1, "skr2k_band": 2}
+TUNING_PATH = os.path.join(HERE, "tuning", "mi355x.json")
+
+
+def load_tuning(path: str | None = None, lib=None) -> int:
+    """Load a tuning table (JSON, ``{"entries": [{"param", "n_lo", "n_hi", "value"}, ...]}``)
+    into the library, replacing what it held; returns the number of entries.
+    A missing default file leaves the built-in rules; a malformed one raises."""
+    import json
+    lib = lib or _load()
+    if path is None:
+        path = os.environ.get("SKF_TUNING", TUNING_PATH)
+    lib.skf_tune_clear()
+    if path == "off" or not os.path.exists(path):
+        return 0
+    with open(path) as f:
+        table = json.load(f)
+    count = 0
+    for e in table.get("entries", []):
+        rc = lib.skf_tune_set(TUNE_PARAMS[e["param"]], int(e["n_lo"]), int(e["n_hi"]), int(e["value"]))
+        if rc != 0:
+            raise ValueError(f"{path}: entry {e} rejected by skf_tune_set (status {rc})")
+        count += 1
+    return count
+
+
+def tune_get(param: str, n: int) -> int:
+    """The value in effect for order n (table entry, SKF_NB override or built-in rule)."""
+    return int(_load().skf_tune_get(TUNE_PARAMS[param], int(n)))
 
 
 def lib():

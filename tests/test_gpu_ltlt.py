@@ -231,10 +231,12 @@ def test_ltlt_repeatable(skf, gen):
     assert np.array_equal(r1[0], r2[0]) and np.array_equal(r1[2], r2[2])
 
 
-@pytest.mark.parametrize("n", [300, 777, 2048, 4500])
-def test_ltlt_parity_nb64(skf, oracle_mod, gen, n, monkeypatch):
-    """The narrower panel (used when the matrix needs more than one CU's worth of slots per CU)."""
-    monkeypatch.setenv("SKF_NB", "64")
+@pytest.mark.parametrize("n,nb", [(300, "64"), (777, "64"), (2048, "64"), (4500, "64"), (300, "128"),
+                                  (2048, "128"), (4096, "128")])
+def test_ltlt_parity_nb(skf, oracle_mod, gen, n, nb, monkeypatch):
+    """Each panel width forced, whatever the tuning table picks for n (the narrow
+    panel is also the only one that fits beyond one CU's worth of slots per CU)."""
+    monkeypatch.setenv("SKF_NB", nb)
     A = gen.skew_gaussian(n, 6000 + n)
     ref = oracle_mod.ltlt(A, want_mag=True, nthreads=8)
     LT, ipiv, T, info = _factor_gpu(skf, A)

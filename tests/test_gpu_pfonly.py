@@ -64,9 +64,11 @@ def test_pfonly_parity(skf, oracle_mod, gen, n):
     _check_against_oracle(oracle_mod, A, ip, T, info)
 
 
-@pytest.mark.parametrize("n", [300, 778, 2048, 4500])
-def test_pfonly_parity_nb64(skf, oracle_mod, gen, n, monkeypatch):
-    monkeypatch.setenv("SKF_NB", "64")
+@pytest.mark.parametrize("n,nb", [(300, "64"), (778, "64"), (2048, "64"), (4500, "64"), (300, "128"),
+                                  (2048, "128"), (4096, "128")])
+def test_pfonly_parity_nb(skf, oracle_mod, gen, n, nb, monkeypatch):
+    """Each panel width forced, whatever the tuning table picks for n."""
+    monkeypatch.setenv("SKF_NB", nb)
     A = gen.skew_gaussian(n, 9300 + n)
     ip, T, info = _pf_gpu(skf, A)
     _check_against_oracle(oracle_mod, A, ip, T, info)

@@ -24,7 +24,8 @@ def skf():
     return s
 
 
-CASES = [(300, 11, None), (1000, 12, None), (4096, 13, None), (1000, 14, "64"), (4500, 15, "64")]
+CASES = [(300, 11, "128"), (1000, 12, "128"), (4096, 13, "128"), (1000, 14, "64"), (4500, 15, "64"),
+         (2000, 16, None)]
 
 
 @pytest.mark.parametrize("n,seed,nb", CASES, ids=[f"n{c[0]}-nb{c[2] or 'auto'}" for c in CASES])
