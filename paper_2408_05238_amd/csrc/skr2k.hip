@@ -382,20 +382,27 @@ __global__ void __launch_bounds__(NTHR, 2) skr2k_perm_kernel(Operands o, int64_t
     // FP64 accumulates straight onto the source tile, gathered while the
     // first operand chunk is loading
     tile_mainloop<T, VEC, kPlain>(o, rI, rJ, wm * WT, wn * WT, active, st, acc, [&] {
-      // by 16-row slices: 16 loads per lane in flight per slice
+      // all 64 loads per lane in flight at once, straight into the
+      // accumulators (one memory latency instead of four); masks and signs
+      // applied in place once they have landed
+      if (active) {
+        gather(0, 4, [&](int mi, int ni, int r, double x) { acc[mi][ni][r] = x; });
+      } else {
 #pragma unroll
-      for (int mi = 0; mi < 4; ++mi) {
-        double v[4][4];
-        if (active) gather(mi, mi + 1, [&](int, int ni, int r, double x) { v[ni][r] = x; });
+        for (int a = 0; a < 4; ++a)
+#pragma unroll
+          for (int b = 0; b < 4; ++b) acc[a][b] = typename Mfma<T>::acc_t{0, 0, 0, 0};
+      }
+#pragma unroll
+      for (int mi = 0; mi < 4; ++mi)
 #pragma unroll
         for (int ni = 0; ni < 4; ++ni)
 #pragma unroll
           for (int r = 0; r < 4; ++r) {
-            double x = active ? v[ni][r] : 0.0;
+            double x = acc[mi][ni][r];
             fix(x, (mi * 4 + ni) * 4 + r);
             acc[mi][ni][r] = x;
           }
-      }
     });
     if (!active) return;
 #pragma unroll
