@@ -90,6 +90,11 @@ __device__ inline double dppd(double x) {
 __device__ inline uint32_t rl32(uint32_t x, int lane) { return (uint32_t)__builtin_amdgcn_readlane((int)x, lane); }
 __device__ inline double rld(double x, int lane) { return from32(rl32(hi32(x), lane), rl32(lo32(x), lane)); }
 
+// Marks a polled word as consumed where its loads are known to have landed (a
+// wait loop's exit), so the compiler never places a later wait for it after
+// stores it cannot tell apart (vmcnt counts stores too).
+__device__ inline void landed(uint64_t& w) { asm volatile("" : "+v"(w)); }
+
 // Candidate ordering: larger |c| first, then lower current index.
 __device__ inline bool better(double a, uint32_t pa, double b, uint32_t pb) {
   return (a > b) || (a == b && pa < pb);
@@ -169,6 +174,10 @@ __global__ void __launch_bounds__(kPanelThreads) panel_kernel(PanelParams P) {
   int32_t psi = mine ? (int32_t)(rowbase + lane) : INT32_MAX;
   const int32_t hbm = mine ? (int32_t)(rowbase + lane) : 0;
   double cur = mine ? src[rowbase + lane + k0 * ld] : 0.0;
+  // wait for this load here: left pending into the step loop, its wait sat at
+  // the loop head and, vmcnt counting stores too, made every step wait for the
+  // previous step's mirror and record stores
+  asm volatile("" : "+v"(cur));
   double lj = 0.0;  // this slot's l of the current pair (register copy of sm.Le[j][lane])
   int stop = 0;
 
@@ -252,6 +261,11 @@ __global__ void __launch_bounds__(kPanelThreads) panel_kernel(PanelParams P) {
           }
         }
         load_all();
+      }
+#pragma unroll
+      for (int q = 0; q < NQ; ++q) {
+        landed(w[q][0]);
+        landed(w[q][1]);
       }
 #pragma unroll
       for (int q = 0; q < NQ; ++q) {
@@ -358,10 +372,20 @@ __global__ void __launch_bounds__(kPanelThreads) panel_kernel(PanelParams P) {
         }
         load_all();
       }
+      landed(a0);
+      landed(a1);
+      landed(b0);
+      landed(b1);
+      landed(z0);
+      landed(z1);
       // coefficient d sits in component d % 2 of pair d / 2
       if (hasA) reinterpret_cast<double*>(&sm.coef[0])[lane] = from32((uint32_t)a0, (uint32_t)a1);
       if (hasB) reinterpret_cast<double*>(&sm.coef[0])[lane + 64] = from32((uint32_t)b0, (uint32_t)b1);
       l0 = from32((uint32_t)z0, (uint32_t)z1);
+      // form l0 in its own registers here, while the coefficient loads are
+      // known to have landed: formed lazily at its use after this step's
+      // mirror stores, it made the compiler wait for those stores too
+      asm volatile("" : "+v"(l0));
       if (__any(tout)) {
         stop = 4;
         break;
@@ -494,6 +518,10 @@ __global__ void __launch_bounds__(kPanelThreads) panel_pf_kernel(PanelParams P) 
   int32_t psi = mine ? (int32_t)(rowbase + lane) : INT32_MAX;
   const int32_t hbm = mine ? (int32_t)(rowbase + lane) : 0;
   double cur = mine ? src[rowbase + lane + k0 * ld] : 0.0;
+  // wait for this load here: left pending into the step loop, its wait sat at
+  // the loop head and, vmcnt counting stores too, made every step wait for the
+  // previous step's mirror and record stores
+  asm volatile("" : "+v"(cur));
   int stop = 0;
   int done = 0;  // steps that produced a pair
 
@@ -585,6 +613,17 @@ __global__ void __launch_bounds__(kPanelThreads) panel_pf_kernel(PanelParams P) 
         }
         load_recs();
       }
+#pragma unroll
+      for (int q = 0; q < NQ; ++q) {
+        landed(w[q][0]);
+        landed(w[q][1]);
+      }
+      landed(f0a);
+      landed(f0b);
+      landed(f0c);
+      landed(f1a);
+      landed(f1b);
+      landed(f1c);
 #pragma unroll
       for (int q = 0; q < NQ; ++q) {
         const int rr = lane + 64 * q;
@@ -685,6 +724,14 @@ __global__ void __launch_bounds__(kPanelThreads) panel_pf_kernel(PanelParams P) 
         }
         load_coef();
       }
+      landed(xa0);
+      landed(xa1);
+      landed(xb0);
+      landed(xb1);
+      landed(ya0);
+      landed(ya1);
+      landed(yb0);
+      landed(yb1);
       // coefficient d sits in component d % 2 of step d / 2
       if (hasA) {
         reinterpret_cast<double*>(&sm.cx[0])[lane] = from32((uint32_t)xa0, (uint32_t)xa1);
