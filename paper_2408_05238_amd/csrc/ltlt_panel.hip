@@ -100,15 +100,15 @@ __device__ inline bool better(double a, uint32_t pa, double b, uint32_t pb) {
   return (a > b) || (a == b && pa < pb);
 }
 
-// Wave-wide maximum of v / minimum of u; every lane ends with the result.
-// Inside each row of 16 lanes: xor-1, xor-2, rotate-4, rotate-8 (DPP); across
-// the four rows: readlane of lanes 0, 16, 32, 48.
-__device__ inline double wave_max(double v) {
-  v = fmax(v, dppd<0xB1>(v));   // quad_perm [1,0,3,2]
-  v = fmax(v, dppd<0x4E>(v));   // quad_perm [2,3,0,1]
-  v = fmax(v, dppd<0x124>(v));  // row_ror:4
-  v = fmax(v, dppd<0x128>(v));  // row_ror:8
-  return fmax(fmax(rld(v, 0), rld(v, 16)), fmax(rld(v, 32), rld(v, 48)));
+// Wave-wide maximum / minimum of u; every lane ends with the result.  Inside
+// each row of 16 lanes: xor-1, xor-2, rotate-4, rotate-8 (DPP); across the four
+// rows: readlane of lanes 0, 16, 32, 48 (scalar, uniform).
+__device__ inline uint32_t wave_max_u32(uint32_t u) {
+  u = max(u, dpp32<0xB1>(u));   // quad_perm [1,0,3,2]
+  u = max(u, dpp32<0x4E>(u));   // quad_perm [2,3,0,1]
+  u = max(u, dpp32<0x124>(u));  // row_ror:4
+  u = max(u, dpp32<0x128>(u));  // row_ror:8
+  return max(max(rl32(u, 0), rl32(u, 16)), max(rl32(u, 32), rl32(u, 48)));
 }
 __device__ inline uint32_t wave_min_u32(uint32_t u) {
   u = min(u, dpp32<0xB1>(u));
@@ -119,13 +119,22 @@ __device__ inline uint32_t wave_min_u32(uint32_t u) {
 }
 
 // Lane of the best candidate (largest v, then lowest p) among the lanes with
-// `cand` set (their v >= 0), or -1 if there is none.  The maximum is found with
-// plain max steps and the lanes holding it by one ballot; only an exact tie of
-// values needs the index reduction.
+// `cand` set (their v >= 0, +0 for zero), or -1 if there is none.  For
+// non-negative doubles the bit patterns order as the values, so the maximum is
+// found on 32-bit keys: the high word (+1, so that every candidate beats a
+// non-candidate's 0), then, only if several lanes share it, the low word among
+// them; the lanes holding it by a ballot; only an exact tie of values needs the
+// index reduction.
 __device__ inline int wave_argbest(double v, uint32_t p, bool cand) {
-  const double m = wave_max(cand ? v : -1.0);
-  const uint64_t at = __ballot(cand && v == m);
-  if (at == 0) return -1;
+  const uint64_t bits = (uint64_t)__double_as_longlong(v);
+  const uint32_t hk = cand ? (uint32_t)(bits >> 32) + 1u : 0u;
+  const uint32_t mh = wave_max_u32(hk);
+  if (mh == 0) return -1;
+  uint64_t at = __ballot(hk == mh);
+  if ((at & (at - 1)) == 0) return (int)__builtin_ctzll(at);
+  const bool in_hi = (at >> threadIdx.x) & 1ull;
+  const uint32_t ml = wave_max_u32(in_hi ? (uint32_t)bits : 0u);
+  at = __ballot(in_hi && (uint32_t)bits == ml);
   if ((at & (at - 1)) == 0) return (int)__builtin_ctzll(at);
   const bool mine = (at >> threadIdx.x) & 1ull;
   const uint32_t q = wave_min_u32(mine ? p : 0xFFFFFFFFu);
@@ -397,24 +406,31 @@ __global__ void __launch_bounds__(kPanelThreads) panel_kernel(PanelParams P) {
     // pass, their LDS reads issued together (coefficients of pairs >= j are zero)
     double corr = 0.0;
     {
-      double c0 = 0.0, c1 = 0.0, c2 = 0.0, c3 = 0.0;
+      // l' w-terms and w l'-terms summed separately (one fused multiply-add per
+      // product, four independent chains each)
+      double p0 = 0.0, p1 = 0.0, p2 = 0.0, p3 = 0.0, m0 = 0.0, m1 = 0.0, m2 = 0.0, m3 = 0.0;
       const int jr = (j + 15) & ~15;
       for (int q = 0; q < jr; q += 16) {
         double2 a[16], c[16];
+        const double2* cb = &sm.coef[q];
 #pragma unroll
         for (int t = 0; t < 16; ++t) {
           a[t] = sm.LW[q + t][lane];
-          c[t] = sm.coef[q + t];
+          c[t] = cb[t];
         }
 #pragma unroll
         for (int t = 0; t < 16; t += 4) {
-          c0 += a[t].x * c[t].y - a[t].y * c[t].x;
-          c1 += a[t + 1].x * c[t + 1].y - a[t + 1].y * c[t + 1].x;
-          c2 += a[t + 2].x * c[t + 2].y - a[t + 2].y * c[t + 2].x;
-          c3 += a[t + 3].x * c[t + 3].y - a[t + 3].y * c[t + 3].x;
+          p0 = fma(a[t].x, c[t].y, p0);
+          m0 = fma(a[t].y, c[t].x, m0);
+          p1 = fma(a[t + 1].x, c[t + 1].y, p1);
+          m1 = fma(a[t + 1].y, c[t + 1].x, m1);
+          p2 = fma(a[t + 2].x, c[t + 2].y, p2);
+          m2 = fma(a[t + 2].y, c[t + 2].x, m2);
+          p3 = fma(a[t + 3].x, c[t + 3].y, p3);
+          m3 = fma(a[t + 3].y, c[t + 3].x, m3);
         }
       }
-      corr = (c0 + c1) + (c2 + c3);
+      corr = ((p0 + p1) + (p2 + p3)) - ((m0 + m1) + (m2 + m3));
     }
 
     // finish the column
