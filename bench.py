@@ -286,46 +286,64 @@ def bench_batched(args):
 
 def bench_complex(args):
     """Complex128 Pfaffian-only reduction of one n x n complex skew Gaussian matrix
-    (real part seed/stream A, imaginary part seed/stream IMAG); n defaults to 4096."""
+    (real part seed/stream A, imaginary part seed/stream IMAG); n defaults to 4096.
+    The blocked reduction: complex panel kernel plus the real trailing update run
+    on the real and imaginary planes (FP64 matrix cores)."""
+    import ctypes
+
     import numpy as np
     import torch
 
     from paper_2408_05238_amd import inputs, skf
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
-    skf.lib()
+    lib = skf.lib()
     n = args.n if args.n != 16384 else 4096
     dev = torch.device("cuda:0")
     A = inputs.skew_gaussian_c128(n, args.seed)
     dA = skf.to_device_colmajor(A, device=dev)
-    work = skf.workspace(int(skf.lib().skf_pfonly_c128_workspace(n)), dev)
+    work = skf.workspace(int(lib.skf_pfonly_c128_workspace(n)), dev)
     ipiv = torch.empty(n, dtype=torch.int32, device=dev)
     T = torch.empty(max(n - 1, 1), dtype=torch.complex128, device=dev)
     dinfo = torch.zeros(1, dtype=torch.int32, device=dev)
     for _ in range(args.warmup):
         skf.pfonly_c128(dA, ipiv, T, work, dinfo)
     torch.cuda.synchronize()
+    lib.skf_profile_read(None, None, None, 1)
+    lib.skf_profile_enable(1)
     t0 = time.perf_counter()
     for _ in range(args.steps):
         skf.pfonly_c128(dA, ipiv, T, work, dinfo)
     torch.cuda.synchronize()
     ms = (time.perf_counter() - t0) * 1e3 / args.steps
+    lib.skf_profile_enable(0)
+    pms = (ctypes.c_double * 2)()
+    pfl = (ctypes.c_double * 2)()
+    pcnt = (ctypes.c_int64 * 2)()
+    lib.skf_profile_read(pms, pfl, pcnt, 1)
     assert int(dinfo.item()) == 0
     la, ph = skf.logpf_c128_from_factors(n, ipiv, T)
-    # algorithmic HBM bytes: each step reads and writes the trailing square once (16 B per entry)
-    nbytes = sum(2.0 * 16.0 * (n - k - 2) ** 2 for k in range(0, n - 1, 2) if n - k - 2 > 0)
-    gbs = nbytes / (ms * 1e-3) / 1e9
+    # nominal work: n/2 complex rank-2 trailing updates = 4 n^3/3 real flops
+    flops = 4.0 * n ** 3 / 3.0
+    upd_tf = pfl[1] / (pms[1] * 1e-3) / 1e12 if pms[1] > 0 else 0.0
+    blocked = pcnt[0] > 0  # only the blocked form records panel launches
     out = {"metric": f"complex128 Pfaffian-only reduction time at n={n}", "value": round(ms, 3), "unit": "ms",
            "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms, 3),
            "higher_is_better": False, "scaling": "weak", "vs_baseline": None, "dtype": "c128",
            "data": "synthetic",
            "config": {"workload": f"dense complex skew-symmetric Gaussian matrix n={n} (seed {args.seed}), "
-                                  "unblocked Pfaffian-only reduction", "n": n},
-           "roofline": {"bound": "hbm", "kernel": "whole reduction (trailing rank-2 updates dominate)",
-                        "achieved": round(gbs, 1), "peak": 8000.0, "unit": "GB/s", "frac": round(gbs / 8000.0, 4),
-                        "traffic": None, "algorithmic_bytes": nbytes},
-           "logabs_pf": float(la.item()), "phase": [float(ph.real.item()), float(ph.imag.item())],
-           "launches_per_reduction": 2 * (n // 2) + 1}
+                                  "blocked Pfaffian-only reduction" if blocked else "unblocked Pfaffian-only reduction",
+                      "n": n},
+           "gflops_nominal": round(flops / (ms * 1e-3) / 1e9, 1),
+           "roofline": {"bound": "mfma", "kernel": "skr2k_perm on the real and imaginary planes (trailing update)",
+                        "achieved": round(upd_tf, 3), "peak": FP64_MFMA_PEAK_TFLOPS, "unit": "TFLOP/s",
+                        "frac": round(upd_tf / FP64_MFMA_PEAK_TFLOPS, 4), "traffic": None,
+                        "launches": int(2 * pcnt[1]) // max(args.steps, 1),
+                        "ms_per_reduction": round(pms[1] / max(args.steps, 1), 3)},
+           "panel": {"ms_per_reduction": round(pms[0] / max(args.steps, 1), 3),
+                     "us_per_step": round(pms[0] * 1e3 / max(args.steps, 1) / max(n // 2, 1), 3),
+                     "share": round(pms[0] / max(args.steps, 1) / ms, 3)},
+           "logabs_pf": float(la.item()), "phase": [float(ph.real.item()), float(ph.imag.item())]}
     if not args.no_cpu_baseline:
         import oracle
         m = min(n, 1024)

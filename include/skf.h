@@ -208,7 +208,8 @@ int skf_solve(skf_int n, skf_int nrhs, const double* LT, skf_int lda, const int3
 int skf_solve_noalloc(skf_int n, skf_int nrhs, const double* LT, skf_int lda, const int32_t* ipiv,
                       const double* T, double* B, skf_int ldb, int* dinfo, void* stream);
 
-/* Device workspace (bytes) for skf_pfonly_c128: a full n x n complex128 copy. */
+/* Device workspace (bytes) for skf_pfonly_c128: four n x n FP64 planes and the
+ * panel buffers (blocked form), at least a full n x n complex128 copy. */
 size_t skf_pfonly_c128_workspace(skf_int n);
 
 /*
@@ -216,9 +217,14 @@ size_t skf_pfonly_c128_workspace(skf_int n);
  * elimination of skf_pfonly at even steps k, with the pivot the largest
  * |z|^2 = re^2 + im^2 below the diagonal of column k (lowest index on ties).
  * Pf(A) = (-1)^{s + n/2} prod_{k even} T[k], s = #{j : ipiv[j] != j}.
- * Unblocked: the strict lower triangle is expanded into a full copy in the
- * workspace and each step is a few launches (pivot, interchange, l and v,
- * trailing rank-2 update); n <= 65535.
+ * Blocked (n up to 64 x 256 panel workgroups of the device, i.e. 16385 with the
+ * wide panel and 32769 with the narrow one on 256 CUs): the input is split into
+ * real and imaginary planes in the workspace, each panel of nb/2 even steps runs
+ * as one persistent kernel and the complex rank-nb trailing update as two real
+ * skew rank-2nb updates on the matrix cores (one per plane).  Beyond that, or
+ * with SKF_C128_UNBLOCKED set, the unblocked form: a full copy and a few
+ * launches per step (n <= 65535).  Both give the same interchanges on generic
+ * input; T agrees to rounding.
  *   A      device, lda x n complex128 (interleaved re, im), strict lower triangle
  *          read, not modified
  *   ipiv   device int32[n]: ipiv[k+1] (k even) = step k's interchange, else j

@@ -5,6 +5,7 @@
 #include <algorithm>
 #include <vector>
 #include <string.h>
+#include <stdlib.h>
 
 #include "skf_internal.h"
 
@@ -307,9 +308,20 @@ int skf_solve_noalloc(skf_int n, skf_int nrhs, const double* LT, skf_int lda, co
   return run_solve_noalloc(n, nrhs, LT, lda, ipiv, T, B, ldb, dinfo, (hipStream_t)stream);
 }
 
+// The blocked reduction runs when its panel fits on the device (n up to 256 or
+// 512 panel workgroups of 64 rows) and SKF_C128_UNBLOCKED is unset; otherwise
+// the unblocked one.  The workspace covers whichever of the two is larger.
+static bool c128_blocked(skf_int n) {
+  return pfonly_c128_blocked_nb(n) > 0 && !getenv("SKF_C128_UNBLOCKED");
+}
+
+static size_t c128_core_bytes(skf_int n) {
+  return std::max(pfonly_c128_workspace_bytes(n), pfonly_c128_blocked_workspace_bytes(n));
+}
+
 size_t skf_pfonly_c128_workspace(skf_int n) {
   if (n < 0) return 0;
-  return pfonly_c128_workspace_bytes(n) + 256;
+  return c128_core_bytes(n) + 256;
 }
 
 int skf_pfonly_c128(skf_int n, const double* A, skf_int lda, int32_t* ipiv, double* T, void* work, size_t lwork,
@@ -322,9 +334,10 @@ int skf_pfonly_c128(skf_int n, const double* A, skf_int lda, int32_t* ipiv, doub
   if (!work || ((uintptr_t)work & 255)) return -6;
   if (lwork < skf_pfonly_c128_workspace(n)) return SKF_EWORK;
   hipStream_t s = (hipStream_t)stream;
-  const size_t core = pfonly_c128_workspace_bytes(n);
+  const size_t core = c128_core_bytes(n);
   int* dinfo_int = (int*)((char*)work + core);
-  int rc = run_pfonly_c128(n, A, lda, ipiv, T, work, core, dinfo ? dinfo : dinfo_int, s);
+  int rc = c128_blocked(n) ? run_pfonly_c128_blocked(n, A, lda, ipiv, T, work, core, dinfo ? dinfo : dinfo_int, s)
+                           : run_pfonly_c128(n, A, lda, ipiv, T, work, core, dinfo ? dinfo : dinfo_int, s);
   if (dinfo) return rc;
   return finish_sync(rc, dinfo_int, s);
 }

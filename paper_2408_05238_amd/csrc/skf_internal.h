@@ -157,6 +157,11 @@ int run_pfonly_c128(int64_t n, const double* A, int64_t lda, int32_t* ipiv, doub
                     int* dinfo, hipStream_t s);
 int launch_logpf_c128(int64_t n, const int32_t* ipiv, const double* T, double* logabs, double* phase,
                       hipStream_t s);
+// Blocked form (complex_blocked.hip): panel width for n (0 when its panel does not fit the device).
+int pfonly_c128_blocked_nb(int64_t n);
+size_t pfonly_c128_blocked_workspace_bytes(int64_t n);
+int run_pfonly_c128_blocked(int64_t n, const double* A, int64_t lda, int32_t* ipiv, double* T, void* work,
+                            size_t lwork, int* dinfo, hipStream_t s);
 
 // Kernel timing hooks (api.hip): no-ops unless skf_profile_enable(1).
 void prof_begin(hipStream_t s);

@@ -11,9 +11,12 @@ Calls only the generator and ``oracle/`` (never the GPU path).  Output per
   and 16384 single entries (``Li``, ``Lj``, ``Lvals``, ``Lmag``), where the
   magnitude sum is that of the multiplier's numerator;
 * ``pfonly_n{n}_s{seed}.npz`` (Pfaffian-only reduction): ipiv, T, T_mag,
-  logabs, sign, info, oracle wall time and threads.
+  logabs, sign, info, oracle wall time and threads;
+* ``pfonly_c128_n{n}_s{seed}.npz`` (complex Pfaffian-only reduction of the
+  complex skew Gaussian matrix of the same seed): ipiv, T (complex128), T_mag,
+  logabs, phase, info, oracle wall time.
 
-    python tests/golden/make_golden.py 16384 2 [threads] [ltlt|pfonly]
+    python tests/golden/make_golden.py 16384 2 [threads] [ltlt|pfonly|c128]
 
 When the file already exists, the new pivots and T must equal the stored ones
 bit for bit (the oracle's arithmetic is deterministic), else nothing is written.
@@ -66,6 +69,21 @@ def main():
     seed = int(sys.argv[2])
     threads = int(sys.argv[3]) if len(sys.argv) > 3 else (os.cpu_count() or 1)
     mode = sys.argv[4] if len(sys.argv) > 4 else "ltlt"
+    if mode == "c128":
+        A = inputs.skew_gaussian_c128(n, seed)
+        t0 = time.time()
+        ipiv, T, info, Tm = oracle.pfonly_c128(A, want_mag=True)
+        dt = time.time() - t0
+        la, ph = oracle.logpf_c128_from_factors(n, ipiv, T)
+        out = os.path.join(HERE, f"pfonly_c128_n{n}_s{seed}.npz")
+        if os.path.exists(out):
+            old = np.load(out)
+            if not (np.array_equal(old["ipiv"], ipiv) and np.array_equal(old["T"], T)):
+                raise SystemExit(f"{out}: new oracle results differ from the stored ones; not overwritten")
+        np.savez(out, ipiv=ipiv.astype(np.int32), T=T.astype(np.complex128), T_mag=Tm, logabs=np.float64(la),
+                 phase=np.complex128(ph), info=np.int32(info), oracle_seconds=np.float64(dt))
+        print(f"c128 n={n} seed={seed} info={info} logabs={la!r} phase={ph!r} time={dt:.1f}s -> {out}")
+        return
     A = inputs.skew_gaussian(n, seed, inputs.STREAM_A)
     t0 = time.time()
     if mode == "pfonly":

@@ -2,7 +2,11 @@
 (skf_pfonly_c128, through the C ABI) against the oracle's numpy reduction:
 interchanges bit for bit, the odd entries exactly the identity / zero, each
 pivot within the complex summation-error bound of its magnitude sum, log|Pf|
-and the phase.
+and the phase.  Both forms are covered: the blocked one (panel kernel plus the
+real matrix-core trailing update on the real and imaginary planes; both panel
+widths) and the unblocked one (SKF_C128_UNBLOCKED=1); at n = 2048 and 4096 the
+reference is the oracle's stored result (tests/golden/pfonly_c128_n*_s2.npz,
+written by tests/golden/make_golden.py).
 """
 from __future__ import annotations
 
@@ -14,6 +18,20 @@ import pytest
 pytestmark = pytest.mark.gpu
 
 U_RND = 2.0 ** -53
+
+
+PATHS = ["blocked", "unblocked", "blocked-nb64"]
+
+
+@pytest.fixture(params=PATHS)
+def path(request, monkeypatch):
+    monkeypatch.delenv("SKF_C128_UNBLOCKED", raising=False)
+    monkeypatch.delenv("SKF_NB", raising=False)
+    if request.param == "unblocked":
+        monkeypatch.setenv("SKF_C128_UNBLOCKED", "1")
+    elif request.param == "blocked-nb64":
+        monkeypatch.setenv("SKF_NB", "64")
+    return request.param
 
 
 @pytest.fixture(scope="module")
@@ -42,11 +60,7 @@ def _run(skf, A):
     return ipiv.cpu().numpy(), T.cpu().numpy(), info, float(la.item()), complex(ph.item())
 
 
-@pytest.mark.parametrize("n", [2, 4, 6, 64, 130, 512, 1024])
-def test_complex_parity(skf, oracle_mod, n):
-    A = _cgauss(n, 7000 + n)
-    ip, T, info, la, ph = _run(skf, A)
-    ip_r, T_r, info_r, Tm = oracle_mod.pfonly_c128(A, want_mag=True)
+def _check(oracle_mod, n, ip, T, info, la, ph, ip_r, T_r, info_r, Tm):
     assert info == info_r == 0
     assert np.array_equal(ip, ip_r), int(np.argmax(ip != ip_r))
     assert np.all(T[1::2] == 0) and np.all(ip[0::2] == np.arange(0, n, 2))
@@ -61,7 +75,28 @@ def test_complex_parity(skf, oracle_mod, n):
     assert abs(ph - ph_r) <= ph_tol, (ph, ph_r, ph_tol)
 
 
-def test_complex_known_values(skf, oracle_mod):
+@pytest.mark.parametrize("n", [2, 4, 6, 64, 130, 512, 1024])
+def test_complex_parity(skf, oracle_mod, path, n):
+    A = _cgauss(n, 7000 + n)
+    ip, T, info, la, ph = _run(skf, A)
+    ip_r, T_r, info_r, Tm = oracle_mod.pfonly_c128(A, want_mag=True)
+    _check(oracle_mod, n, ip, T, info, la, ph, ip_r, T_r, info_r, Tm)
+
+
+@pytest.mark.parametrize("n", [2048, 4096])
+def test_complex_against_stored_oracle(skf, oracle_mod, n, monkeypatch):
+    """The blocked reduction at n = 2048 (32 panel workgroups) and 4096 (64) on the
+    complex skew Gaussian matrix of seed 2 (the bench workload at 4096)."""
+    import os
+    from paper_2408_05238_amd import inputs
+    monkeypatch.delenv("SKF_C128_UNBLOCKED", raising=False)
+    g = np.load(os.path.join(os.path.dirname(__file__), "golden", f"pfonly_c128_n{n}_s2.npz"))
+    print(f"complex golden case n={n}", flush=True)
+    ip, T, info, la, ph = _run(skf, inputs.skew_gaussian_c128(n, 2))
+    _check(oracle_mod, n, ip, T, info, la, ph, g["ipiv"], g["T"], int(g["info"]), g["T_mag"])
+
+
+def test_complex_known_values(skf, oracle_mod, path):
     # block diagonal: Pf = prod over blocks of A[2i, 2i+1] = prod(-d_i)
     m = 40
     rng = np.random.default_rng(3)
@@ -80,7 +115,7 @@ def test_complex_known_values(skf, oracle_mod):
     assert np.all(T.imag == 0)
 
 
-def test_complex_edges(skf, oracle_mod):
+def test_complex_edges(skf, oracle_mod, path):
     from paper_2408_05238_amd import skf as s
     ip, T, info, la, ph = _run(skf, _cgauss(9, 1))
     assert info == 9 and np.array_equal(ip, np.arange(9)) and np.all(T == 0) and la == -math.inf and ph == 0
