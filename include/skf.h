@@ -70,14 +70,15 @@ typedef int64_t skf_int;
  * as JSON and the Python binding loads them here when the library is first
  * used.  Each entry covers the orders n_lo <= n <= n_hi; a later entry covering
  * the same order wins over an earlier one.  Without an entry the built-in rule
- * applies (panel width 128 when its workgroups fit on the device, else 64; band
- * of 8 block rows).  The environment variable SKF_NB=64|128 overrides both
- * panel widths.  A table value that is infeasible for a given n (too many panel
- * workgroups to be resident) is ignored for that n.  Host-only; thread-safe;
- * takes effect for calls made afterwards (workspace sizes cover every width).
+ * applies (the widest panel of 128, 64, 32, 16 whose workgroups fit on the
+ * device; band of 8 block rows).  The environment variable SKF_NB=16|32|64|128
+ * overrides both panel widths.  A table value that is infeasible for a given n
+ * (too many panel workgroups to be resident) is ignored for that n.  Host-only;
+ * thread-safe; takes effect for calls made afterwards (workspace sizes cover
+ * every feasible width).
  */
-#define SKF_TUNE_LTLT_NB 0    /* panel width of skf_ltlt and skf_ltlt-based calls: 64 or 128 */
-#define SKF_TUNE_PFONLY_NB 1  /* panel width (twice the steps per panel) of skf_pfonly / skf_logpf: 64 or 128 */
+#define SKF_TUNE_LTLT_NB 0    /* panel width of skf_ltlt and skf_ltlt-based calls: 16, 32, 64 or 128 */
+#define SKF_TUNE_PFONLY_NB 1  /* panel width (twice the steps per panel) of skf_pfonly / skf_logpf: 16, 32, 64 or 128 */
 #define SKF_TUNE_SKR2K_BAND 2 /* block rows per band of the trailing update's tile walk, by trailing order: 1..64 */
 #define SKF_TUNE_NPARAMS 3
 /* Add an entry; returns 0, or -1 (param), -2 (n_lo < 0), -3 (n_hi < n_lo), -4 (value not allowed). */
@@ -113,6 +114,10 @@ size_t skf_ltlt_workspace(skf_int n, int prec);
  *   prec   SKF_PREC_F64 or SKF_PREC_F32_TRAILING
  *   work   device workspace of at least skf_ltlt_workspace(n, prec) bytes
  *   dinfo  device int or NULL (see status codes)
+ * Orders: a panel runs one workgroup per 64 rows, all resident at once, so the
+ * panel width is the widest that fits (on 256 CUs: 128 up to n = 16385, 64 up
+ * to 49153, 32 or 16 up to 65537); beyond, SKF_ENOTIMPL.  skf_pfonly: 128 up to
+ * 32769, 64, 32 or 16 up to 65537.
  */
 int skf_ltlt(skf_int n, double* A, skf_int lda, int32_t* ipiv, double* T, int prec,
              void* work, size_t lwork, int* dinfo, void* stream);

@@ -218,6 +218,7 @@ __global__ void __launch_bounds__(kPanelThreads) cpanel_kernel(CPanelParams P) {
           ok &= !need | ((tag16_of(w[q][0]) == t16) & (tag16_of(w[q][1]) == t16));
         }
         if (__all(ok)) break;
+        poll_refresh(it);
         if ((it & 31) == 0) {
           const uint64_t now = wall_clock64();
           if (it == 0) t0 = now;
@@ -319,6 +320,7 @@ __global__ void __launch_bounds__(kPanelThreads) cpanel_kernel(CPanelParams P) {
         for (int t = 0; t < 8; ++t) okc &= (tag_of(cx[t]) == tq) & (tag_of(cy[t]) == tq);
         ok &= !has | okc;
         if (__all(ok)) break;
+        poll_refresh(it);
         if ((it & 31) == 0) {
           const uint64_t now = wall_clock64();
           if (it == 0) t0 = now;

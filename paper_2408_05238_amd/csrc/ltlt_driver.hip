@@ -17,41 +17,45 @@
 
 namespace skf {
 
-// The panel kernel is one wave per workgroup with 64 row slots; LDS holds three
-// (nb/2) x 64 FP64 arrays per workgroup (97 KB at nb = 128, 49 KB at nb = 64),
-// so a CU hosts one (nb = 128) or two (nb = 64) of them at once.  Every
-// workgroup of a panel launch must be resident together.
-static constexpr int kMaxPanelG = 512;
+// The panel kernel is one wave per workgroup with 64 row slots; LDS holds the
+// (nb/2) x 64 pair vectors per workgroup (97 KB at nb = 128, 49 KB at 64, 24 KB
+// at 32, 12 KB at 16), so a CU hosts one, three, six or twelve of them (the
+// occupancy query decides, registers and wave slots included).  Every
+// workgroup of a panel launch must be resident together, so the narrower
+// widths carry larger orders: up to 256, 768, 1536 and 2048 workgroups of 64
+// rows on 256 CUs.
+static constexpr int kMaxPanelG = 2048;
 
 static int slots() { return panel_slots(); }
 
-static int64_t max_panel_groups(int nb) {
-  const int64_t per_cu = (nb == 128) ? 1 : 2;
-  return std::min<int64_t>(kMaxPanelG, per_cu * device_info().num_cus);
+static int64_t max_panel_groups(int nb, bool pf = false) {
+  return std::min<int64_t>(kMaxPanelG, (int64_t)panel_wgs_per_cu(nb, pf) * device_info().num_cus);
 }
 
 // Panel width for order n: SKF_NB override, else the tuning table's entry,
-// else 128 when its workgroups fit on the device, else 64; an infeasible choice
-// falls through to the next rule.  -1: no width fits.
+// else the widest of 128, 64, 32, 16 whose workgroups fit on the device; an
+// infeasible choice falls through to the next rule.  -1: no width fits.
 static int plan_nb(int64_t n, int param) {
   const int64_t g0 = std::max<int64_t>(1, (n - 1 + slots() - 1) / slots());
+  const bool pf = param == SKF_TUNE_PFONLY_NB;
+  auto fits = [&](int nb) { return (nb == 128 || nb == 64 || nb == 32 || nb == 16) && g0 <= max_panel_groups(nb, pf); };
   if (const char* e = getenv("SKF_NB")) {
     const int want = atoi(e);
-    if ((want == 64 || want == 128) && g0 <= max_panel_groups(want)) return want;
+    if (fits(want)) return want;
   }
   const int t = tune_lookup(param, n);
-  if ((t == 64 || t == 128) && g0 <= max_panel_groups(t)) return t;
-  if (g0 <= max_panel_groups(128)) return 128;
-  if (g0 <= max_panel_groups(64)) return 64;
+  if (fits(t)) return t;
+  for (int nb : {128, 64, 32, 16})
+    if (fits(nb)) return nb;
   return -1;
 }
 
 int ltlt_plan_nb(int64_t n) { return plan_nb(n, SKF_TUNE_LTLT_NB); }
 int pfonly_plan_nb(int64_t n) { return plan_nb(n, SKF_TUNE_PFONLY_NB); }
 
-int ltlt_panel_grid(int64_t m, int nb, int* G, int* S) {
+int ltlt_panel_grid(int64_t m, int nb, int* G, int* S, bool pf) {
   const int64_t g = std::max<int64_t>(1, (m + slots() - 1) / slots());
-  if (g > max_panel_groups(nb)) return SKF_ENOTIMPL;
+  if (g > max_panel_groups(nb, pf)) return SKF_ENOTIMPL;
   *G = (int)g;
   *S = slots();
   return 0;
@@ -90,11 +94,11 @@ static size_t carve(LtltWork* w, char* base, int64_t n, int nb) {
 // table or the environment selects later.
 size_t ltlt_workspace_bytes(int64_t n, int prec) {
   (void)prec;
-  if (ltlt_plan_nb(n) < 0) return 0;
+  if (ltlt_plan_nb(n) < 0 && pfonly_plan_nb(n) < 0) return 0;
   const int64_t g0 = std::max<int64_t>(1, (n - 1 + slots() - 1) / slots());
   size_t b = 0;
-  for (int nb : {64, 128}) {
-    if (g0 > max_panel_groups(nb)) continue;
+  for (int nb : {16, 32, 64, 128}) {
+    if (g0 > max_panel_groups(nb, false) && g0 > max_panel_groups(nb, true)) continue;
     LtltWork w;
     b = std::max(b, carve(&w, nullptr, n, nb));
   }
@@ -142,7 +146,7 @@ int run_ltlt(int64_t n, double* A, int64_t lda, int32_t* ipiv, double* T, int pr
     pp.k0 = k0;
     pp.nsteps = nsteps;
     pp.nb = nb;
-    if ((rc = ltlt_panel_grid(m, nb, &pp.G, &pp.S))) return rc;
+    if ((rc = ltlt_panel_grid(m, nb, &pp.G, &pp.S, false))) return rc;
     pp.src = buf[P % 2];
     pp.ld = ldb[P % 2];
     pp.Lbuf = w.Lbuf;
@@ -212,7 +216,7 @@ int run_pfonly(int64_t n, double* A, int64_t lda, int32_t* ipiv, double* T, int 
     pp.k0 = k0;
     pp.nsteps = nsteps;
     pp.nb = nb;
-    if ((rc = ltlt_panel_grid(n - k0 - 1, nb, &pp.G, &pp.S))) return rc;
+    if ((rc = ltlt_panel_grid(n - k0 - 1, nb, &pp.G, &pp.S, true))) return rc;
     pp.src = buf[P % 2];
     pp.ld = ldb[P % 2];
     pp.Lp = w.Lp;

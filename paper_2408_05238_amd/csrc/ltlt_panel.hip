@@ -34,6 +34,8 @@
 // expected step's tag, so no fence is needed and a torn record is never used.
 // Records are double-buffered by step parity.  Every wait is bounded: past the
 // limit the workgroup records SKF_ETIMEOUT and leaves, so every wave ends.
+#include <algorithm>
+
 #include "panel_common.h"
 
 namespace skf {
@@ -160,6 +162,7 @@ __global__ void __launch_bounds__(kPanelThreads) panel_kernel(PanelParams P) {
           ok &= !need | ((tag16_of(w[q][0]) == t16) & (tag16_of(w[q][1]) == t16));  // no short-circuit branches
         }
         if (__all(ok)) break;
+        poll_refresh(it);
         if ((it & 31) == 0) {
           const uint64_t now = wall_clock64();
           if (it == 0) t0 = now;
@@ -270,6 +273,7 @@ __global__ void __launch_bounds__(kPanelThreads) panel_kernel(PanelParams P) {
                         (!hasB | ((tag_of(b0) == tB) & (tag_of(b1) == tB))) & (tag_of(z0) == tag) &
                         (tag_of(z1) == tag);
         if (__all(ok)) break;
+        poll_refresh(it);
         if ((it & 31) == 0) {
           const uint64_t now = wall_clock64();
           if (it == 0) t0 = now;
@@ -302,23 +306,25 @@ __global__ void __launch_bounds__(kPanelThreads) panel_kernel(PanelParams P) {
     const double gat = below ? (lowr ? graw : -graw) : 0.0;
 
     // skew GEMV with the pivot row over the pairs so far: sixteen pairs per
-    // pass, their LDS reads issued together (coefficients of pairs >= j are zero)
+    // pass (all of them for the narrowest panel), their LDS reads issued
+    // together (coefficients of pairs >= j are zero)
     double corr = 0.0;
     {
       // l' w-terms and w l'-terms summed separately (one fused multiply-add per
       // product, four independent chains each)
       double p0 = 0.0, p1 = 0.0, p2 = 0.0, p3 = 0.0, m0 = 0.0, m1 = 0.0, m2 = 0.0, m3 = 0.0;
-      const int jr = (j + 15) & ~15;
-      for (int q = 0; q < jr; q += 16) {
-        double2 a[16], c[16];
+      constexpr int GW = NP < 16 ? NP : 16;
+      const int jr = (j + GW - 1) / GW * GW;
+      for (int q = 0; q < jr; q += GW) {
+        double2 a[GW], c[GW];
         const double2* cb = &sm.coef[q];
 #pragma unroll
-        for (int t = 0; t < 16; ++t) {
+        for (int t = 0; t < GW; ++t) {
           a[t] = sm.LW[q + t][lane];
           c[t] = cb[t];
         }
 #pragma unroll
-        for (int t = 0; t < 16; t += 4) {
+        for (int t = 0; t < GW; t += 4) {
           p0 = fma(a[t].x, c[t].y, p0);
           m0 = fma(a[t].y, c[t].x, m0);
           p1 = fma(a[t + 1].x, c[t + 1].y, p1);
@@ -518,6 +524,7 @@ __global__ void __launch_bounds__(kPanelThreads) panel_pf_kernel(PanelParams P) 
           ok &= !need | ((tag16_of(w[q][0]) == t16) & (tag16_of(w[q][1]) == t16));
         }
         if (__all(ok)) break;
+        poll_refresh(it);
         if ((it & 31) == 0) {
           const uint64_t now = wall_clock64();
           if (it == 0) t0 = now;
@@ -629,6 +636,7 @@ __global__ void __launch_bounds__(kPanelThreads) panel_pf_kernel(PanelParams P) 
                         (!hasB | ((tag_of(xb0) == tB) & (tag_of(xb1) == tB) & (tag_of(yb0) == tB) &
                                   (tag_of(yb1) == tB)));
         if (__all(ok)) break;
+        poll_refresh(it);
         if ((it & 31) == 0) {
           const uint64_t now = wall_clock64();
           if (it == 0) t0 = now;
@@ -741,37 +749,33 @@ int launch_panel_t(const PanelParams& p, hipStream_t s) {
 int launch_panel(const PanelParams& p, hipStream_t s) {
   if (p.G > kMaxG || p.S > 64 || p.n >= (1 << 24)) return SKF_ENOTIMPL;
   const int nq = (p.G + 63) / 64;
-  if (p.nb == 128) {
-    if (nq <= 1) return launch_panel_t<128, 1>(p, s);
-    if (nq <= 2) return launch_panel_t<128, 2>(p, s);
-    if (nq <= 4) return launch_panel_t<128, 4>(p, s);
-    return launch_panel_t<128, 8>(p, s);
+  switch (p.nb) {
+    case 128: return nq <= 1 ? launch_panel_t<128, 1>(p, s) : nq <= 2 ? launch_panel_t<128, 2>(p, s)
+                     : nq <= 4 ? launch_panel_t<128, 4>(p, s) : launch_panel_t<128, 8>(p, s);
+    case 64: return nq <= 1 ? launch_panel_t<64, 1>(p, s) : nq <= 2 ? launch_panel_t<64, 2>(p, s)
+                    : nq <= 4 ? launch_panel_t<64, 4>(p, s) : nq <= 8 ? launch_panel_t<64, 8>(p, s) : launch_panel_t<64, 16>(p, s);
+    case 32: return nq <= 2 ? launch_panel_t<32, 2>(p, s) : nq <= 8 ? launch_panel_t<32, 8>(p, s)
+                    : nq <= 16 ? launch_panel_t<32, 16>(p, s) : launch_panel_t<32, 32>(p, s);
+    case 16: return nq <= 2 ? launch_panel_t<16, 2>(p, s) : nq <= 8 ? launch_panel_t<16, 8>(p, s)
+                    : nq <= 16 ? launch_panel_t<16, 16>(p, s) : launch_panel_t<16, 32>(p, s);
+    default: return SKF_ENOTIMPL;
   }
-  if (p.nb == 64) {
-    if (nq <= 1) return launch_panel_t<64, 1>(p, s);
-    if (nq <= 2) return launch_panel_t<64, 2>(p, s);
-    if (nq <= 4) return launch_panel_t<64, 4>(p, s);
-    return launch_panel_t<64, 8>(p, s);
-  }
-  return SKF_ENOTIMPL;
 }
 
 int launch_panel_pf(const PanelParams& p, hipStream_t s) {
   if (p.G > kMaxG || p.S > 64 || p.n >= (1 << 24) || !p.front) return SKF_ENOTIMPL;
   const int nq = (p.G + 63) / 64;
-  if (p.nb == 128) {
-    if (nq <= 1) return launch_panel_pf_t<128, 1>(p, s);
-    if (nq <= 2) return launch_panel_pf_t<128, 2>(p, s);
-    if (nq <= 4) return launch_panel_pf_t<128, 4>(p, s);
-    return launch_panel_pf_t<128, 8>(p, s);
+  switch (p.nb) {
+    case 128: return nq <= 1 ? launch_panel_pf_t<128, 1>(p, s) : nq <= 2 ? launch_panel_pf_t<128, 2>(p, s)
+                     : nq <= 4 ? launch_panel_pf_t<128, 4>(p, s) : launch_panel_pf_t<128, 8>(p, s);
+    case 64: return nq <= 1 ? launch_panel_pf_t<64, 1>(p, s) : nq <= 2 ? launch_panel_pf_t<64, 2>(p, s)
+                    : nq <= 4 ? launch_panel_pf_t<64, 4>(p, s) : nq <= 8 ? launch_panel_pf_t<64, 8>(p, s) : launch_panel_pf_t<64, 16>(p, s);
+    case 32: return nq <= 2 ? launch_panel_pf_t<32, 2>(p, s) : nq <= 8 ? launch_panel_pf_t<32, 8>(p, s)
+                    : nq <= 16 ? launch_panel_pf_t<32, 16>(p, s) : launch_panel_pf_t<32, 32>(p, s);
+    case 16: return nq <= 2 ? launch_panel_pf_t<16, 2>(p, s) : nq <= 8 ? launch_panel_pf_t<16, 8>(p, s)
+                    : nq <= 16 ? launch_panel_pf_t<16, 16>(p, s) : launch_panel_pf_t<16, 32>(p, s);
+    default: return SKF_ENOTIMPL;
   }
-  if (p.nb == 64) {
-    if (nq <= 1) return launch_panel_pf_t<64, 1>(p, s);
-    if (nq <= 2) return launch_panel_pf_t<64, 2>(p, s);
-    if (nq <= 4) return launch_panel_pf_t<64, 4>(p, s);
-    return launch_panel_pf_t<64, 8>(p, s);
-  }
-  return SKF_ENOTIMPL;
 }
 
 size_t panel_record_words(int G) { return (size_t)2 * G * kRecCopies * (kRecStride + 2); }
@@ -779,6 +783,33 @@ size_t panel_record_words(int G) { return (size_t)2 * G * kRecCopies * (kRecStri
 size_t panel_mirror_words(int G, int nb) { return (size_t)G * 64 * (nb / 2) * 4; }
 
 int panel_slots() { return 64; }
+
+// Panel workgroups that can be resident on one CU at once for width nb (the
+// full or the Pfaffian-only panel), from the occupancy of its largest
+// record-pass instantiation (LDS, registers and wave slots); cached.
+int panel_wgs_per_cu(int nb, bool pf) {
+  static int cache[2][5] = {{0}};
+  const int w = nb == 128 ? 0 : nb == 64 ? 1 : nb == 32 ? 2 : nb == 16 ? 3 : 4;
+  if (w == 4) return 0;
+  int& c = cache[pf ? 1 : 0][w];
+  if (c) return c;
+  const void* k = nullptr;
+  switch (w) {
+    case 0: k = pf ? (const void*)panel_pf_kernel<128, 8> : (const void*)panel_kernel<128, 8>; break;
+    case 1: k = pf ? (const void*)panel_pf_kernel<64, 16> : (const void*)panel_kernel<64, 16>; break;
+    case 2: k = pf ? (const void*)panel_pf_kernel<32, 32> : (const void*)panel_kernel<32, 32>; break;
+    default: k = pf ? (const void*)panel_pf_kernel<16, 32> : (const void*)panel_kernel<16, 32>; break;
+  }
+  int b = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&b, k, kPanelThreads, 0) != hipSuccess || b < 1) {
+    // no device to ask (host-only use of the planner): the LDS bound alone
+    (void)hipGetLastError();
+    const size_t lds = pf ? sizeof(PanelPfSmem<128>) * nb / 128 : sizeof(PanelSmem<128>) * nb / 128;
+    b = (int)std::max<size_t>(1, (size_t)163840 / lds);
+  }
+  c = b;
+  return c;
+}
 
 size_t panel_scratch_doubles(int, int) { return 0; }
 

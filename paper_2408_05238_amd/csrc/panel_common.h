@@ -26,7 +26,7 @@ constexpr int kRecCopies = 8;
 constexpr uint32_t kFlagNonFinite = 1u << 30;
 constexpr uint32_t kFlagNoCand = 1u << 31;
 constexpr uint64_t kLow47 = (1ull << 47) - 1;
-constexpr int kMaxG = 512;    // workgroups of one panel launch
+constexpr int kMaxG = 2048;   // workgroups of one panel launch
 constexpr uint32_t kNoCand = 0xFFFFFFFFu;
 
 

@@ -39,6 +39,18 @@ const DeviceInfo& device_info();
 
 inline size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
 
+// Cross-workgroup words are polled with relaxed device-scope loads.  Those are
+// not bound to observe a store from another XCD within any time: a reader's
+// cached copy of the line can keep answering (measured: with a fourth panel
+// workgroup on some CUs, a record stayed invisible to a third of the readers for
+// the full two-second wait bound).  Every eighth polling round therefore issues
+// a device-scope acquire fence, which invalidates the reader's non-coherent
+// cache lines, so a polled word is at most eight rounds stale; the common case,
+// where the word lands within a few rounds, pays nothing.
+__device__ inline void poll_refresh(int it) {
+  if ((it & 7) == 7) __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+}
+
 // Tuning table (tune.hip)
 int tune_lookup(int param, int64_t n);
 int tune_set(int param, int64_t lo, int64_t hi, int value);
@@ -111,6 +123,7 @@ struct PanelParams {
 int launch_panel(const PanelParams& p, hipStream_t s);
 int launch_panel_pf(const PanelParams& p, hipStream_t s);
 int panel_slots();
+int panel_wgs_per_cu(int nb, bool pf);
 size_t panel_record_words(int G);
 size_t panel_mirror_words(int G, int nb);
 size_t panel_scratch_doubles(int G, int nb);
@@ -134,7 +147,7 @@ struct LtltWork {
 };
 
 int ltlt_plan_nb(int64_t n);
-int ltlt_panel_grid(int64_t n, int nb, int* G, int* S);
+int ltlt_panel_grid(int64_t m, int nb, int* G, int* S, bool pf);
 size_t ltlt_workspace_bytes(int64_t n, int prec);
 LtltWork ltlt_carve(void* work, int64_t n, int prec);
 

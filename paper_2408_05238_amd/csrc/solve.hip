@@ -337,6 +337,7 @@ __global__ void __launch_bounds__(NT) trsv_kernel(int64_t n, const double* __res
 #pragma unroll
         for (int q = 0; q < 4; ++q) ok &= ((uint32_t)(w[q][0] >> 32) == tag) & ((uint32_t)(w[q][1] >> 32) == tag);
         if (ok) break;
+        poll_refresh(it);
         if ((it & 31) == 0) {
           const uint64_t now = wall_clock64();
           if (it == 0) t0 = now;

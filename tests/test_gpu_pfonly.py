@@ -65,7 +65,8 @@ def test_pfonly_parity(skf, oracle_mod, gen, n):
 
 
 @pytest.mark.parametrize("n,nb", [(300, "64"), (778, "64"), (2048, "64"), (4500, "64"), (300, "128"),
-                                  (2048, "128"), (4096, "128")])
+                                  (2048, "128"), (4096, "128"), (300, "32"), (2048, "32"), (778, "16"),
+                                  (2048, "16")])
 def test_pfonly_parity_nb(skf, oracle_mod, gen, n, nb, monkeypatch):
     """Each panel width forced, whatever the tuning table picks for n."""
     monkeypatch.setenv("SKF_NB", nb)
