@@ -114,10 +114,10 @@ size_t skf_ltlt_workspace(skf_int n, int prec);
  *   prec   SKF_PREC_F64 or SKF_PREC_F32_TRAILING
  *   work   device workspace of at least skf_ltlt_workspace(n, prec) bytes
  *   dinfo  device int or NULL (see status codes)
- * Orders: a panel runs one workgroup per 64 rows, all resident at once, so the
- * panel width is the widest that fits (on 256 CUs: 128 up to n = 16385, 64 up
- * to 49153, 32 or 16 up to 65537); beyond, SKF_ENOTIMPL.  skf_pfonly: 128 up to
- * 32769, 64, 32 or 16 up to 65537.
+ * Orders: a panel runs one workgroup per 64 rows, all resident at once (at most
+ * six per CU), so the panel width is the widest that fits (on 256 CUs: 128 up
+ * to n = 16385, 64 up to 49153, 32 or 16 up to 98305); beyond, SKF_ENOTIMPL.
+ * skf_pfonly: 128 up to 32769, 64 up to 65537, 32 or 16 up to 98305.
  */
 int skf_ltlt(skf_int n, double* A, skf_int lda, int32_t* ipiv, double* T, int prec,
              void* work, size_t lwork, int* dinfo, void* stream);

@@ -131,71 +131,81 @@ __global__ void __launch_bounds__(kPanelThreads) panel_kernel(PanelParams P) {
     }
 
     // (C) every workgroup's record (lane t reads records t, t+64, ...) -> global pivot.
-    // Each round reloads both words of every record (addresses always valid;
-    // lanes past G read record 0 and ignore it) until all carry this step's tag.
+    // Each round reloads both words of every record of a block (addresses always
+    // valid; lanes past G read record 0 and ignore it) until all carry this step's
+    // tag.  One block holds up to 16 records per lane, so up to 1024 workgroups
+    // are read in one round; beyond, the blocks are waited for one after the other
+    // (a record with this step's tag stays until every workgroup has read it).
     double gv = -1.0, gc = 0.0;
     uint32_t gp = kNoCand, gslot = 0;
     int gs = -1;
     bool bad = false, tout = false;
     {
-      uint64_t w[NQ][2];
-      const uint64_t* rp[NQ];
+      constexpr int QB = NQ < 16 ? NQ : 16;
+      const int nblk = (G + 64 * QB - 1) / (64 * QB);
+#pragma unroll 1
+      for (int b = 0; b < nblk && !tout; ++b) {
+        const int rb = 64 * QB * b;
+        uint64_t w[QB][2];
+        const uint64_t* rp[QB];
 #pragma unroll
-      for (int q = 0; q < NQ; ++q) {
-        const int rr = lane + 64 * q;
-        rp[q] = recs + (size_t)(rr < G ? rr : 0) * kRecStride;
-      }
-      auto load_all = [&]() {
-#pragma unroll
-        for (int q = 0; q < NQ; ++q) {
-          w[q][0] = ld_word(rp[q]);
-          w[q][1] = ld_word(rp[q] + 1);
+        for (int q = 0; q < QB; ++q) {
+          const int rr = rb + lane + 64 * q;
+          rp[q] = recs + (size_t)(rr < G ? rr : 0) * kRecStride;
         }
-      };
-      load_all();
-      uint64_t t0 = 0;
-      for (int it = 0;; ++it) {
-        bool ok = true;
+        auto load_all = [&]() {
 #pragma unroll
-        for (int q = 0; q < NQ; ++q) {
-          const bool need = lane + 64 * q < G;
-          ok &= !need | ((tag16_of(w[q][0]) == t16) & (tag16_of(w[q][1]) == t16));  // no short-circuit branches
-        }
-        if (__all(ok)) break;
-        poll_refresh(it);
-        if ((it & 31) == 0) {
-          const uint64_t now = wall_clock64();
-          if (it == 0) t0 = now;
-          else if (now - t0 > kWaitTicks) {
-            tout = true;
-            break;
+          for (int q = 0; q < QB; ++q) {
+            w[q][0] = ld_word(rp[q]);
+            w[q][1] = ld_word(rp[q] + 1);
           }
-        }
+        };
         load_all();
-      }
+        uint64_t t0 = 0;
+        for (int it = 0;; ++it) {
+          bool ok = true;
 #pragma unroll
-      for (int q = 0; q < NQ; ++q) {
-        landed(w[q][0]);
-        landed(w[q][1]);
-      }
+          for (int q = 0; q < QB; ++q) {
+            const bool need = rb + lane + 64 * q < G;
+            ok &= !need | ((tag16_of(w[q][0]) == t16) & (tag16_of(w[q][1]) == t16));  // no short-circuit branches
+          }
+          if (__all(ok)) break;
+          poll_refresh<(NQ > 16)>(it);
+          if ((it & 31) == 0) {
+            const uint64_t now = wall_clock64();
+            if (it == 0) t0 = now;
+            else if (now - t0 > kWaitTicks) {
+              tout = true;
+              break;
+            }
+          }
+          load_all();
+        }
 #pragma unroll
-      for (int q = 0; q < NQ; ++q) {
-        const int rr = lane + 64 * q;
-        const uint32_t meta = (uint32_t)(w[q][0] >> 16);
-        const bool use = rr < G && !tout;
-        bad |= use && (meta & kFlagNonFinite);
-        if (use && !(meta & (kFlagNonFinite | kFlagNoCand))) {
-          const uint64_t mag = ((w[q][0] & 0xFFFFull) << 47) | (w[q][1] & kLow47);
-          const double a = __longlong_as_double((long long)mag);
-          const uint32_t ps = meta & 0xFFFFFFu;
-          if (better(a, ps, gv, gp)) {
-            gv = a;
-            gc = __longlong_as_double((long long)(mag | (((w[q][1] >> 47) & 1ull) << 63)));
-            gp = ps;
-            gs = rr;
-            gslot = meta >> 24 & 63u;
+        for (int q = 0; q < QB; ++q) {
+          landed(w[q][0]);
+          landed(w[q][1]);
+        }
+#pragma unroll
+        for (int q = 0; q < QB; ++q) {
+          const int rr = rb + lane + 64 * q;
+          const uint32_t meta = (uint32_t)(w[q][0] >> 16);
+          const bool use = rr < G && !tout;
+          bad |= use && (meta & kFlagNonFinite);
+          if (use && !(meta & (kFlagNonFinite | kFlagNoCand))) {
+            const uint64_t mag = ((w[q][0] & 0xFFFFull) << 47) | (w[q][1] & kLow47);
+            const double a = __longlong_as_double((long long)mag);
+            const uint32_t ps = meta & 0xFFFFFFu;
+            if (better(a, ps, gv, gp)) {
+              gv = a;
+              gc = __longlong_as_double((long long)(mag | (((w[q][1] >> 47) & 1ull) << 63)));
+              gp = ps;
+              gs = rr;
+              gslot = meta >> 24 & 63u;
+            }
           }
         }
+        tout = __any(tout);
       }
     }
     tout = __any(tout);
@@ -273,7 +283,7 @@ __global__ void __launch_bounds__(kPanelThreads) panel_kernel(PanelParams P) {
                         (!hasB | ((tag_of(b0) == tB) & (tag_of(b1) == tB))) & (tag_of(z0) == tag) &
                         (tag_of(z1) == tag);
         if (__all(ok)) break;
-        poll_refresh(it);
+        poll_refresh<(NQ > 16)>(it);
         if ((it & 31) == 0) {
           const uint64_t now = wall_clock64();
           if (it == 0) t0 = now;
@@ -486,84 +496,93 @@ __global__ void __launch_bounds__(kPanelThreads) panel_pf_kernel(PanelParams P) 
       }
     }
 
-    // (C) records -> global pivot; front entries (every lane reads the same words)
+    // (C) records -> global pivot; front entries (every lane reads the same words).
+    // Records are read in blocks of up to 16 per lane as in the full panel; the
+    // front entries are polled with every block.
     double gv = -1.0, gc = 0.0;
     uint32_t gp = kNoCand, gslot = 0;
     int gs = -1;
     bool bad = false, tout = false;
     uint64_t f0a = 0, f0b = 0, f0c = 0, f1a = 0, f1b = 0, f1c = 0;
     {
-      uint64_t w[NQ][2];
-      const uint64_t* rp[NQ];
+      constexpr int QB = NQ < 16 ? NQ : 16;
+      const int nblk = (G + 64 * QB - 1) / (64 * QB);
+#pragma unroll 1
+      for (int b = 0; b < nblk && !tout; ++b) {
+        const int rb = 64 * QB * b;
+        uint64_t w[QB][2];
+        const uint64_t* rp[QB];
 #pragma unroll
-      for (int q = 0; q < NQ; ++q) {
-        const int rr = lane + 64 * q;
-        rp[q] = recs + (size_t)(rr < G ? rr : 0) * kRecStride;
-      }
-      auto load_recs = [&]() {
-#pragma unroll
-        for (int q = 0; q < NQ; ++q) {
-          w[q][0] = ld_word(rp[q]);
-          w[q][1] = ld_word(rp[q] + 1);
+        for (int q = 0; q < QB; ++q) {
+          const int rr = rb + lane + 64 * q;
+          rp[q] = recs + (size_t)(rr < G ? rr : 0) * kRecStride;
         }
-        f0a = ld_word(front);
-        f0b = ld_word(front + 1);
-        f0c = ld_word(front + 2);
-        f1a = ld_word(front + 4);
-        f1b = ld_word(front + 5);
-        f1c = ld_word(front + 6);
-      };
-      load_recs();
-      uint64_t t0 = 0;
-      for (int it = 0;; ++it) {
-        bool ok = (tag_of(f0a) == tag) & (tag_of(f0b) == tag) & (tag_of(f0c) == tag);
-        ok &= last | ((tag_of(f1a) == tag) & (tag_of(f1b) == tag) & (tag_of(f1c) == tag));
+        auto load_recs = [&]() {
 #pragma unroll
-        for (int q = 0; q < NQ; ++q) {
-          const bool need = lane + 64 * q < G;
-          ok &= !need | ((tag16_of(w[q][0]) == t16) & (tag16_of(w[q][1]) == t16));
-        }
-        if (__all(ok)) break;
-        poll_refresh(it);
-        if ((it & 31) == 0) {
-          const uint64_t now = wall_clock64();
-          if (it == 0) t0 = now;
-          else if (now - t0 > kWaitTicks) {
-            tout = true;
-            break;
+          for (int q = 0; q < QB; ++q) {
+            w[q][0] = ld_word(rp[q]);
+            w[q][1] = ld_word(rp[q] + 1);
           }
-        }
+          f0a = ld_word(front);
+          f0b = ld_word(front + 1);
+          f0c = ld_word(front + 2);
+          f1a = ld_word(front + 4);
+          f1b = ld_word(front + 5);
+          f1c = ld_word(front + 6);
+        };
         load_recs();
-      }
+        uint64_t t0 = 0;
+        for (int it = 0;; ++it) {
+          bool ok = (tag_of(f0a) == tag) & (tag_of(f0b) == tag) & (tag_of(f0c) == tag);
+          ok &= last | ((tag_of(f1a) == tag) & (tag_of(f1b) == tag) & (tag_of(f1c) == tag));
 #pragma unroll
-      for (int q = 0; q < NQ; ++q) {
-        landed(w[q][0]);
-        landed(w[q][1]);
-      }
-      landed(f0a);
-      landed(f0b);
-      landed(f0c);
-      landed(f1a);
-      landed(f1b);
-      landed(f1c);
+          for (int q = 0; q < QB; ++q) {
+            const bool need = rb + lane + 64 * q < G;
+            ok &= !need | ((tag16_of(w[q][0]) == t16) & (tag16_of(w[q][1]) == t16));
+          }
+          if (__all(ok)) break;
+          poll_refresh<(NQ > 16)>(it);
+          if ((it & 31) == 0) {
+            const uint64_t now = wall_clock64();
+            if (it == 0) t0 = now;
+            else if (now - t0 > kWaitTicks) {
+              tout = true;
+              break;
+            }
+          }
+          load_recs();
+        }
 #pragma unroll
-      for (int q = 0; q < NQ; ++q) {
-        const int rr = lane + 64 * q;
-        const uint32_t meta = (uint32_t)(w[q][0] >> 16);
-        const bool use = rr < G && !tout;
-        bad |= use && (meta & kFlagNonFinite);
-        if (use && !(meta & (kFlagNonFinite | kFlagNoCand))) {
-          const uint64_t mag = ((w[q][0] & 0xFFFFull) << 47) | (w[q][1] & kLow47);
-          const double a = __longlong_as_double((long long)mag);
-          const uint32_t ps = meta & 0xFFFFFFu;
-          if (better(a, ps, gv, gp)) {
-            gv = a;
-            gc = __longlong_as_double((long long)(mag | (((w[q][1] >> 47) & 1ull) << 63)));
-            gp = ps;
-            gs = rr;
-            gslot = meta >> 24 & 63u;
+        for (int q = 0; q < QB; ++q) {
+          landed(w[q][0]);
+          landed(w[q][1]);
+        }
+        landed(f0a);
+        landed(f0b);
+        landed(f0c);
+        landed(f1a);
+        landed(f1b);
+        landed(f1c);
+#pragma unroll
+        for (int q = 0; q < QB; ++q) {
+          const int rr = rb + lane + 64 * q;
+          const uint32_t meta = (uint32_t)(w[q][0] >> 16);
+          const bool use = rr < G && !tout;
+          bad |= use && (meta & kFlagNonFinite);
+          if (use && !(meta & (kFlagNonFinite | kFlagNoCand))) {
+            const uint64_t mag = ((w[q][0] & 0xFFFFull) << 47) | (w[q][1] & kLow47);
+            const double a = __longlong_as_double((long long)mag);
+            const uint32_t ps = meta & 0xFFFFFFu;
+            if (better(a, ps, gv, gp)) {
+              gv = a;
+              gc = __longlong_as_double((long long)(mag | (((w[q][1] >> 47) & 1ull) << 63)));
+              gp = ps;
+              gs = rr;
+              gslot = meta >> 24 & 63u;
+            }
           }
         }
+        tout = __any(tout);
       }
     }
     tout = __any(tout);
@@ -636,7 +655,7 @@ __global__ void __launch_bounds__(kPanelThreads) panel_pf_kernel(PanelParams P) 
                         (!hasB | ((tag_of(xb0) == tB) & (tag_of(xb1) == tB) & (tag_of(yb0) == tB) &
                                   (tag_of(yb1) == tB)));
         if (__all(ok)) break;
-        poll_refresh(it);
+        poll_refresh<(NQ > 16)>(it);
         if ((it & 31) == 0) {
           const uint64_t now = wall_clock64();
           if (it == 0) t0 = now;
@@ -778,15 +797,24 @@ int launch_panel_pf(const PanelParams& p, hipStream_t s) {
   }
 }
 
+// At most six panel workgroups per CU: measured with every polling round fenced,
+// 1536 workgroups (six per CU) exchange their records correctly, while with
+// 2032 (eight per CU) some readers still never saw records already written and
+// the bounded wait ended in SKF_ETIMEOUT.
+constexpr int kMaxPanelPerCu = 6;
+
 size_t panel_record_words(int G) { return (size_t)2 * G * kRecCopies * (kRecStride + 2); }
 
 size_t panel_mirror_words(int G, int nb) { return (size_t)G * 64 * (nb / 2) * 4; }
 
 int panel_slots() { return 64; }
 
-// Panel workgroups that can be resident on one CU at once for width nb (the
-// full or the Pfaffian-only panel), from the occupancy of its largest
-// record-pass instantiation (LDS, registers and wave slots); cached.
+// Panel workgroups that may share one CU for width nb (the full or the
+// Pfaffian-only panel): the occupancy of its largest record-pass instantiation
+// (registers and wave slots), capped by the LDS it holds rounded up to 1 KB per
+// workgroup (the occupancy query counts the exact byte size, and one workgroup
+// more than the rounded bound, 13 of 12416 bytes on a 160 KB CU, was measured
+// not to fit), and by kMaxPanelPerCu.  Cached per width.
 int panel_wgs_per_cu(int nb, bool pf) {
   static int cache[2][5] = {{0}};
   const int w = nb == 128 ? 0 : nb == 64 ? 1 : nb == 32 ? 2 : nb == 16 ? 3 : 4;
@@ -800,14 +828,21 @@ int panel_wgs_per_cu(int nb, bool pf) {
     case 2: k = pf ? (const void*)panel_pf_kernel<32, 32> : (const void*)panel_kernel<32, 32>; break;
     default: k = pf ? (const void*)panel_pf_kernel<16, 32> : (const void*)panel_kernel<16, 32>; break;
   }
+  const size_t lds = pf ? sizeof(PanelPfSmem<128>) * nb / 128 : sizeof(PanelSmem<128>) * nb / 128;
+  size_t lds_cu = 163840;
+  int dev = 0, v = 0;
+  if (hipGetDevice(&dev) == hipSuccess &&
+      hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerMultiprocessor, dev) == hipSuccess && v > 0)
+    lds_cu = (size_t)v;
+  (void)hipGetLastError();
+  const int by_lds = (int)std::max<size_t>(1, lds_cu / align_up(lds, 1024));
   int b = 0;
   if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&b, k, kPanelThreads, 0) != hipSuccess || b < 1) {
     // no device to ask (host-only use of the planner): the LDS bound alone
     (void)hipGetLastError();
-    const size_t lds = pf ? sizeof(PanelPfSmem<128>) * nb / 128 : sizeof(PanelSmem<128>) * nb / 128;
-    b = (int)std::max<size_t>(1, (size_t)163840 / lds);
+    b = by_lds;
   }
-  c = b;
+  c = std::min(std::min(b, by_lds), kMaxPanelPerCu);
   return c;
 }
 

@@ -43,12 +43,15 @@ inline size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
 // not bound to observe a store from another XCD within any time: a reader's
 // cached copy of the line can keep answering (measured: with a fourth panel
 // workgroup on some CUs, a record stayed invisible to a third of the readers for
-// the full two-second wait bound).  Every eighth polling round therefore issues
-// a device-scope acquire fence, which invalidates the reader's non-coherent
-// cache lines, so a polled word is at most eight rounds stale; the common case,
-// where the word lands within a few rounds, pays nothing.
+// the full two-second wait bound).  A device-scope acquire fence, which
+// invalidates the reader's non-coherent cache lines, ends that.  With up to four
+// polling workgroups per CU one fence every eighth round was enough (measured up
+// to 1094 panel workgroups) and the common case, where the word lands within a
+// few rounds, pays nothing; with six per CU stale lines outlived that cadence, so
+// the widest grids (kEveryRound) fence before every reload.
+template <bool kEveryRound = false>
 __device__ inline void poll_refresh(int it) {
-  if ((it & 7) == 7) __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+  if (kEveryRound || (it & 7) == 7) __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
 }
 
 // Tuning table (tune.hip)

@@ -33,11 +33,13 @@ def test_builtin_rules_without_table(skf):
     assert skf.tune_get("pfonly_nb", 1000) == 128
     assert skf.tune_get("skr2k_band", 16384) == 8
     # wider orders take the narrower panels (more of their workgroups fit a CU;
-    # here without a device: by LDS alone, 1 / 3 / 6 / 12 per CU on 256 CUs)
+    # here without a device: by LDS alone, 1 / 3 / 6 per CU on 256 CUs, and at
+    # most six per CU for any width)
     assert skf.tune_get("ltlt_nb", 40000) == 64
     assert skf.tune_get("ltlt_nb", 60000) == 32
-    assert skf.tune_get("ltlt_nb", 120000) == 16
-    assert skf.tune_get("ltlt_nb", 140000) == 0       # no width fits
+    assert skf.tune_get("ltlt_nb", 98305) == 32       # 1536 workgroups
+    assert skf.tune_get("ltlt_nb", 98306) == 0        # no width fits
+    assert skf.tune_get("pfonly_nb", 98305) == 32
     assert skf.tune_get("pfonly_nb", 30000) == 128    # the Pfaffian-only panel's LDS fits two per CU
 
 
