@@ -338,12 +338,20 @@ int skf_pfonly_batched(skf_int batch, const skf_int* n_host, double* const* A, c
 int skf_logpf_batched(skf_int batch, const skf_int* n_host, double* const* A, const skf_int* lda_host,
                       double* logabs, int* sign, int* info, void* work, size_t lwork, void* stream);
 
+/* Device workspace (bytes) for skf_solve_batched (host arrays n_host, nrhs_host). */
+size_t skf_solve_batched_workspace(skf_int batch, const skf_int* n_host, const skf_int* nrhs_host);
+
 /*
- * Batched solves with factors from skf_ltlt_batched: B[b] (n_b x nrhs_host[b],
- * ldb_host[b]) overwritten by X[b].  Pointer arrays are device arrays (read back
- * to the host once, synchronously); the solves run in order on `stream` and
- * share the workspace, which must hold skf_solve_workspace of the largest
- * (n_b, nrhs_b).  info[b] (device) as for skf_solve.
+ * Batched solves with factors from skf_ltlt_batched (or skf_ltlt): B[b]
+ * (n_b x nrhs_host[b], ldb_host[b]) overwritten by X[b] = A_b^{-1} B[b], the
+ * same steps as skf_solve.  One launch for every matrix of order <= 1024, one
+ * wave per (matrix, right-hand side); asynchronous on `stream` (the host size
+ * arrays are staged into the workspace).  Matrices of larger order are solved
+ * one after the other by the skf_solve path after a synchronous read-back of
+ * the pointer arrays.  LT, ipiv, T, B: device arrays of device pointers.
+ * info[b] (device) as for skf_solve.  work: skf_solve_batched_workspace bytes
+ * (256-aligned; skf_batched_workspace covers up to 16 right-hand sides).
+ * Returns 0, or an argument error (-1: batch, -2: a pointer or size array).
  */
 int skf_solve_batched(skf_int batch, const skf_int* n_host, double* const* LT, const skf_int* lda_host,
                       int32_t* const* ipiv, double* const* T, const skf_int* nrhs_host,

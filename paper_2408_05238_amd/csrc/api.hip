@@ -103,9 +103,6 @@ void prof_end(hipStream_t s, int cls, double flops) {
   p.pending = nullptr;
 }
 
-size_t solve_workspace_bytes(int64_t n, int64_t nrhs);
-int run_solve(int64_t n, int64_t nrhs, const double* LT, int64_t lda, const int32_t* ipiv, const double* T,
-              double* B, int64_t ldb, void* work, size_t lwork, int* dinfo, hipStream_t s);
 size_t batched_workspace_bytes(int64_t batch);
 int batched_max_n();
 int run_batched(int64_t batch, const int64_t* n_host, double* const* A, const int64_t* lda_host,
@@ -413,10 +410,13 @@ int skf_solve_refine(skf_int n, skf_int nrhs, const double* A0, skf_int lda0, co
 
 size_t skf_batched_workspace(skf_int batch, const skf_int* n_host) {
   if (batch < 0) return 0;
-  size_t solve_max = 0;
-  for (skf_int b = 0; b < batch && n_host; ++b)
-    solve_max = std::max(solve_max, skf_solve_workspace(n_host[b], 16));
-  return align_up(batched_workspace_bytes(batch), 256) + solve_max;
+  size_t solve = 0;
+  if (n_host && batch > 0) {
+    // the factors' batched solve with up to 16 right-hand sides each
+    std::vector<skf_int> nr((size_t)batch, 16);
+    solve = solve_batched_workspace_bytes(batch, n_host, nr.data());
+  }
+  return std::max(align_up(batched_workspace_bytes(batch), 256), solve);
 }
 
 static int check_batched(skf_int batch, const skf_int* n_host, double* const* A, const skf_int* lda_host,
@@ -461,36 +461,25 @@ int skf_logpf_batched(skf_int batch, const skf_int* n_host, double* const* A, co
                      (hipStream_t)stream);
 }
 
+size_t skf_solve_batched_workspace(skf_int batch, const skf_int* n_host, const skf_int* nrhs_host) {
+  if (batch < 0 || (batch > 0 && (!n_host || !nrhs_host))) return 0;
+  return solve_batched_workspace_bytes(batch, n_host, nrhs_host);
+}
+
 int skf_solve_batched(skf_int batch, const skf_int* n_host, double* const* LT, const skf_int* lda_host,
                       int32_t* const* ipiv, double* const* T, const skf_int* nrhs_host, double* const* B,
                       const skf_int* ldb_host, int* info, void* work, size_t lwork, void* stream) {
   if (batch < 0) return -1;
   if (batch == 0) return 0;
   if (!n_host || !LT || !lda_host || !ipiv || !T || !nrhs_host || !B || !ldb_host || !info) return -2;
-  hipStream_t s = (hipStream_t)stream;
-  // the per-matrix device pointers are needed on the host to enqueue each solve
-  std::vector<double*> hLT((size_t)batch), hT((size_t)batch), hB((size_t)batch);
-  std::vector<int32_t*> hP((size_t)batch);
-  SKF_CHECK(hipMemcpyAsync(hLT.data(), LT, sizeof(double*) * batch, hipMemcpyDeviceToHost, s), "ptrs");
-  SKF_CHECK(hipMemcpyAsync(hT.data(), T, sizeof(double*) * batch, hipMemcpyDeviceToHost, s), "ptrs");
-  SKF_CHECK(hipMemcpyAsync(hB.data(), B, sizeof(double*) * batch, hipMemcpyDeviceToHost, s), "ptrs");
-  SKF_CHECK(hipMemcpyAsync(hP.data(), ipiv, sizeof(int32_t*) * batch, hipMemcpyDeviceToHost, s), "ptrs");
-  SKF_CHECK(hipStreamSynchronize(s), "ptrs");
-  size_t need = 0;
-  for (skf_int b = 0; b < batch; ++b) {
+  for (skf_int b = 0; b < batch; ++b)
     if (n_host[b] < 0 || nrhs_host[b] < 0 || lda_host[b] < std::max<skf_int>(1, n_host[b]) ||
         ldb_host[b] < std::max<skf_int>(1, n_host[b]))
       return -2;
-    need = std::max(need, solve_workspace_bytes(n_host[b], nrhs_host[b]));
-  }
-  if (!work || ((uintptr_t)work & 255) || lwork < need) return SKF_EWORK;
-  for (skf_int b = 0; b < batch; ++b) {
-    // solves share the workspace; they are ordered on the stream
-    int rc = run_solve(n_host[b], nrhs_host[b], hLT[b], lda_host[b], hP[b], hT[b], hB[b], ldb_host[b], work, need,
-                       info + b, s);
-    if (rc) return rc;
-  }
-  return 0;
+  if (!work || ((uintptr_t)work & 255)) return SKF_EWORK;
+  return run_solve_batched(batch, n_host, (const double* const*)LT, lda_host, (const int32_t* const*)ipiv,
+                           (const double* const*)T, nrhs_host, B, ldb_host, info, work, lwork,
+                           (hipStream_t)stream);
 }
 
 int skf_profile_enable(int on) {

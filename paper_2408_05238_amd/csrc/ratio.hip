@@ -19,9 +19,6 @@
 
 namespace skf {
 
-size_t solve_workspace_bytes(int64_t n, int64_t nrhs);
-int run_solve(int64_t n, int64_t nrhs, const double* LT, int64_t lda, const int32_t* ipiv, const double* T,
-              double* B, int64_t ldb, void* work, size_t lwork, int* dinfo, hipStream_t s);
 
 namespace {
 

@@ -61,6 +61,18 @@ void tune_clear();
 int pfonly_plan_nb(int64_t n);
 int skr2k_band(int64_t m);
 
+// Solve with the factors (solve.hip): workspace bytes, and the solve in place over B.
+size_t solve_workspace_bytes(int64_t n, int64_t nrhs);
+int run_solve(int64_t n, int64_t nrhs, const double* LT, int64_t lda, const int32_t* ipiv, const double* T,
+              double* B, int64_t ldb, void* work, size_t lwork, int* dinfo, hipStream_t s);
+// Batched solves in one launch (solve_batched.hip); orders above 1024 fall back
+// to run_solve per matrix.
+size_t solve_batched_workspace_bytes(int64_t batch, const int64_t* n_host, const int64_t* nrhs_host);
+int run_solve_batched(int64_t batch, const int64_t* n_host, const double* const* LT, const int64_t* lda_host,
+                      const int32_t* const* ipiv, const double* const* T, const int64_t* nrhs_host,
+                      double* const* B, const int64_t* ldb_host, int* info, void* work, size_t lwork,
+                      hipStream_t s);
+
 // Allocation-free solve (solve.hip): fixed device scratch for n <= kSolveNoAllocMaxN.
 constexpr int64_t kSolveNoAllocMaxN = SKF_SOLVE_NOALLOC_MAX_N;
 size_t solve_noalloc_scratch_bytes();

@@ -34,7 +34,8 @@ EXPORTS = [
     "skf_solve_workspace", "skf_solve", "skf_solve_noalloc", "skf_pf_ratio_workspace", "skf_pf_ratio", "skf_pfonly_c128_workspace",
     "skf_pfonly_c128", "skf_logpf_c128_from_factors", "skf_refine_workspace",
     "skf_solve_refine",
-    "skf_batched_workspace", "skf_ltlt_batched", "skf_pfonly_batched", "skf_logpf_batched", "skf_solve_batched",
+    "skf_batched_workspace", "skf_ltlt_batched", "skf_pfonly_batched", "skf_logpf_batched",
+    "skf_solve_batched_workspace", "skf_solve_batched",
     "skf_profile_enable", "skf_profile_read", "skf_tune_set", "skf_tune_get", "skf_tune_clear",
 ]
 
@@ -91,6 +92,7 @@ def _load():
                 "skf_ltlt_batched": (ci, [i64, vp, vp, vp, vp, vp, vp, vp, vp, vp, sz, vp]),
                 "skf_pfonly_batched": (ci, [i64, vp, vp, vp, vp, vp, vp, vp, vp, vp, sz, vp]),
                 "skf_logpf_batched": (ci, [i64, vp, vp, vp, vp, vp, vp, vp, sz, vp]),
+                "skf_solve_batched_workspace": (sz, [i64, vp, vp]),
                 "skf_solve_batched": (ci, [i64, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, sz, vp]),
                 "skf_tune_set": (ci, [ci, i64, i64, ci]),
                 "skf_tune_get": (ci, [ci, i64]),
@@ -580,8 +582,9 @@ def solve_batched(LTs, ipivs, Ts, Bs, work=None, stream=None):
     ldb_h = np.array([_ld(b) if b.dim() == 2 and b.shape[0] > 0 else max(int(n), 1) for b, n in zip(Bs, n_h)],
                      dtype=np.int64)
     if work is None:
-        need = max([solve_workspace(int(n), int(r)) for n, r in zip(n_h, nr_h)] or [256])
-        work = workspace(need, dev)
+        need = int(_load().skf_solve_batched_workspace(nb, n_h.ctypes.data_as(ctypes.c_void_p),
+                                                        nr_h.ctypes.data_as(ctypes.c_void_p)))
+        work = workspace(max(need, 256), dev)
     lt_arr = _ptr_array(LTs, dev, stream)
     ip_arr = _ptr_array(ipivs, dev, stream)
     t_arr = _ptr_array(Ts, dev, stream)

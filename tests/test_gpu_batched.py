@@ -70,17 +70,64 @@ def test_batched_logpf_only_and_nonfinite(skf, oracle_mod, gen):
     assert sg[2] == 0 and la[2] == -np.inf
 
 
+SOLVE_NS = [0, 1, 2, 3, 4, 6, 64, 65, 66, 100, 130, 257, 300, 511, 512]
+SOLVE_NRHS = [1, 2, 3, 1, 0, 4, 1, 2, 5, 1, 3, 1, 2, 1, 3]
+
+
 def test_solve_batched(skf, oracle_mod, gen):
-    ns = [64, 100, 2]
+    """One launch over uneven orders and right-hand-side counts: every solution
+    has backward error <= 1e-13 with its matrix and matches the oracle's solve
+    with the same factors; odd orders report n, and the result of a matrix is
+    the same bits alone as in the mix."""
+    import torch
+    ns, nrs = SOLVE_NS, SOLVE_NRHS
     mats_h = [gen.batch_matrix(n, 17, b) for b, n in enumerate(ns)]
     mats = [skf.to_device_colmajor(A) for A in mats_h]
     _, _, _, ipivs, Ts = skf.ltlt_batched(mats)
-    Bs_h = [gen.gaussian(n, 3, 100 + b) for b, n in enumerate(ns)]
+    Bs_h = [gen.gaussian(n, r, 100 + b) for b, (n, r) in enumerate(zip(ns, nrs))]
     Bs = [skf.to_device_colmajor(B) for B in Bs_h]
-    info = skf.solve_batched(mats, ipivs, Ts, Bs)
-    assert _host(info).tolist() == [0, 0, 0]
-    for b in range(3):
-        assert oracle_mod.backward_error(mats_h[b], _host(Bs[b]), Bs_h[b]) <= 1e-13
+    info = _host(skf.solve_batched(mats, ipivs, Ts, Bs)).tolist()
+    assert info == [n if n % 2 else 0 for n in ns]
+    for b, n in enumerate(ns):
+        if n % 2 or n == 0 or nrs[b] == 0:
+            continue
+        X = _host(Bs[b])
+        assert oracle_mod.backward_error(mats_h[b], X, Bs_h[b]) <= 1e-13, (n, b)
+        Xr, inf2 = oracle_mod.solve(_host(mats[b]), _host(ipivs[b]), _host(Ts[b]), Bs_h[b])
+        assert inf2 == 0
+        assert np.abs(X - Xr).max() <= 1e-9 * np.abs(Xr).max() * max(1.0, n / 64), (n, b)
+    # alone vs in the mix: bitwise
+    b = ns.index(300)
+    B1 = skf.to_device_colmajor(Bs_h[b])
+    assert _host(skf.solve_batched([mats[b]], [ipivs[b]], [Ts[b]], [B1])).tolist() == [0]
+    assert np.array_equal(_host(B1), _host(Bs[b]))
+    torch.cuda.synchronize()
+
+
+def test_solve_batched_wide_orders_and_singular(skf, oracle_mod, gen):
+    """Orders above the batched factorization's reach, factored one by one: 700
+    (sixteen rows per lane) stays in the one launch, 1100 takes the single-matrix
+    solve; a zero first row and column gives info 1."""
+    ns = [700, 1100, 40]
+    mats_h = [gen.skew_gaussian(n, 300 + n) for n in ns]
+    mats_h[2][:, 0] = 0.0
+    mats_h[2][0, :] = 0.0
+    mats, ipivs, Ts = [], [], []
+    for A in mats_h:
+        dA = skf.to_device_colmajor(A)
+        ip, T, _ = skf.ltlt(dA)
+        mats.append(dA)
+        ipivs.append(ip)
+        Ts.append(T)
+    Bs_h = [gen.gaussian(n, 2, 700 + n) for n in ns]
+    Bs = [skf.to_device_colmajor(B) for B in Bs_h]
+    info = _host(skf.solve_batched(mats, ipivs, Ts, Bs)).tolist()
+    assert info == [0, 0, 1]
+    for b in range(2):
+        X = _host(Bs[b])
+        assert oracle_mod.backward_error(mats_h[b], X, Bs_h[b]) <= 1e-13, ns[b]
+        Xr, _ = oracle_mod.solve(_host(mats[b]), _host(ipivs[b]), _host(Ts[b]), Bs_h[b])
+        assert np.abs(X - Xr).max() <= 1e-9 * np.abs(Xr).max() * max(1.0, ns[b] / 64), ns[b]
 
 
 def test_batched_repeatable_large_mix(skf, gen):
