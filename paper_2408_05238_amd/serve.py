@@ -16,12 +16,17 @@ compute tokens free up, so work of different requests overlaps on the device
   from resident factors hold no tokens.
 * continuous batching: small Pfaffian requests (n <= 512) waiting together are
   factored by one persistent batched launch.
+* Pfaffian ratios: a "ratio" request asks for Pf(A + U V^T - V U^T) / Pf(A)
+  with U, V of rank r <= 32; it is served from the resident FP64 factors of A
+  (factoring A first when they are not resident), one solve with 2r
+  right-hand sides instead of a factorization of the updated matrix.
 * precision: a request labelled FP32 means an FP32-trailing factorization plus
   iterative refinement to FP64 backward error; refinement corrects solves only,
-  so Pfaffian requests are always taken from FP64 factors (their error is the
-  FP64 path's).  Every result states its error against FP64: the backward error
-  eta of its solution for a solve, the relative log|Pf| bound of the FP64
-  reduction for a Pfaffian.
+  so Pfaffian and ratio requests are always taken from FP64 factors.  Every
+  result states its error against FP64: the backward error eta of its solution
+  for a solve, the relative log|Pf| bound of the FP64 reduction for a Pfaffian,
+  and for a ratio a first-order bound on the error of log|ratio| from the
+  measured backward error of its solve (see ratio_error_bound).
 * FIFO with overtaking: a request that does not fit yet does not block smaller
   ones behind it.
 
@@ -42,7 +47,7 @@ from typing import Callable, Dict, List, Optional
 @dataclasses.dataclass
 class Request:
     rid: int
-    kind: str            # "pf" or "solve"
+    kind: str            # "pf", "solve" or "ratio"
     n: int
     prec: str            # "f64" or "f32" (FP32 trailing update + refinement for solves)
     matrix_id: int
@@ -50,6 +55,9 @@ class Request:
     nrhs: int = 16
     A: object = None     # client-owned device tensor (column-major), read-only
     B: object = None     # client-owned right-hand sides for solves
+    r: int = 0           # rank of a ratio request's update
+    U: object = None     # client-owned n x r device tensors of a ratio request
+    V: object = None
 
 
 @dataclasses.dataclass
@@ -67,7 +75,7 @@ class Result:
     cached: bool = False
     batched: bool = False
     err: float = float("nan")   # stated error against FP64 (see the module docstring)
-    err_kind: str = ""          # "berr" (solve) or "logpf_rel_bound" (Pfaffian)
+    err_kind: str = ""          # "berr" (solve), "logpf_rel_bound" (Pfaffian) or "log_ratio_bound" (ratio)
 
     @property
     def latency(self) -> float:
@@ -89,9 +97,35 @@ SMALL_N = 512
 PF_REL_BOUND = 1e-12
 
 
+U_RND = 2.0 ** -53
+
+
+def ratio_error_bound(n: int, r: int, logabs: float, XtX, WtX, eta: float, anorm_inf: float) -> float:
+    """First-order bound on the error of log|ratio| for a ratio served through
+    the identity ratio = Pf(K) / Pf(-J), K = W^T X - J, X = A^-1 W, W = [U V]
+    (J = [[0, I_r], [-I_r, 0]]).  A backward error dA of the solve perturbs K by
+    X^T dA X (A skew), and d log|Pf(K)| = tr(K^-1 dK) / 2, so
+      |d| <= (2r / 2) ||X K^-1 X^T||_2 ||dA||_2,
+    with ||X K^-1 X^T||_2 = ||R K^-1 R^T||_2 (X^T X = R^T R) and
+    ||dA||_2 <= sqrt(n) eta ||A||_inf (eta: the measured componentwise-normwise
+    backward error of the solve with W); plus 64 u max(1, |log|ratio||) for the
+    2r x 2r Pfaffian, the logarithms and their sums.  XtX, WtX: 2r x 2r host arrays."""
+    import numpy as np
+    tail = 64 * U_RND * max(1.0, abs(logabs))
+    if r == 0:
+        return tail
+    m = 2 * r
+    J = np.block([[np.zeros((r, r)), np.eye(r)], [-np.eye(r), np.zeros((r, r))]])
+    K = np.asarray(WtX, dtype=np.float64) - J
+    w, Q = np.linalg.eigh(0.5 * (XtX + XtX.T))
+    Rt = Q * np.sqrt(np.clip(w, 0.0, None))          # X^T X = Rt Rt^T
+    c = np.linalg.norm(Rt.T @ np.linalg.solve(K, Rt), 2)
+    return 0.5 * m * c * math.sqrt(n) * eta * anorm_inf + tail
+
+
 def factor_prec(req: Request) -> str:
-    """Precision of the factors a request uses: Pfaffians always FP64."""
-    return "f64" if req.kind == "pf" else req.prec
+    """Precision of the factors a request uses: Pfaffians and ratios always FP64."""
+    return "f64" if req.kind in ("pf", "ratio") else req.prec
 
 
 def factor_key(req: Request):
@@ -106,7 +140,8 @@ def factor_bytes(n: int) -> int:
 def request_bytes(req: Request, ex, have_factors: bool) -> int:
     """Device bytes a request holds while it runs (besides cached factors).
 
-    `ex` supplies the library's workspace queries (ltlt_ws, solve_ws, refine_ws).
+    `ex` supplies the library's workspace queries (ltlt_ws, solve_ws, refine_ws,
+    ratio_ws).
     """
     n = req.n
     b = 0
@@ -115,6 +150,10 @@ def request_bytes(req: Request, ex, have_factors: bool) -> int:
     if req.kind == "solve":
         b += 2 * 8 * n * req.nrhs          # right-hand sides and solution
         b += ex.refine_ws(n, req.nrhs)     # every solve states its backward error
+    elif req.kind == "ratio":
+        m = 2 * req.r
+        b += ex.ratio_ws(n, req.r)         # the ratio itself
+        b += 2 * 8 * n * m + ex.refine_ws(n, m)  # its error bound: [U V] and the solve
     return b
 
 
@@ -359,6 +398,9 @@ class GpuExecutor:
     def refine_ws(self, n: int, nrhs: int) -> int:
         return self.skf.refine_workspace(n, nrhs)
 
+    def ratio_ws(self, n: int, r: int) -> int:
+        return self.skf.pf_ratio_workspace(n, r)
+
     def _stream(self):
         s = getattr(self._tls, "stream", None)
         if s is None:
@@ -403,6 +445,26 @@ class GpuExecutor:
                 s.synchronize()
                 res.logabs, res.sign, res.info = float(la.item()), int(sg.item()), int(dinfo.item())
                 res.err, res.err_kind = PF_REL_BOUND, "logpf_rel_bound"
+            elif r.kind == "ratio":
+                Tn = T[:max(r.n - 1, 0)]
+                la, sg, info = skf.pf_ratio(LT, ipiv[:r.n], Tn, r.U, r.V, stream=s)
+                res.logabs, res.sign = float(la.item()), int(sg.item())
+                res.info = int(dinfo.item()) or int(info)
+                eta, anorm, XtX, WtX = 0.0, 0.0, None, None
+                if r.r > 0 and res.info == 0:
+                    # the stated error: the solve with W = [U V] through the same
+                    # factors, its measured backward error and the 2r x 2r Gram products
+                    W = skf.colmajor(r.n, 2 * r.r, device=self.device)
+                    W[:, :r.r].copy_(r.U)
+                    W[:, r.r:].copy_(r.V)
+                    X, _, _, eta = skf.solve_refine(r.A, LT, ipiv[:r.n], Tn, W, maxit=0, stream=s)
+                    S = torch.tril(r.A, -1).abs()
+                    anorm = float((S.sum(0) + S.sum(1)).max().item())
+                    Xh, Wh = X.cpu().numpy(), W.cpu().numpy()
+                    XtX, WtX = Xh.T @ Xh, Wh.T @ Xh
+                s.synchronize()
+                res.err = ratio_error_bound(r.n, r.r, res.logabs, XtX, WtX, float(eta), anorm)
+                res.err_kind = "log_ratio_bound"
             else:
                 # FP64 factors: one solve, then the backward error (no correction
                 # when it already meets the tolerance); FP32-trailing factors:
@@ -415,9 +477,12 @@ class GpuExecutor:
 
 
 def make_workload(count: int, rate_hz: float, seed: int = 8, nmin: int = 64, nmax: int = 4096,
-                  f32_frac: float = 0.3, solve_frac: float = 0.5, reuse_frac: float = 0.25):
+                  f32_frac: float = 0.3, solve_frac: float = 0.5, reuse_frac: float = 0.25,
+                  ratio_frac: float = 0.0, ratio_rmax: int = 8):
     """The serving trace: Poisson arrivals at `rate_hz`; n = 2 round(exp(U(ln nmin, ln nmax))/2);
-    70/30 FP64/FP32+refine; Pfaffian:solve 50:50; 25% of requests reuse an earlier matrix."""
+    70/30 FP64/FP32+refine; Pfaffian:solve 50:50; 25% of requests reuse an earlier matrix.
+    With ratio_frac > 0, that share of the requests that reuse a matrix ask for a
+    Pfaffian ratio of a rank-r update (r uniform in 1..ratio_rmax) instead."""
     from . import inputs
     reqs = []
     t = 0.0
@@ -427,7 +492,8 @@ def make_workload(count: int, rate_hz: float, seed: int = 8, nmin: int = 64, nma
         u = [inputs.uniform(seed, inputs.STREAM_SERVE, ctr + c) for c in range(6)]
         ctr += 6
         t += -math.log(max(u[0], 1e-300)) / rate_hz if rate_hz > 0 else 0.0
-        if mids and u[1] < reuse_frac:
+        reuse = bool(mids) and u[1] < reuse_frac
+        if reuse:
             mid, n = mids[int(u[2] * len(mids)) % len(mids)]
         else:
             n = int(2 * round(math.exp(math.log(nmin) + u[2] * (math.log(nmax) - math.log(nmin))) / 2))
@@ -436,7 +502,11 @@ def make_workload(count: int, rate_hz: float, seed: int = 8, nmin: int = 64, nma
             mids.append((mid, n))
         kind = "solve" if u[3] < solve_frac else "pf"
         prec = "f32" if u[4] < f32_frac else "f64"
-        reqs.append(Request(rid=i, kind=kind, n=n, prec=prec, matrix_id=mid, arrival=t))
+        rk = 0
+        if reuse and u[5] < ratio_frac:
+            kind, prec = "ratio", "f64"
+            rk = 1 + min(ratio_rmax - 1, int(u[4] * ratio_rmax))
+        reqs.append(Request(rid=i, kind=kind, n=n, prec=prec, matrix_id=mid, arrival=t, r=rk))
     return reqs, mids
 
 
@@ -454,4 +524,10 @@ def materialize(reqs: List[Request], mids, seed: int = 8, device="cuda:0", threa
         if r.kind == "solve":
             r.B = skf.to_device_colmajor(inputs.gaussian(r.n, r.nrhs, seed, inputs.STREAM_BATCH0 + 1_000_000 + r.rid),
                                          device)
+        elif r.kind == "ratio":
+            # U and V of the update: Gaussian, scaled by 1/sqrt(n) so the update
+            # is of the size of A's entries
+            w = inputs.gaussian(r.n, 2 * r.r, seed, inputs.STREAM_BATCH0 + 1_000_000 + r.rid) / math.sqrt(r.n)
+            r.U = skf.to_device_colmajor(w[:, :r.r], device)
+            r.V = skf.to_device_colmajor(w[:, r.r:], device)
     return mats

@@ -61,3 +61,32 @@ def test_serve_alone_equals_mix(ex, oracle_mod, count, nmax):
             assert m.sign == sg and oracle_mod.isclose_log(m.logabs, la) <= m.err, (r, m.logabs, la)
             checked += 1
     assert checked > 0
+
+
+def test_serve_ratio_requests(ex, oracle_mod):
+    """Pfaffian ratios through the serving loop: served from the resident FP64
+    factors of a matrix an earlier solve factored (cache hits), or factoring a
+    new one; each against the oracle's quotient of two Pfaffians within the
+    conditioning bound of the ratio tests, with its stated error bound."""
+    from test_gpu_ratio import ratio_tol
+
+    from paper_2408_05238_amd import serve
+    R = serve.Request
+    reqs = [R(rid=0, kind="solve", n=1000, prec="f64", matrix_id=0, arrival=0.0, nrhs=2),
+            R(rid=1, kind="ratio", n=1000, prec="f64", matrix_id=0, arrival=0.0, r=3),
+            R(rid=2, kind="ratio", n=1000, prec="f32", matrix_id=0, arrival=0.0, r=1),
+            R(rid=3, kind="ratio", n=600, prec="f64", matrix_id=1, arrival=0.0, r=5)]
+    serve.materialize(reqs, [(0, 1000), (1, 600)], seed=8)
+    sch = serve.Scheduler(ex, budget_bytes=16 << 30, workers=1)
+    res = sch.run_trace(reqs)
+    assert res[0].info == 0 and not res[0].cached
+    assert res[1].cached and res[2].cached and not res[3].cached
+    for q in reqs[1:]:
+        m = res[q.rid]
+        A, U, V = q.A.cpu().numpy(), q.U.cpu().numpy(), q.V.cpu().numpy()
+        la_r, s_r, info_r = oracle_mod.pf_ratio(A, U, V, nthreads=8)
+        tol = ratio_tol(oracle_mod.full_from_lower(A), U, V, la_r)
+        print(f"ratio n={q.n} r={q.r}: {m.logabs!r} vs {la_r!r}, stated {m.err:.3e}, bound {tol:.3e}", flush=True)
+        assert m.info == info_r == 0 and m.sign == s_r
+        assert abs(m.logabs - la_r) <= tol
+        assert m.err_kind == "log_ratio_bound" and 0.0 < m.err < 1e-8

@@ -31,6 +31,9 @@ class FakeExecutor:
     def refine_ws(self, n, nrhs):
         return 8 * n * nrhs * 4
 
+    def ratio_ws(self, n, r):
+        return 8 * n * 2 * r * 2
+
     def run(self, reqs, factors):
         tk = sum(serve.tokens(r, factors is not None) for r in reqs)
         with self.lock:
@@ -147,3 +150,63 @@ def test_small_solves_hold_tokens_next_to_large_factorizations():
     assert serve.tokens(reqs[1], False) == 8 and serve.tokens(reqs[1], True) == 0
     assert serve.tokens(reqs[-1], False) == 0
     assert ex.max_tok <= 40 and sch.tokens_used == 0
+
+
+def test_ratio_requests_share_the_fp64_factors():
+    """A ratio request is served from the resident FP64 factors of its matrix: a
+    Pfaffian of order > 512 leaves them, the ratios (and an FP32-labelled
+    Pfaffian) reuse them; a ratio on a new matrix factors it first."""
+    ex = FakeExecutor()
+    sch = serve.Scheduler(ex, budget_bytes=1 << 40, workers=1)
+    reqs = [serve.Request(rid=0, kind="pf", n=1000, prec="f64", matrix_id=3, arrival=0.0),
+            serve.Request(rid=1, kind="ratio", n=1000, prec="f64", matrix_id=3, arrival=0.05, r=4),
+            serve.Request(rid=2, kind="ratio", n=1000, prec="f32", matrix_id=3, arrival=0.1, r=1),
+            serve.Request(rid=3, kind="ratio", n=800, prec="f64", matrix_id=4, arrival=0.15, r=2),
+            serve.Request(rid=4, kind="ratio", n=800, prec="f64", matrix_id=4, arrival=0.2, r=2)]
+    res = sch.run_trace(reqs)
+    assert serve.factor_prec(reqs[2]) == "f64"
+    assert not res[0].cached and res[1].cached and res[2].cached
+    assert not res[3].cached and res[4].cached
+    assert sch.reserved == 0 and sch.tokens_used == 0
+    # the bytes a ratio holds: its workspace, [U V], the solve behind its error bound
+    b = serve.request_bytes(reqs[1], ex, True)
+    assert b == ex.ratio_ws(1000, 4) + 2 * 8 * 1000 * 8 + ex.refine_ws(1000, 8)
+
+
+def test_workload_ratio_share_and_ranks():
+    reqs, mids = serve.make_workload(400, rate_hz=100.0, seed=3, ratio_frac=0.5, ratio_rmax=6)
+    ratios = [r for r in reqs if r.kind == "ratio"]
+    assert ratios and all(1 <= r.r <= 6 and r.prec == "f64" for r in ratios)
+    seen = set()
+    for r in reqs:   # a ratio always refers to a matrix that appeared before it
+        if r.kind == "ratio":
+            assert r.matrix_id in seen
+        seen.add(r.matrix_id)
+    base, _ = serve.make_workload(400, rate_hz=100.0, seed=3)
+    assert not any(r.kind == "ratio" for r in base)
+    assert [(r.n, r.matrix_id, r.arrival) for r in base] == [(r.n, r.matrix_id, r.arrival) for r in reqs]
+
+
+def test_ratio_error_bound_terms():
+    """The stated ratio error: r = 0 leaves the rounding term alone; otherwise the
+    first-order term grows linearly in eta and in ||A||_inf, and the Gram form
+    ||R K^-1 R^T||_2 (X^T X = R^T R) equals ||X K^-1 X^T||_2."""
+    import math
+
+    import numpy as np
+    u = 2.0 ** -53
+    assert serve.ratio_error_bound(100, 0, 5.0, None, None, 0.0, 0.0) == 64 * u * 5.0
+    rng = np.random.default_rng(0)
+    n, r = 40, 3
+    S = np.tril(rng.standard_normal((n, n)), -1)
+    A = S - S.T
+    W = rng.standard_normal((n, 2 * r))
+    X = np.linalg.solve(A, W)
+    J = np.block([[np.zeros((r, r)), np.eye(r)], [-np.eye(r), np.zeros((r, r))]])
+    K = W.T @ X - J
+    direct = np.linalg.norm(X @ np.linalg.solve(K, X.T), 2)
+    eta, an = 1e-16, np.abs(A).sum(1).max()
+    got = serve.ratio_error_bound(n, r, 0.0, X.T @ X, W.T @ X, eta, an) - 64 * u
+    assert math.isclose(got, 0.5 * 2 * r * direct * math.sqrt(n) * eta * an, rel_tol=1e-9)
+    got2 = serve.ratio_error_bound(n, r, 0.0, X.T @ X, W.T @ X, 2 * eta, an) - 64 * u
+    assert math.isclose(got2, 2 * got, rel_tol=1e-9)
