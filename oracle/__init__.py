@@ -20,6 +20,10 @@ remaining references are written here from their definitions:
   |z|^2 = re^2 + im^2 (each product rounded, lowest index on ties), rows and
   columns k+1 and p are interchanged, l = column k / alpha, v = column k+1, and
   l v^T - v l^T is added to the trailing block;
+* ``ltlt_c128`` / ``solve_c128`` -- the LTL^T of a complex skew matrix (the real
+  elimination step at every k with the complex pivot key, multipliers kept in
+  place as for real input) and the solve with its factors (as the real solve,
+  in complex arithmetic), in numpy complex128;
 * ``pf_ratio`` -- Pf(A + U V^T - V U^T) / Pf(A) by its definition: the updated
   matrix is formed (one library product per term) and both Pfaffians are taken
   with the C factorization.
@@ -298,6 +302,176 @@ def logpf_c128_from_factors(n: int, ipiv: np.ndarray, T: np.ndarray):
         la += math.log(a)
         ph *= t / a
     return la, ph
+
+
+def cdiv(a, b):
+    """a / b for complex128 arrays or scalars by Smith's method with true
+    divisions (scaled by the larger component of b): for real operands it is
+    the real division exactly."""
+    a = np.asarray(a, dtype=np.complex128)
+    b = np.asarray(b, dtype=np.complex128)
+    ar, ai, br, bi = a.real, a.imag, b.real, b.imag
+    big = np.abs(br) >= np.abs(bi)
+    with np.errstate(divide="ignore", invalid="ignore"):
+        r1 = bi / br
+        d1 = br + bi * r1
+        r2 = br / bi
+        d2 = br * r2 + bi
+        re = np.where(big, (ar + ai * r1) / d1, (ar * r2 + ai) / d2)
+        im = np.where(big, (ai - ar * r1) / d1, (ai * r2 - ar) / d2)
+    return re + 1j * im
+
+
+def ltlt_c128(A: np.ndarray, want_mag: bool = False):
+    """Partially pivoted LTL^T of the complex skew matrix whose strict lower
+    triangle A holds: P A P^T = L T L^T, L unit lower triangular with
+    L[:, 0] = e_0, T complex skew tridiagonal (T(k+1, k) = T[k], T(k, k+1) = -T[k]).
+    Each step k = 0 .. n-2 is the real elimination step with the complex pivot
+    key: p = the first index >= k+1 maximising |A[p,k]|^2 = re^2 + im^2 (each
+    product rounded); rows and columns k+1 and p interchanged (the multipliers
+    already stored in earlier columns move with their rows); T[k] = A[k+1, k];
+    l = A[k+2:, k] / T[k] (0 when T[k] = 0); A[k+2:, k+2:] := (A + l v^T) - v l^T
+    with v = A[k+2:, k+1]; l is then kept in column k, so that L[i, j] (i > j >= 1)
+    is LT[i, j-1], as for real input.  Returns (LT, ipiv, T, info): ipiv[0] = 0,
+    ipiv[j] the interchange of step j-1; info ENONFINITE for a non-finite pivot
+    column, else 1 + the first even k with T[k] = 0, else 0 (the real rule).
+
+    want_mag: a fifth item M (n x n): M[i, j] (i > j) the sum of the magnitudes
+    of the terms entry (i, j) accumulated (|input| plus |l_i v_j| + |v_i l_j| per
+    update, moved with the entry by the interchanges), so that M[k+1, k] belongs
+    to T[k] and M[i, j-1] to the numerator of L[i, j]."""
+    n = A.shape[0]
+    Lw = np.tril(np.asarray(A, dtype=np.complex128), -1)
+    W = Lw - Lw.T
+    M = np.abs(W) if want_mag else None
+    ipiv = np.arange(n, dtype=np.int32)
+    T = np.zeros(max(n - 1, 0), dtype=np.complex128)
+    info = 0
+    for k in range(0, n - 1):
+        col = W[k + 1:, k]
+        if not np.all(np.isfinite(col)):
+            info = ENONFINITE
+            break
+        key = col.real * col.real + col.imag * col.imag
+        p = k + 1 + int(np.argmax(key))
+        ipiv[k + 1] = p
+        if p != k + 1:
+            W[[k + 1, p], :] = W[[p, k + 1], :]
+            W[:, [k + 1, p]] = W[:, [p, k + 1]]
+            if want_mag:
+                M[[k + 1, p], :] = M[[p, k + 1], :]
+                M[:, [k + 1, p]] = M[:, [p, k + 1]]
+        alpha = W[k + 1, k]
+        T[k] = alpha
+        if k + 2 < n:
+            l = cdiv(W[k + 2:, k], alpha) if alpha != 0 else np.zeros(n - k - 2, dtype=np.complex128)
+            v = W[k + 2:, k + 1].copy()
+            # the strict lower triangle as the definition reads; the upper one is
+            # its negative (so an interchange reads exactly what lower storage holds)
+            U = np.tril((W[k + 2:, k + 2:] + np.outer(l, v)) - np.outer(v, l), -1)
+            W[k + 2:, k + 2:] = U - U.T
+            W[k + 2:, k] = l
+            if want_mag:
+                al, av = np.abs(l), np.abs(v)
+                M[k + 2:, k + 2:] += np.outer(al, av) + np.outer(av, al)
+    if info == 0:
+        for k in range(0, n - 1, 2):
+            if T[k] == 0:
+                info = k + 1
+                break
+    LT = np.tril(W, -1)
+    return (LT, ipiv, T, info, M) if want_mag else (LT, ipiv, T, info)
+
+
+def t_tolerance_c128_full(T_mag: np.ndarray) -> np.ndarray:
+    """Per-entry bound for |T_a[k] - T_b[k]| between two complex LTL^T
+    factorizations along the same interchanges: T[k] collects at most 2k + 1
+    complex products (two per earlier step), each sum within sqrt(2) gamma_(m+2)
+    of its magnitude sum (Higham, section 3.6); twice that for the two."""
+    k = np.arange(T_mag.size, dtype=np.float64)
+    return 2.0 * np.sqrt(2.0) * gamma(2.0 * k + 3.0) * T_mag
+
+
+def l_tolerance_c128(L: np.ndarray, num_mag: np.ndarray, alpha: np.ndarray, alpha_mag: np.ndarray,
+                     col: np.ndarray) -> np.ndarray:
+    """Per-entry bound for |L_a[i,j] - L_b[i,j]| of the complex factorization:
+    L[i,j] = c_i / alpha with c_i and alpha (step j-1) each within the bound of
+    ``t_tolerance_c128_full``, plus the rounding of the two complex divisions
+    (Smith's method: a few u each)."""
+    m = 2.0 * np.asarray(col, dtype=np.float64) + 1.0
+    g = 2.0 * np.sqrt(2.0) * gamma(m)
+    a = np.abs(alpha)
+    return (g * num_mag + np.abs(L) * g * alpha_mag) / a + 16.0 * U_F64 * np.abs(L)
+
+
+def solve_c128(LT: np.ndarray, ipiv: np.ndarray, T: np.ndarray, B: np.ndarray):
+    """X = P^T L^{-T} T^{-1} L^{-1} P B with the complex factors (plain
+    transposes: A is complex skew, A^T = -A).  As the real solve: the
+    interchanges in order, forward substitution with L (L[i,j] = LT[i,j-1]),
+    the tridiagonal T by Gaussian elimination with partial pivoting (row i+1
+    taken as pivot row when |T(i+1,i)|^2 > |running diagonal|^2, squares of
+    rounded products), back substitution, L^T, the interchanges in reverse.
+    Returns (X, info): info = n for odd n, 1 + the first even k with T[k] = 0,
+    or the elimination's own zero pivot, else 0."""
+    n = LT.shape[0]
+    X = np.array(B, dtype=np.complex128)
+    if X.ndim == 1:
+        X = X.reshape(-1, 1)
+    if n == 0:
+        return X, 0
+    if n % 2 == 1:
+        return X, n
+    for k in range(0, n - 1, 2):
+        if T[k] == 0:
+            return X, k + 1
+    c2 = lambda z: z.real * z.real + z.imag * z.imag
+    for j in range(1, n):
+        p = int(ipiv[j])
+        if p != j:
+            X[[j, p], :] = X[[p, j], :]
+    for j in range(1, n):
+        X[j + 1:, :] = X[j + 1:, :] - np.outer(LT[j + 1:, j - 1], X[j, :])
+    dd = np.zeros(n, dtype=np.complex128)
+    du = np.zeros(n, dtype=np.complex128)
+    du2 = np.zeros(n, dtype=np.complex128)
+    dl = np.zeros(n, dtype=np.complex128)
+    dl[:n - 1] = T
+    du[:n - 1] = -T
+    for i in range(n - 1):
+        if c2(dd[i]) >= c2(dl[i]):
+            if dd[i] == 0:
+                return X, i + 1
+            f = complex(cdiv(dl[i], dd[i]))
+            dd[i + 1] = dd[i + 1] - f * du[i]
+            X[i + 1, :] = X[i + 1, :] - f * X[i, :]
+        else:
+            f = complex(cdiv(dd[i], dl[i]))
+            dd[i] = dl[i]
+            t = dd[i + 1]
+            dd[i + 1] = du[i] - f * t
+            du[i] = t
+            if i + 2 < n:
+                du2[i] = du[i + 1]
+                du[i + 1] = -f * du2[i]
+            tb = X[i, :].copy()
+            X[i, :] = X[i + 1, :]
+            X[i + 1, :] = tb - f * X[i, :]
+    if dd[n - 1] == 0:
+        return X, n
+    X[n - 1, :] = cdiv(X[n - 1, :], dd[n - 1])
+    X[n - 2, :] = cdiv(X[n - 2, :] - du[n - 2] * X[n - 1, :], dd[n - 2])
+    for i in range(n - 3, -1, -1):
+        X[i, :] = cdiv(X[i, :] - du[i] * X[i + 1, :] - du2[i] * X[i + 2, :], dd[i])
+    for j in range(n - 1, 0, -1):   # x_j -= L[i, j] x_i, i = j+1 .. n-1 in order
+        acc = X[j, :].copy()
+        for i in range(j + 1, n):
+            acc = acc - LT[i, j - 1] * X[i, :]
+        X[j, :] = acc
+    for j in range(n - 1, 0, -1):
+        p = int(ipiv[j])
+        if p != j:
+            X[[j, p], :] = X[[p, j], :]
+    return X, 0
 
 
 def pfaffian_bruteforce_complex(A) -> complex:
