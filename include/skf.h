@@ -242,6 +242,50 @@ size_t skf_pfonly_c128_workspace(skf_int n);
 int skf_pfonly_c128(skf_int n, const double* A, skf_int lda, int32_t* ipiv, double* T, void* work,
                     size_t lwork, int* dinfo, void* stream);
 
+/* Device workspace (bytes) for skf_ltlt_c128: four n x n FP64 planes and the
+ * panel buffers; 0 when no panel width fits the order on this device. */
+size_t skf_ltlt_c128_workspace(skf_int n);
+
+/*
+ * Partially pivoted LTL^T of a complex (complex128) skew-symmetric matrix:
+ * P A P^T = L T L^T with L unit lower triangular (L[:,0] = e_0) and T complex
+ * skew tridiagonal (T(k+1,k) = T[k], T(k,k+1) = -T[k]); plain transposes.
+ * The elimination step of skf_ltlt at every k with the pivot the largest
+ * |z|^2 = re^2 + im^2 below the diagonal of column k (lowest index on ties).
+ * Blocked: panels of 64 steps (n up to 64 x 256 panel workgroups on 256 CUs,
+ * i.e. 16385) or 32 steps (up to 32769), each a persistent kernel on the real
+ * and imaginary planes, its pairs (l, v) applied as one real skew rank-2k update
+ * per plane on the matrix cores; beyond, SKF_ENOTIMPL.
+ *   A      device, lda x n complex128 (interleaved re, im), strict lower triangle
+ *          read; on exit as skf_ltlt's A: L[i,j] (i > j >= 1) at A[i, j-1], the
+ *          subdiagonal A[k+1,k] = T[k]
+ *   ipiv   device int32[n] (n >= 1), output, as skf_ltlt
+ *   T      device complex128[max(n-1,1)], output
+ *   work   device workspace of skf_ltlt_c128_workspace(n) bytes (256-aligned)
+ *   dinfo  device int or NULL: 0; 1 + the first even k with T[k] = 0 (then
+ *          Pf = 0; the factorization is complete); SKF_ENONFINITE for a
+ *          non-finite pivot column
+ * Pf(A) follows from (ipiv, T) by skf_logpf_c128_from_factors.
+ * Returns 0, the outcome (dinfo NULL: synchronous) or an argument error.
+ */
+int skf_ltlt_c128(skf_int n, double* A, skf_int lda, int32_t* ipiv, double* T, void* work, size_t lwork, int* dinfo,
+                  void* stream);
+
+/* Device workspace (bytes) for skf_solve_c128 with nrhs right-hand sides. */
+size_t skf_solve_c128_workspace(skf_int n, skf_int nrhs);
+
+/*
+ * Solve A X = B with the factors of skf_ltlt_c128 (complex128, interleaved):
+ * X = P^T L^{-T} T^{-1} L^{-1} P B in place over B (n x nrhs, ldb >= n), as
+ * skf_solve: triangular solves by 64-row blocks, T by Gaussian elimination with
+ * partial pivoting on the tridiagonal (row i+1 becomes the pivot row when
+ * |T(i+1,i)|^2 exceeds the running diagonal's |.|^2).
+ * Numerical outcome (dinfo / return): 0; n for odd n; 1 + the first even k with
+ * T[k] = 0 (B is then left as it is); the elimination's own zero pivot.
+ */
+int skf_solve_c128(skf_int n, skf_int nrhs, const double* LT, skf_int lda, const int32_t* ipiv, const double* T,
+                   double* B, skf_int ldb, void* work, size_t lwork, int* dinfo, void* stream);
+
 /* log|Pf| and phase = Pf/|Pf| (device double[2], re and im; 0 when Pf = 0)
  * from the factors of skf_pfonly_c128, in index order.  n = 0: Pf = 1. */
 int skf_logpf_c128_from_factors(skf_int n, const int32_t* ipiv, const double* T, double* logabs,

@@ -339,6 +339,55 @@ int skf_pfonly_c128(skf_int n, const double* A, skf_int lda, int32_t* ipiv, doub
   return finish_sync(rc, dinfo_int, s);
 }
 
+size_t skf_ltlt_c128_workspace(skf_int n) {
+  if (n < 0) return 0;
+  const size_t core = ltlt_c128_workspace_bytes(n);
+  return (core || n == 0) ? core + 256 : 0;
+}
+
+int skf_ltlt_c128(skf_int n, double* A, skf_int lda, int32_t* ipiv, double* T, void* work, size_t lwork, int* dinfo,
+                  void* stream) {
+  if (n < 0) return -1;
+  if (n > 0 && !A) return -2;
+  if (lda < (n > 1 ? n : 1)) return -3;
+  if (n > 0 && !ipiv) return -4;
+  if (n > 1 && !T) return -5;
+  if (!work || ((uintptr_t)work & 255)) return -6;
+  if (n > 0 && ltlt_c128_nb(n) == 0) return SKF_ENOTIMPL;
+  if (lwork < skf_ltlt_c128_workspace(n)) return SKF_EWORK;
+  hipStream_t s = (hipStream_t)stream;
+  const size_t core = ltlt_c128_workspace_bytes(n);
+  int* dinfo_int = (int*)((char*)work + core);
+  int rc = run_ltlt_c128(n, A, lda, ipiv, T, work, core, dinfo ? dinfo : dinfo_int, s);
+  if (dinfo) return rc;
+  return finish_sync(rc, dinfo_int, s);
+}
+
+size_t skf_solve_c128_workspace(skf_int n, skf_int nrhs) {
+  if (n < 0 || nrhs < 0) return 0;
+  return solve_c128_workspace_bytes(n, nrhs) + 256;
+}
+
+int skf_solve_c128(skf_int n, skf_int nrhs, const double* LT, skf_int lda, const int32_t* ipiv, const double* T,
+                   double* B, skf_int ldb, void* work, size_t lwork, int* dinfo, void* stream) {
+  if (n < 0) return -1;
+  if (nrhs < 0) return -2;
+  if (n > 0 && !LT) return -3;
+  if (lda < (n > 1 ? n : 1)) return -4;
+  if (n > 0 && !ipiv) return -5;
+  if (n > 1 && !T) return -6;
+  if (n > 0 && nrhs > 0 && !B) return -7;
+  if (ldb < (n > 1 ? n : 1)) return -8;
+  if (!work || ((uintptr_t)work & 255)) return -9;
+  if (lwork < skf_solve_c128_workspace(n, nrhs)) return SKF_EWORK;
+  hipStream_t s = (hipStream_t)stream;
+  const size_t core = solve_c128_workspace_bytes(n, nrhs);
+  int* dinfo_int = (int*)((char*)work + core);
+  int rc = run_solve_c128(n, nrhs, LT, lda, ipiv, T, B, ldb, work, core, dinfo ? dinfo : dinfo_int, s);
+  if (dinfo) return rc;
+  return finish_sync(rc, dinfo_int, s);
+}
+
 int skf_logpf_c128_from_factors(skf_int n, const int32_t* ipiv, const double* T, double* logabs, double* phase,
                                 void* stream) {
   if (n < 0) return -1;

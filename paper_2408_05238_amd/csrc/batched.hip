@@ -265,8 +265,11 @@ __global__ void __launch_bounds__(BT, kWgPerCu) batched_kernel(BatchArgs a) {
         // pivot column through cur; the next step overwrites it with L).
         // Every thread has read alpha = cur[p] before rows r and p of the LDS
         // arrays are swapped: an LDS-only barrier (global stores stay in flight).
-        __builtin_amdgcn_s_waitcnt(0xC07F);  // lgkmcnt(0); vmcnt and expcnt not waited
+        // (fences on LDS only: they order the LDS accesses around the barrier for
+        // the compiler too, and wait for LDS, not for the global stores)
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
         __builtin_amdgcn_s_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
         if (p != rr && tid < BNP + 2) {
           // LDS rows r and p: pairs, current-pair multipliers, pivot column
           if (tid < BNP) {
@@ -496,8 +499,9 @@ __global__ void __launch_bounds__(BT, kWgPerCu) pfonly_kernel(BatchArgs a) {
           }
           // every thread has read alpha = cur[p] before rows r and p of the LDS
           // arrays are swapped: an LDS-only barrier (global stores stay in flight)
-          __builtin_amdgcn_s_waitcnt(0xC07F);
+          __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
           __builtin_amdgcn_s_barrier();
+          __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
           if (p != rr && tid <= BNP) {
             if (tid < BNP) {
               const double2 t = sm.LW[tid][rr];

@@ -470,6 +470,376 @@ int launch_cpanel(const CPanelParams& p, int nb, hipStream_t s) {
   return SKF_ENOTIMPL;
 }
 
+// ---------------------------------------------------------------------------
+// Complex LTL^T panel: steps k = k0 .. k0 + nsteps - 1, every one of them (the
+// real factorization's step with the complex pivot key).  Step k gives the pair
+// (l, v): l = column k / alpha below row k+1, v = column k+1 after the
+// interchange there; the update l v^T - v l^T touches only rows and columns
+// >= k+2, so v is itself the next step's pivot column: a step gathers one
+// column of the panel-start matrix, S(., x) for the winner x, and adds the GEMV
+// over the panel's pairs so far (the winner's coefficients from its mirror).
+// The panel leaves the pairs as the operands of the two real trailing updates
+// (as the Pfaffian-only panel does), and its L columns (alpha at the pivot row,
+// l below) in the slots' panel-end order.
+// ---------------------------------------------------------------------------
+template <int NB>
+struct CLSmem {
+  double2 L[NB][64];  // l of each step, per slot
+  double2 V[NB][64];  // v of each step, per slot
+  double2 xl[NB];     // the winner's l and v of the steps so far
+  double2 xv[NB];
+  double2 al[NB];     // alpha of each step
+};
+
+struct CLtltParams {
+  CPanelParams c;
+  double* Lre;  // n x nsteps: the panel's L columns, real plane (slot rows in panel-end order)
+  double* Lim;  // imaginary plane
+  int npairs;   // steps with a pair (k <= n-3)
+};
+
+template <int NB, int NQ>
+__global__ void __launch_bounds__(kPanelThreads) cltlt_panel_kernel(CLtltParams Q) {
+  const CPanelParams& P = Q.c;
+  __shared__ CLSmem<NB> sm;
+
+  const int lane = threadIdx.x;
+  const int g = blockIdx.x;
+  const int64_t n = P.n, k0 = P.k0, ld = P.ld;
+  const int64_t rowbase = k0 + 1 + (int64_t)g * P.S;
+  const int nslots = (int)max((int64_t)0, min((int64_t)P.S, n - rowbase));
+  const int G = P.G;
+  const bool mine = lane < nslots;
+  if (g == 0)
+    for (int64_t i = lane; i <= k0; i += kPanelThreads) P.pi[i] = (int32_t)i;
+  if (*P.status != 0) {
+    if (mine) P.pi[rowbase + lane] = (int32_t)(rowbase + lane);
+    return;
+  }
+  uint64_t* const my_mirror = P.mirror + ((size_t)g * 64 + lane) * NB * 8;
+  for (int q = 0; q < NB; ++q) {
+    sm.L[q][lane] = make_double2(0.0, 0.0);
+    sm.V[q][lane] = make_double2(0.0, 0.0);
+  }
+  if (lane < NB) sm.xl[lane] = sm.xv[lane] = sm.al[lane] = make_double2(0.0, 0.0);
+
+  int32_t psi = mine ? (int32_t)(rowbase + lane) : INT32_MAX;
+  const int32_t hbm = mine ? (int32_t)(rowbase + lane) : 0;
+  cd cur = {0.0, 0.0};
+  if (mine) cur = {P.sre[rowbase + lane + k0 * ld], P.sim[rowbase + lane + k0 * ld]};
+  asm volatile("" : "+v"(cur.re), "+v"(cur.im));  // landed here, not at the loop head
+  int stop = 0;
+  int done = 0;      // steps with a pair
+  int recorded = 0;  // steps whose pivot is recorded
+
+  for (int si = 0; si < P.nsteps; ++si) {
+    const int64_t k = k0 + si;
+    const int64_t r = k + 1;
+    const bool last = si >= Q.npairs;  // k = n-2: pivot only
+    const uint32_t tag = P.tag_base + (uint32_t)si + 1u;
+    const uint32_t t16 = tag16(tag);
+    uint64_t* const recs0 = P.rec + (size_t)(si & 1) * G * kRecCopies * kRecStride;
+    uint64_t* const recs = recs0 + (size_t)(g % kRecCopies) * G * kRecStride;
+    uint64_t* const zcs = P.zc + (size_t)(si & 1) * G * 4;
+
+    // (A) local candidate: largest |z|^2 of this workgroup's rows at index >= k+1
+    const bool act = mine && psi >= k + 1;
+    const bool nonfin = __any(act && !cfinite(cur));
+    const double key = act ? cnorm2z(cur) : 0.0;
+    const int bs = wave_argbest(key, (uint32_t)psi, act);
+
+    // (B) record (key, index, slot) and the candidate's value
+    {
+      const int owner = (bs >= 0) ? bs : 0;
+      const double kv = rld(key, owner);
+      const cd zv = rldz(cur, owner);
+      const uint32_t meta = nonfin ? kFlagNonFinite
+                                   : (bs < 0 ? kFlagNoCand : (rl32((uint32_t)psi, owner) | ((uint32_t)owner << 24)));
+      const uint64_t kb = (uint64_t)__double_as_longlong(kv) & ~(1ull << 63);
+      const uint64_t th = (uint64_t)t16 << 48;
+      const uint64_t w0 = th | ((uint64_t)meta << 16) | (kb >> 47);
+      const uint64_t w1 = th | (kb & kLow47);
+      constexpr int kW = 2 * kRecCopies;
+      if (lane < kW) st_word(recs0 + ((size_t)(lane >> 1) * G + g) * kRecStride + (lane & 1), (lane & 1) ? w1 : w0);
+      if (lane >= kW && lane < kW + 4) {
+        const int t = lane - kW;
+        const uint32_t pay = (t == 0) ? hi32(zv.re) : (t == 1) ? lo32(zv.re) : (t == 2) ? hi32(zv.im) : lo32(zv.im);
+        st_word(zcs + (size_t)g * 4 + t, mk(tag, pay));
+      }
+    }
+
+    // (C) records -> global pivot
+    double gv = -1.0;
+    uint32_t gp = kNoCand, gslot = 0;
+    int gs = -1;
+    bool bad = false, tout = false;
+    {
+      uint64_t w[NQ][2];
+      const uint64_t* rp[NQ];
+#pragma unroll
+      for (int q = 0; q < NQ; ++q) {
+        const int rr = lane + 64 * q;
+        rp[q] = recs + (size_t)(rr < G ? rr : 0) * kRecStride;
+      }
+      auto load_recs = [&]() {
+#pragma unroll
+        for (int q = 0; q < NQ; ++q) {
+          w[q][0] = ld_word(rp[q]);
+          w[q][1] = ld_word(rp[q] + 1);
+        }
+      };
+      load_recs();
+      uint64_t t0 = 0;
+      for (int it = 0;; ++it) {
+        bool ok = true;
+#pragma unroll
+        for (int q = 0; q < NQ; ++q) {
+          const bool need = lane + 64 * q < G;
+          ok &= !need | ((tag16_of(w[q][0]) == t16) & (tag16_of(w[q][1]) == t16));
+        }
+        if (__all(ok)) break;
+        poll_refresh(it);
+        if ((it & 31) == 0) {
+          const uint64_t now = wall_clock64();
+          if (it == 0) t0 = now;
+          else if (now - t0 > kWaitTicks) {
+            tout = true;
+            break;
+          }
+        }
+        load_recs();
+      }
+#pragma unroll
+      for (int q = 0; q < NQ; ++q) {
+        landed(w[q][0]);
+        landed(w[q][1]);
+      }
+#pragma unroll
+      for (int q = 0; q < NQ; ++q) {
+        const int rr = lane + 64 * q;
+        const uint32_t meta = (uint32_t)(w[q][0] >> 16);
+        const bool use = rr < G && !tout;
+        bad |= use && (meta & kFlagNonFinite);
+        if (use && !(meta & (kFlagNonFinite | kFlagNoCand))) {
+          const uint64_t kb = ((w[q][0] & 0xFFFFull) << 47) | (w[q][1] & kLow47);
+          const double a = __longlong_as_double((long long)kb);
+          const uint32_t ps = meta & 0xFFFFFFu;
+          if (better(a, ps, gv, gp)) {
+            gv = a;
+            gp = ps;
+            gs = rr;
+            gslot = meta >> 24 & 63u;
+          }
+        }
+      }
+    }
+    tout = __any(tout);
+    bad = __any(bad);
+    const int wl = wave_argbest(gv, gp, gs >= 0);
+    stop = tout ? 4 : (bad ? 2 : (wl < 0 ? 4 : 0));
+    if (stop) break;
+    gp = rl32(gp, wl);
+    gs = (int)rl32((uint32_t)gs, wl);
+    const int wslot = (int)rl32(gslot, wl);
+    const int64_t hx = k0 + 1 + (int64_t)gs * P.S + wslot;
+    const int64_t pidx = gp;
+
+    // (D) relabel
+    if (mine && pidx != r) {
+      if (psi == (int32_t)r) psi = (int32_t)pidx;
+      else if (psi == (int32_t)pidx) psi = (int32_t)r;
+    }
+    const bool below = mine && psi >= k + 2;
+
+    // (F) the winner's value (alpha), the gather S(i, x) (valid addresses
+    // everywhere; sign and mask afterwards) and the winner's coefficient rows:
+    // lane q fetches step q's (l, v) of row x
+    const bool lowx = (int64_t)hbm > hx;
+    const int64_t ax_ = lowx ? (int64_t)hbm + hx * ld : hx + (int64_t)hbm * ld;
+    const cd grx = {P.sre[ax_], P.sim[ax_]};
+    cd alpha;
+    {
+      const bool has = lane < si;
+      const uint64_t* wx = P.mirror + (((size_t)gs * 64 + wslot) * NB + (has ? lane : 0)) * 8;
+      const uint64_t* za = zcs + (size_t)gs * 4;
+      const uint32_t tq = P.tag_base + (uint32_t)lane + 1u;  // pair q carries the tag of step q
+      uint64_t cx[8], z[4];
+      auto load_all = [&]() {
+#pragma unroll
+        for (int t = 0; t < 8; ++t) cx[t] = ld_word(wx + t);
+#pragma unroll
+        for (int t = 0; t < 4; ++t) z[t] = ld_word(za + t);
+      };
+      load_all();
+      uint64_t t0 = 0;
+      for (int it = 0;; ++it) {
+        bool ok = true, okc = true;
+#pragma unroll
+        for (int t = 0; t < 4; ++t) ok &= tag_of(z[t]) == tag;
+#pragma unroll
+        for (int t = 0; t < 8; ++t) okc &= tag_of(cx[t]) == tq;
+        ok &= !has | okc;
+        if (__all(ok)) break;
+        poll_refresh(it);
+        if ((it & 31) == 0) {
+          const uint64_t now = wall_clock64();
+          if (it == 0) t0 = now;
+          else if (now - t0 > kWaitTicks) {
+            tout = true;
+            break;
+          }
+        }
+        load_all();
+      }
+#pragma unroll
+      for (int t = 0; t < 8; ++t) landed(cx[t]);
+#pragma unroll
+      for (int t = 0; t < 4; ++t) landed(z[t]);
+      if (__any(tout)) {
+        stop = 4;
+        break;
+      }
+      alpha = {from32((uint32_t)z[0], (uint32_t)z[1]), from32((uint32_t)z[2], (uint32_t)z[3])};
+      if (has) {
+        sm.xl[lane] = make_double2(from32((uint32_t)cx[0], (uint32_t)cx[1]), from32((uint32_t)cx[2], (uint32_t)cx[3]));
+        sm.xv[lane] = make_double2(from32((uint32_t)cx[4], (uint32_t)cx[5]), from32((uint32_t)cx[6], (uint32_t)cx[7]));
+      }
+    }
+    if (g == 0 && lane == 0) {
+      P.ipiv[r] = (int32_t)pidx;
+      P.T[2 * k] = alpha.re;
+      P.T[2 * k + 1] = alpha.im;
+    }
+    if (lane == 0) sm.al[si] = d2(alpha);
+    recorded = si + 1;
+    if (last) break;
+    const cd gx = below ? (lowx ? grx : cnegz(grx)) : cd{0.0, 0.0};
+
+    // complex skew GEMV over the steps so far
+    cd ax = {0.0, 0.0};
+    for (int q = 0; q < si; ++q) {
+      const cd l = cz(sm.L[q][lane]), v = cz(sm.V[q][lane]);
+      ax = caddz(ax, csubz(cmulz(l, cz(sm.xv[q])), cmulz(v, cz(sm.xl[q]))));
+    }
+    const bool anz = alpha.re != 0.0 || alpha.im != 0.0;
+    const cd li = (below && anz) ? cdivz(cur, alpha) : cd{0.0, 0.0};
+    const cd vi = below ? caddz(gx, ax) : cd{0.0, 0.0};
+    sm.L[si][lane] = d2(li);
+    sm.V[si][lane] = d2(vi);
+    cur = vi;  // the next pivot column (rows at index >= k+2)
+    ++done;
+    if (mine) {
+      uint64_t* m = my_mirror + (size_t)si * 8;
+      st_word(m + 0, mk(tag, hi32(li.re)));
+      st_word(m + 1, mk(tag, lo32(li.re)));
+      st_word(m + 2, mk(tag, hi32(li.im)));
+      st_word(m + 3, mk(tag, lo32(li.im)));
+      st_word(m + 4, mk(tag, hi32(vi.re)));
+      st_word(m + 5, mk(tag, lo32(vi.re)));
+      st_word(m + 6, mk(tag, hi32(vi.im)));
+      st_word(m + 7, mk(tag, lo32(vi.im)));
+    }
+  }
+
+  // ---- panel end ----
+  if (stop) {
+    if (lane == 0) atomicMin(P.status, (stop & 4) ? SKF_ETIMEOUT : SKF_ENONFINITE);
+    if (mine) P.pi[psi] = hbm;
+    return;
+  }
+  __syncthreads();  // sm.al written by lane 0
+  if (!mine) return;
+  const int64_t lo = k0 + done;
+  const bool z0 = psi == lo;  // row lo of the operands is zero: column lo gets no products
+  for (int q = 0; q < done; ++q) {
+    const double2 l = sm.L[q][lane], v = sm.V[q][lane];
+    const int64_t a = psi + (int64_t)q * n, b = psi + (int64_t)(done + q) * n;
+    const double lr = z0 ? 0.0 : l.x, lim = z0 ? 0.0 : l.y, vr = z0 ? 0.0 : v.x, vim = z0 ? 0.0 : v.y;
+    P.P[a] = lr;
+    P.P[b] = lim;
+    P.NP[a] = -lr;
+    P.NP[b] = -lim;
+    P.Qre[a] = vr;
+    P.Qre[b] = -vim;
+    P.Qim[a] = vim;
+    P.Qim[b] = vr;
+  }
+  // L columns: alpha at the step's pivot row, l below it
+  for (int q = 0; q < recorded; ++q) {
+    const int64_t kq = k0 + q;
+    const double2 x = ((int64_t)psi == kq + 1) ? sm.al[q] : sm.L[q][lane];
+    Q.Lre[psi + (int64_t)q * n] = x.x;
+    Q.Lim[psi + (int64_t)q * n] = x.y;
+  }
+  P.pi[psi] = hbm;
+  if (psi >= lo + 1) {
+    P.cnre[psi] = cur.re;
+    P.cnim[psi] = cur.im;
+  }
+}
+
+template <int NB, int NQ>
+int launch_cltlt_t(const CLtltParams& p, hipStream_t s) {
+  hipLaunchKernelGGL((cltlt_panel_kernel<NB, NQ>), dim3(p.c.G), dim3(kPanelThreads), 0, s, p);
+  SKF_CHECK_LAUNCH("complex ltlt panel");
+  return 0;
+}
+
+int launch_cltlt(const CLtltParams& p, int nb, hipStream_t s) {
+  const int nq = (p.c.G + 63) / 64;
+  if (nb == 64) {
+    if (nq <= 1) return launch_cltlt_t<64, 1>(p, s);
+    if (nq <= 2) return launch_cltlt_t<64, 2>(p, s);
+    if (nq <= 4) return launch_cltlt_t<64, 4>(p, s);
+  } else if (nb == 32) {
+    if (nq <= 1) return launch_cltlt_t<32, 1>(p, s);
+    if (nq <= 2) return launch_cltlt_t<32, 2>(p, s);
+    if (nq <= 4) return launch_cltlt_t<32, 4>(p, s);
+    if (nq <= 8) return launch_cltlt_t<32, 8>(p, s);
+  }
+  return SKF_ENOTIMPL;
+}
+
+// W[i, k0+c] = L[i, c] (both planes) for the rows below the diagonal of column k0+c.
+__global__ void park_L_kernel(int64_t n, int64_t k0, const double* __restrict__ Lre, const double* __restrict__ Lim,
+                              double* __restrict__ Wre, double* __restrict__ Wim) {
+  const int c = blockIdx.y;
+  const int64_t col = k0 + c;
+  for (int64_t i = col + 1 + blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    Wre[i + col * n] = Lre[i + (int64_t)c * n];
+    Wim[i + col * n] = Lim[i + (int64_t)c * n];
+  }
+}
+
+// A[i, c] (interleaved) = W[sigma_P(i), c] for i > c, P the panel of column c.
+__global__ void final_L_c128_kernel(int64_t n, int nb, const double* __restrict__ Wre, const double* __restrict__ Wim,
+                                    const int32_t* __restrict__ sigma, double* __restrict__ A, int64_t lda) {
+  const int64_t c = blockIdx.y;
+  const int32_t* sg = sigma + (c / nb) * n;
+  for (int64_t i = c + 1 + blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t src = (int64_t)sg[i] + c * n;
+    A[2 * (i + c * lda)] = Wre[src];
+    A[2 * (i + c * lda) + 1] = Wim[src];
+  }
+}
+
+// dinfo: status if set; else 1 + the first even k with T[k] = 0, or 0 (the
+// real factorization's rule: odd n completes, Pf = 0 follows from n).
+__global__ void cltlt_info_kernel(int64_t n, const double* __restrict__ T, const int* __restrict__ status,
+                                  int* __restrict__ dinfo) {
+  if (threadIdx.x != 0) return;
+  int v = *status;
+  if (v == 0)
+    for (int64_t k = 0; k + 1 < n; k += 2)
+      if (T[2 * k] == 0.0 && T[2 * k + 1] == 0.0) {
+        v = (int)(k + 1);
+        break;
+      }
+  *dinfo = v;
+}
+
 constexpr int kCSlots = 64;
 
 // Panel width for order n: 128 (132 KB of LDS per workgroup, one per CU) when
@@ -520,6 +890,62 @@ CBWork cb_carve(void* base, int64_t n, int nb) {
   w.mirror = (uint64_t*)take(sizeof(uint64_t) * (size_t)G * 64 * (nb / 2) * 8);
   w.zc = (uint64_t*)take(sizeof(uint64_t) * 2 * (size_t)G * 4);
   w.front = (uint64_t*)take(sizeof(uint64_t) * 32);
+  w.status = (int*)take(256);
+  w.bytes = off;
+  return w;
+}
+
+// Panel width (steps per panel) of the complex LTL^T for order n: 64 (134 KB
+// of LDS per workgroup, one per CU) when its workgroups fit on the device, else
+// 32 (two per CU), else 0.  SKF_NB=32 selects the narrow panel wherever it fits.
+int clplan_nb(int64_t n) {
+  const int64_t g0 = std::max<int64_t>(1, (n - 1 + kCSlots - 1) / kCSlots);
+  const int64_t cus = device_info().num_cus;
+  const char* e = getenv("SKF_NB");
+  const bool narrow = e && atoi(e) == 32;
+  if (!narrow && g0 <= std::min<int64_t>(256, cus)) return 64;
+  if (g0 <= std::min<int64_t>(512, 2 * cus)) return 32;
+  return 0;
+}
+
+struct CLWork {
+  double* re[2];
+  double* im[2];
+  double *P, *NP, *Qre, *Qim, *Lre, *Lim, *cnre, *cnim;
+  int32_t *pis, *sigma;
+  uint64_t *rec, *mirror, *zc;
+  int* status;
+  size_t bytes;
+};
+
+CLWork cl_carve(void* base, int64_t n, int nb) {
+  CLWork w{};
+  size_t off = 0;
+  auto take = [&](size_t b) {
+    size_t o = off;
+    off = align_up(off + b, 256);
+    return base ? (void*)((char*)base + o) : nullptr;
+  };
+  const size_t m = (size_t)std::max<int64_t>(n, 1);
+  const int64_t G = std::max<int64_t>(1, (n - 1 + kCSlots - 1) / kCSlots);
+  const size_t np = (size_t)std::max<int64_t>(1, (n - 1 + nb - 1) / nb);
+  for (int t = 0; t < 2; ++t) {
+    w.re[t] = (double*)take(sizeof(double) * m * m);
+    w.im[t] = (double*)take(sizeof(double) * m * m);
+  }
+  w.P = (double*)take(sizeof(double) * m * 2 * nb);
+  w.NP = (double*)take(sizeof(double) * m * 2 * nb);
+  w.Qre = (double*)take(sizeof(double) * m * 2 * nb);
+  w.Qim = (double*)take(sizeof(double) * m * 2 * nb);
+  w.Lre = (double*)take(sizeof(double) * m * nb);
+  w.Lim = (double*)take(sizeof(double) * m * nb);
+  w.cnre = (double*)take(sizeof(double) * m);
+  w.cnim = (double*)take(sizeof(double) * m);
+  w.pis = (int32_t*)take(sizeof(int32_t) * np * m);
+  w.sigma = (int32_t*)take(sizeof(int32_t) * np * m);
+  w.rec = (uint64_t*)take(sizeof(uint64_t) * 2 * (size_t)G * kRecCopies * kRecStride);
+  w.mirror = (uint64_t*)take(sizeof(uint64_t) * (size_t)G * 64 * nb * 8);
+  w.zc = (uint64_t*)take(sizeof(uint64_t) * 2 * (size_t)G * 4);
   w.status = (int*)take(256);
   w.bytes = off;
   return w;
@@ -602,6 +1028,102 @@ int run_pfonly_c128_blocked(int64_t n, const double* A, int64_t lda, int32_t* ip
   if (dinfo) {
     hipLaunchKernelGGL(cinfo_kernel, dim3(1), dim3(64), 0, s, n, T, w.status, dinfo);
     SKF_CHECK_LAUNCH("complex info");
+  }
+  return 0;
+}
+
+
+size_t ltlt_c128_workspace_bytes(int64_t n) {
+  const int nb = clplan_nb(n);
+  return nb ? cl_carve(nullptr, n, nb).bytes : 0;
+}
+
+int ltlt_c128_nb(int64_t n) { return clplan_nb(n); }
+
+// Blocked complex LTL^T: per panel of nb steps the panel kernel, the trailing
+// update of both planes on the matrix cores (the panel's pairs as in the
+// Pfaffian-only reduction), and the panel's L columns parked in plane set 1;
+// at the end the later panels' interchanges are composed and L is gathered into
+// A (interleaved) in final row order.
+int run_ltlt_c128(int64_t n, double* A, int64_t lda, int32_t* ipiv, double* T, void* work, size_t lwork,
+                  int* dinfo, hipStream_t s) {
+  if (n == 0) return dinfo ? launch_fill_i32(dinfo, 1, 0, s) : 0;
+  const int nb = clplan_nb(n);
+  if (!nb) return SKF_ENOTIMPL;
+  CLWork w = cl_carve(work, n, nb);
+  if (lwork < w.bytes) return SKF_EWORK;
+  int rc;
+  if ((rc = launch_fill_i32(w.status, 1, 0, s))) return rc;
+  if ((rc = launch_fill_i32(ipiv, 1, 0, s))) return rc;  // ipiv[0] = 0
+  if (n >= 2) {
+    if ((rc = launch_fill_u64((uint64_t*)T, (size_t)(n - 1) * 2, 0, s))) return rc;
+    const int64_t G0 = std::max<int64_t>(1, (n - 1 + kCSlots - 1) / kCSlots);
+    const unsigned gx = (unsigned)std::min<int64_t>((n + 255) / 256, 1024);
+    hipLaunchKernelGGL(split_kernel, dim3(gx, (unsigned)n), dim3(256), 0, s, n, A, lda, w.re[0], w.im[0]);
+    SKF_CHECK_LAUNCH("complex split");
+    if ((rc = launch_fill_u64(w.rec, 2 * (size_t)G0 * kRecCopies * kRecStride, 0, s))) return rc;
+    if ((rc = launch_fill_u64(w.mirror, (size_t)G0 * 64 * nb * 8, 0, s))) return rc;
+    if ((rc = launch_fill_u64(w.zc, 2 * (size_t)G0 * 4, 0, s))) return rc;
+    const int64_t np = (n - 1 + nb - 1) / nb;
+    for (int64_t Pn = 0; Pn < np; ++Pn) {
+      const int64_t k0 = Pn * nb;
+      const int nsteps = (int)std::min<int64_t>(nb, n - 1 - k0);
+      const int npairs = (int)std::max<int64_t>(0, std::min<int64_t>(nsteps, n - 2 - k0));
+      CLtltParams q{};
+      CPanelParams& pp = q.c;
+      pp.n = n;
+      pp.k0 = k0;
+      pp.nsteps = nsteps;
+      pp.S = kCSlots;
+      pp.G = (int)std::max<int64_t>(1, (n - k0 - 1 + kCSlots - 1) / kCSlots);
+      pp.sre = w.re[Pn % 2];
+      pp.sim = w.im[Pn % 2];
+      pp.ld = n;
+      pp.P = w.P;
+      pp.NP = w.NP;
+      pp.Qre = w.Qre;
+      pp.Qim = w.Qim;
+      pp.pi = w.pis + Pn * n;
+      pp.cnre = w.cnre;
+      pp.cnim = w.cnim;
+      pp.T = T;
+      pp.ipiv = ipiv;
+      pp.rec = w.rec;
+      pp.mirror = w.mirror;
+      pp.zc = w.zc;
+      pp.front = nullptr;
+      pp.status = w.status;
+      pp.tag_base = (uint32_t)k0;
+      q.Lre = w.Lre;
+      q.Lim = w.Lim;
+      q.npairs = npairs;
+      prof_begin(s);
+      if ((rc = launch_cltlt(q, nb, s))) return rc;
+      prof_end(s, 0, 0.0);
+      const int64_t lo = k0 + npairs;
+      if (npairs == nsteps) {  // not the last panel: the trailing planes get the panel's pairs
+        const int64_t m = n - lo;
+        prof_begin(s);
+        rc = launch_skr2k_perm(n, lo, 2 * npairs, w.re[Pn % 2], n, w.re[(Pn + 1) % 2], n, pp.pi, w.P, w.Qre, w.NP,
+                               n, w.cnre, false, s);
+        if (rc) return rc;
+        rc = launch_skr2k_perm(n, lo, 2 * npairs, w.im[Pn % 2], n, w.im[(Pn + 1) % 2], n, pp.pi, w.P, w.Qim, w.NP,
+                               n, w.cnim, false, s);
+        if (rc) return rc;
+        prof_end(s, 1, 2.0 * 2.0 * (2.0 * npairs) * (double)m * (double)(m - 1) / 2.0);
+      }
+      hipLaunchKernelGGL(park_L_kernel, dim3(gx, (unsigned)nsteps), dim3(256), 0, s, n, k0, w.Lre, w.Lim, w.re[1],
+                         w.im[1]);
+      SKF_CHECK_LAUNCH("complex park L");
+    }
+    if ((rc = launch_compose_sigma(n, (int)np, w.pis, w.sigma, s))) return rc;
+    hipLaunchKernelGGL(final_L_c128_kernel, dim3(gx, (unsigned)(n - 1)), dim3(256), 0, s, n, nb, w.re[1], w.im[1],
+                       w.sigma, A, lda);
+    SKF_CHECK_LAUNCH("complex final L");
+  }
+  if (dinfo) {
+    hipLaunchKernelGGL(cltlt_info_kernel, dim3(1), dim3(64), 0, s, n, T, w.status, dinfo);
+    SKF_CHECK_LAUNCH("complex ltlt info");
   }
   return 0;
 }

@@ -65,6 +65,12 @@ int skr2k_band(int64_t m);
 size_t solve_workspace_bytes(int64_t n, int64_t nrhs);
 int run_solve(int64_t n, int64_t nrhs, const double* LT, int64_t lda, const int32_t* ipiv, const double* T,
               double* B, int64_t ldb, void* work, size_t lwork, int* dinfo, hipStream_t s);
+// perm[j] = the original row at position j after the interchanges ipiv (solve.hip).
+int launch_solve_perm(int64_t n, const int32_t* ipiv, int32_t* perm, hipStream_t s);
+// Solve with complex factors (csolve.hip).
+size_t solve_c128_workspace_bytes(int64_t n, int64_t nrhs);
+int run_solve_c128(int64_t n, int64_t nrhs, const double* LT, int64_t lda, const int32_t* ipiv, const double* T,
+                   double* B, int64_t ldb, void* work, size_t lwork, int* dinfo, hipStream_t s);
 // Batched solves in one launch (solve_batched.hip); orders above 1024 fall back
 // to run_solve per matrix.
 size_t solve_batched_workspace_bytes(int64_t batch, const int64_t* n_host, const int64_t* nrhs_host);
@@ -187,6 +193,11 @@ int launch_logpf_c128(int64_t n, const int32_t* ipiv, const double* T, double* l
                       hipStream_t s);
 // Blocked form (complex_blocked.hip): panel width for n (0 when its panel does not fit the device).
 int pfonly_c128_blocked_nb(int64_t n);
+// Complex LTL^T (complex_blocked.hip): steps per panel (0: order too large), workspace, run.
+int ltlt_c128_nb(int64_t n);
+size_t ltlt_c128_workspace_bytes(int64_t n);
+int run_ltlt_c128(int64_t n, double* A, int64_t lda, int32_t* ipiv, double* T, void* work, size_t lwork,
+                  int* dinfo, hipStream_t s);
 size_t pfonly_c128_blocked_workspace_bytes(int64_t n);
 int run_pfonly_c128_blocked(int64_t n, const double* A, int64_t lda, int32_t* ipiv, double* T, void* work,
                             size_t lwork, int* dinfo, hipStream_t s);

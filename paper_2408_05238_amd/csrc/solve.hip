@@ -816,6 +816,14 @@ size_t solve_workspace_bytes(int64_t n, int64_t nrhs) {
   return solve_carve(nullptr, n).bytes + 256;
 }
 
+// perm[j] = the original row at position j after the recorded interchanges.
+int launch_solve_perm(int64_t n, const int32_t* ipiv, int32_t* perm, hipStream_t s) {
+  if (n <= 0) return 0;
+  hipLaunchKernelGGL(perm_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, n, ipiv, perm);
+  SKF_CHECK_LAUNCH("perm");
+  return 0;
+}
+
 // Solve in place over B; dinfo (device) receives the numerical outcome.
 int run_solve(int64_t n, int64_t nrhs, const double* LT, int64_t lda, const int32_t* ipiv, const double* T,
               double* B, int64_t ldb, void* work, size_t lwork, int* dinfo, hipStream_t s) {

@@ -32,7 +32,8 @@ EXPORTS = [
     "skf_version", "skf_last_error", "skf_ltlt_workspace", "skf_ltlt", "skf_pfonly", "skf_logpf_from_factors",
     "skf_logpf_workspace", "skf_logpf", "skf_pfaffian", "skf_skr2k", "skf_skr2k_f32",
     "skf_solve_workspace", "skf_solve", "skf_solve_noalloc", "skf_pf_ratio_workspace", "skf_pf_ratio", "skf_pfonly_c128_workspace",
-    "skf_pfonly_c128", "skf_logpf_c128_from_factors", "skf_refine_workspace",
+    "skf_pfonly_c128", "skf_logpf_c128_from_factors", "skf_ltlt_c128_workspace", "skf_ltlt_c128",
+    "skf_solve_c128_workspace", "skf_solve_c128", "skf_refine_workspace",
     "skf_solve_refine",
     "skf_batched_workspace", "skf_ltlt_batched", "skf_pfonly_batched", "skf_logpf_batched",
     "skf_solve_batched_workspace", "skf_solve_batched",
@@ -83,6 +84,10 @@ def _load():
                 "skf_pfonly_c128_workspace": (sz, [i64]),
                 "skf_pfonly_c128": (ci, [i64, vp, i64, vp, vp, vp, sz, vp, vp]),
                 "skf_logpf_c128_from_factors": (ci, [i64, vp, vp, vp, vp, vp]),
+                "skf_ltlt_c128_workspace": (sz, [i64]),
+                "skf_ltlt_c128": (ci, [i64, vp, i64, vp, vp, vp, sz, vp, vp]),
+                "skf_solve_c128_workspace": (sz, [i64, i64]),
+                "skf_solve_c128": (ci, [i64, i64, vp, i64, vp, vp, vp, i64, vp, sz, vp, vp]),
                 "skf_pf_ratio_workspace": (sz, [i64, i64]),
                 "skf_pf_ratio": (ci, [i64, i64, vp, i64, vp, vp, vp, i64, vp, i64, vp, vp, vp, sz, vp, vp]),
                 "skf_refine_workspace": (sz, [i64, i64]),
@@ -385,6 +390,44 @@ def pfonly_c128(A, ipiv=None, T=None, work=None, dinfo=None, stream=None):
                                  _stream(stream))
     _check(rc, "skf_pfonly_c128")
     return ipiv[:n], T[:max(n - 1, 0)], (rc if dinfo is None else dinfo)
+
+
+def ltlt_c128(A, ipiv=None, T=None, work=None, dinfo=None, stream=None):
+    """LTL^T of a complex128 skew matrix (column-major device tensor, strict lower
+    triangle read) in place: (ipiv, T, info) as :func:`ltlt`."""
+    torch = _torch()
+    n = A.shape[0]
+    lda = _ld(A)
+    dev = A.device
+    if A.dtype != torch.complex128:
+        raise ValueError("expected a complex128 tensor")
+    if ipiv is None:
+        ipiv = torch.empty(max(n, 1), dtype=torch.int32, device=dev)
+    if T is None:
+        T = torch.empty(max(n - 1, 1), dtype=torch.complex128, device=dev)
+    if work is None:
+        work = workspace(max(int(_load().skf_ltlt_c128_workspace(n)), 256), dev)
+    rc = _load().skf_ltlt_c128(n, _ptr(A), lda, _ptr(ipiv), _ptr(T), _ptr(work), work.numel(), _ptr(dinfo),
+                               _stream(stream))
+    _check(rc, "skf_ltlt_c128")
+    return ipiv[:n], T[:max(n - 1, 0)], (rc if dinfo is None else dinfo)
+
+
+def solve_c128(LT, ipiv, T, B, work=None, dinfo=None, stream=None):
+    """X = A^-1 B in place over B (complex128, column-major) with the factors of
+    :func:`ltlt_c128`; returns info (an int when ``dinfo`` is None)."""
+    torch = _torch()
+    n = LT.shape[0]
+    nrhs = B.shape[1] if B.dim() == 2 else 1
+    dev = LT.device
+    if work is None:
+        work = workspace(int(_load().skf_solve_c128_workspace(n, nrhs)), dev)
+    Tp = T if T.numel() > 0 else torch.zeros(1, dtype=torch.complex128, device=dev)
+    rc = _load().skf_solve_c128(n, nrhs, _ptr(LT), _ld(LT), _ptr(ipiv), _ptr(Tp), _ptr(B),
+                                _ld(B) if B.dim() == 2 else max(n, 1), _ptr(work), work.numel(), _ptr(dinfo),
+                                _stream(stream))
+    _check(rc, "skf_solve_c128")
+    return rc if dinfo is None else dinfo
 
 
 def logpf_c128_from_factors(n: int, ipiv, T, stream=None):
