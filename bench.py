@@ -344,6 +344,8 @@ def bench_complex(args):
                      "us_per_step": round(pms[0] * 1e3 / max(args.steps, 1) / max(n // 2, 1), 3),
                      "share": round(pms[0] / max(args.steps, 1) / ms, 3)},
            "logabs_pf": float(la.item()), "phase": [float(ph.real.item()), float(ph.imag.item())]}
+    if not args.no_side:
+        out["ltlt"] = _complex_ltlt_side(args, n, dA, lib)
     if not args.no_cpu_baseline:
         import oracle
         m = min(n, 1024)
@@ -354,6 +356,65 @@ def bench_complex(args):
                                "sample": f"numpy oracle on the n={m} leading case of the same recipe, {ct:.2f} s, "
                                          f"scaled by (n/{m})^3"}
     print(json.dumps(out), flush=True)
+
+
+def _complex_ltlt_side(args, n, dA, lib):
+    """The complex LTL^T of the same matrix (in place on a copy restored before
+    each timed call; HIP events around the call only) and the solve with its
+    factors for one right-hand side.  Nominal work: n unpaired complex rank-2
+    updates, 8 n^3 / 3 real flops."""
+    import ctypes
+
+    import numpy as np
+    import torch
+
+    from paper_2408_05238_amd import skf
+    dev = dA.device
+    if int(lib.skf_ltlt_c128_workspace(n)) == 0:
+        return {"skipped": "order beyond the complex LTL^T panel"}
+    work = skf.workspace(int(lib.skf_ltlt_c128_workspace(n)), dev)
+    ipiv = torch.empty(n, dtype=torch.int32, device=dev)
+    T = torch.empty(max(n - 1, 1), dtype=torch.complex128, device=dev)
+    dinfo = torch.zeros(1, dtype=torch.int32, device=dev)
+    W = dA.clone()
+    reps, times = max(1, min(args.steps, 5)), []
+    for r in range(reps + 1):
+        W.copy_(dA)
+        if r == reps:
+            lib.skf_profile_read(None, None, None, 1)
+            lib.skf_profile_enable(1)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        skf.ltlt_c128(W, ipiv, T, work, dinfo)
+        e1.record()
+        torch.cuda.synchronize()
+        if r > 0:
+            times.append(e0.elapsed_time(e1))
+    lib.skf_profile_enable(0)
+    pms = (ctypes.c_double * 2)()
+    pfl = (ctypes.c_double * 2)()
+    pcnt = (ctypes.c_int64 * 2)()
+    lib.skf_profile_read(pms, pfl, pcnt, 1)
+    assert int(dinfo.item()) == 0
+    ms = float(np.median(times))
+    b = torch.ones((n, 1), dtype=torch.complex128, device=dev)
+    B = skf.colmajor(n, 1, device=dev, dtype=torch.complex128)
+    swork = skf.workspace(int(lib.skf_solve_c128_workspace(n, 1)), dev)
+    st = []
+    for _ in range(3):
+        B.copy_(b)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        skf.solve_c128(W, ipiv, T, B, swork, dinfo)
+        e1.record()
+        torch.cuda.synchronize()
+        st.append(e0.elapsed_time(e1))
+    upd_tf = pfl[1] / (pms[1] * 1e-3) / 1e12 if pms[1] > 0 else 0.0
+    return {"ms": round(ms, 3), "gflops_nominal": round(8.0 * n ** 3 / 3.0 / (ms * 1e-3) / 1e9, 1),
+            "panel_us_per_step": round(pms[0] * 1e3 / max(n - 1, 1), 3),
+            "update_tflops": round(upd_tf, 3), "update_frac_fp64_peak": round(upd_tf / FP64_MFMA_PEAK_TFLOPS, 4),
+            "solve_ms_1rhs": round(float(np.median(st)), 3)}
 
 
 def bench_serve(args):
