@@ -202,15 +202,11 @@ __global__ void __launch_bounds__(256) update_kernel(int64_t n, int64_t k, c128*
 // dinfo: status if set; n for odd n; else 1 + the first even k with T[k] = 0, or 0.
 __global__ void info_c128_kernel(int64_t n, const c128* __restrict__ T, const int* __restrict__ status,
                                  int* __restrict__ dinfo) {
+  const int64_t z = first_zero_even_pivot(n, reinterpret_cast<const double*>(T), true);
   if (threadIdx.x != 0) return;
   int v = *status;
   if (v == 0 && (n & 1)) v = (int)n;
-  if (v == 0)
-    for (int64_t k = 0; k + 1 < n; k += 2)
-      if (T[k].re == 0.0 && T[k].im == 0.0) {
-        v = (int)(k + 1);
-        break;
-      }
+  if (v == 0 && z != INT64_MAX) v = (int)(z + 1);
   *dinfo = v;
 }
 
@@ -305,7 +301,7 @@ int run_pfonly_c128(int64_t n, const double* A, int64_t lda, int32_t* ipiv, doub
     }
   }
   if (dinfo) {
-    hipLaunchKernelGGL(info_c128_kernel, dim3(1), dim3(64), 0, s, n, Tc, w.status, dinfo);
+    hipLaunchKernelGGL(info_c128_kernel, dim3(1), dim3(256), 0, s, n, Tc, w.status, dinfo);
     SKF_CHECK_LAUNCH("c128 info");
   }
   return 0;

@@ -436,15 +436,11 @@ __global__ void split_kernel(int64_t n, const double* __restrict__ A, int64_t ld
 // dinfo: status if set; n for odd n; else 1 + the first even k with T[k] = 0, or 0.
 __global__ void cinfo_kernel(int64_t n, const double* __restrict__ T, const int* __restrict__ status,
                              int* __restrict__ dinfo) {
+  const int64_t z = first_zero_even_pivot(n, T, true);
   if (threadIdx.x != 0) return;
   int v = *status;
   if (v == 0 && (n & 1)) v = (int)n;
-  if (v == 0)
-    for (int64_t k = 0; k + 1 < n; k += 2)
-      if (T[2 * k] == 0.0 && T[2 * k + 1] == 0.0) {
-        v = (int)(k + 1);
-        break;
-      }
+  if (v == 0 && z != INT64_MAX) v = (int)(z + 1);
   *dinfo = v;
 }
 
@@ -829,14 +825,10 @@ __global__ void final_L_c128_kernel(int64_t n, int nb, const double* __restrict_
 // real factorization's rule: odd n completes, Pf = 0 follows from n).
 __global__ void cltlt_info_kernel(int64_t n, const double* __restrict__ T, const int* __restrict__ status,
                                   int* __restrict__ dinfo) {
+  const int64_t z = first_zero_even_pivot(n, T, true);
   if (threadIdx.x != 0) return;
   int v = *status;
-  if (v == 0)
-    for (int64_t k = 0; k + 1 < n; k += 2)
-      if (T[2 * k] == 0.0 && T[2 * k + 1] == 0.0) {
-        v = (int)(k + 1);
-        break;
-      }
+  if (v == 0 && z != INT64_MAX) v = (int)(z + 1);
   *dinfo = v;
 }
 
@@ -1026,7 +1018,7 @@ int run_pfonly_c128_blocked(int64_t n, const double* A, int64_t lda, int32_t* ip
     }
   }
   if (dinfo) {
-    hipLaunchKernelGGL(cinfo_kernel, dim3(1), dim3(64), 0, s, n, T, w.status, dinfo);
+    hipLaunchKernelGGL(cinfo_kernel, dim3(1), dim3(256), 0, s, n, T, w.status, dinfo);
     SKF_CHECK_LAUNCH("complex info");
   }
   return 0;
@@ -1122,7 +1114,7 @@ int run_ltlt_c128(int64_t n, double* A, int64_t lda, int32_t* ipiv, double* T, v
     SKF_CHECK_LAUNCH("complex final L");
   }
   if (dinfo) {
-    hipLaunchKernelGGL(cltlt_info_kernel, dim3(1), dim3(64), 0, s, n, T, w.status, dinfo);
+    hipLaunchKernelGGL(cltlt_info_kernel, dim3(1), dim3(256), 0, s, n, T, w.status, dinfo);
     SKF_CHECK_LAUNCH("complex ltlt info");
   }
   return 0;

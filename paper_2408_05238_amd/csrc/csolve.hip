@@ -10,8 +10,9 @@
 //           of four right-hand sides, the 64 x 64 block of L read once);
 //   T⁻¹     Gaussian elimination with partial pivoting on the tridiagonal
 //           T(k+1, k) = T[k], T(k, k+1) = -T[k]: the pivot choices depend on T
-//           only, so one thread records them (multipliers and the U bands),
-//           then one lane per right-hand side applies them and back-substitutes;
+//           only, so they are recorded once (multipliers and the U bands), then
+//           one workgroup per right-hand side applies them and back-substitutes
+//           (each chain on one thread over chunks staged in LDS);
 //   L⁻ᵀ     by blocks from the last: the transposed diagonal block by one
 //           workgroup, then every block above subtracts L[I, J]ᵀ Y_I;
 //   scatter B[perm[i], :] = Y[i, :].
@@ -72,192 +73,267 @@ __global__ void cscatter_kernel(int64_t n, int64_t nr, const int32_t* __restrict
     st2(B, perm[i] + c * ldb, ld2(Y, i + c * n));
 }
 
-// Diagonal block J, forward: Y_J := L_JJ^{-1} Y_J.  Thread (r, c): row j0+r of
-// right-hand side c0+c; column sweep, the final y_j published through LDS.
+// The 64 x 64 block L[I0 .. I0+63, J0 .. J0+63] (zero outside the strict lower
+// part of L, rows past n zero) into LDS, by the whole workgroup in one round
+// trip: lb[j][r] = L[I0 + r, J0 + j].
+__device__ inline void stage_block(z2 (*lb)[kBs + 1], const double* __restrict__ LT, int64_t lda, int64_t n, int64_t I0,
+                                   int64_t J0) {
+  for (int e = threadIdx.x; e < kBs * kBs; e += blockDim.x) {
+    const int r = e % kBs, j = e / kBs;
+    const int64_t i = I0 + r, jj = J0 + j;
+    lb[j][r] = (i < n && jj < n && i > jj) ? lij(LT, lda, i, jj) : z2{0.0, 0.0};
+  }
+}
+
+// Diagonal block J, forward: Y_J := L_JJ^{-1} Y_J.  Wave c takes right-hand side
+// c0 + c, lane r row j0 + r; the final y_j is broadcast by readlane (no barrier).
 __global__ void __launch_bounds__(kBs* kRc) cdiag_fwd_kernel(int64_t n, int64_t nr, const double* __restrict__ LT,
                                                              int64_t lda, double* __restrict__ Y, int64_t j0) {
-  __shared__ z2 yj[kRc];
+  __shared__ z2 lb[kBs][kBs + 1];  // padded: column reads (lb[r][t]) stay conflict-free
+  stage_block(lb, LT, lda, n, j0, j0);
+  __syncthreads();
   const int r = threadIdx.x % kBs, c = threadIdx.x / kBs;
   const int64_t i = j0 + r, col = (int64_t)blockIdx.x * kRc + c;
+  if (col >= nr) return;  // a whole wave
   const int m = (int)min((int64_t)kBs, n - j0);
-  const bool act = r < m && col < nr;
-  z2 y = act ? ld2(Y, i + col * n) : z2{0.0, 0.0};
+  z2 y = (r < m) ? ld2(Y, i + col * n) : z2{0.0, 0.0};
   for (int j = 0; j < m - 1; ++j) {
-    if (r == j) yj[c] = y;
-    __syncthreads();
-    if (act && r > j) y = zsub(y, zmul(lij(LT, lda, i, j0 + j), yj[c]));
-    __syncthreads();
+    const z2 yj = {__shfl(y.re, j), __shfl(y.im, j)};
+    if (r > j) y = zsub(y, zmul(lb[j][r], yj));
   }
-  if (act) st2(Y, i + col * n, y);
+  if (r < m) st2(Y, i + col * n, y);
 }
 
 // Blocks below J: Y_I -= L[I, J] Y_J, one workgroup per block row I and group of
-// kRc right-hand sides; Y_J staged in LDS, L read column by column (coalesced).
+// kRc right-hand sides; the block of L and Y_J staged in LDS.
 __global__ void __launch_bounds__(kBs* kRc) cupdate_fwd_kernel(int64_t n, int64_t nr, const double* __restrict__ LT,
                                                                int64_t lda, double* __restrict__ Y, int64_t j0) {
+  __shared__ z2 lb[kBs][kBs + 1];  // padded: column reads (lb[r][t]) stay conflict-free
   __shared__ z2 ys[kRc][kBs];
   const int r = threadIdx.x % kBs, c = threadIdx.x / kBs;
   const int64_t i0 = j0 + kBs * (1 + (int64_t)blockIdx.x), i = i0 + r;
   const int64_t col = (int64_t)blockIdx.y * kRc + c;
   const int m = (int)min((int64_t)kBs, n - j0);
+  stage_block(lb, LT, lda, n, i0, j0);
   ys[c][r] = (r < m && col < nr) ? ld2(Y, j0 + r + col * n) : z2{0.0, 0.0};
   __syncthreads();
   if (i >= n || col >= nr) return;
   z2 acc = ld2(Y, i + col * n);
-  for (int j = 0; j < m; ++j) acc = zsub(acc, zmul(lij(LT, lda, i, j0 + j), ys[c][j]));
+  for (int j = 0; j < m; ++j) acc = zsub(acc, zmul(lb[j][r], ys[c][j]));
   st2(Y, i + col * n, acc);
 }
 
 // Diagonal block J, backward: Y_J := L_JJ^{-T} Y_J (x_j final from the last row
-// up; x_i -= L[j, i] x_j for i < j inside the block).
+// up; x_i -= L[j, i] x_j for i < j inside the block), one wave per right-hand side.
 __global__ void __launch_bounds__(kBs* kRc) cdiag_bwd_kernel(int64_t n, int64_t nr, const double* __restrict__ LT,
                                                              int64_t lda, double* __restrict__ Y, int64_t j0) {
-  __shared__ z2 xj[kRc];
+  __shared__ z2 lb[kBs][kBs + 1];  // padded: column reads (lb[r][t]) stay conflict-free
+  stage_block(lb, LT, lda, n, j0, j0);
+  __syncthreads();
   const int r = threadIdx.x % kBs, c = threadIdx.x / kBs;
   const int64_t i = j0 + r, col = (int64_t)blockIdx.x * kRc + c;
+  if (col >= nr) return;  // a whole wave
   const int m = (int)min((int64_t)kBs, n - j0);
-  const bool act = r < m && col < nr;
-  z2 y = act ? ld2(Y, i + col * n) : z2{0.0, 0.0};
+  z2 y = (r < m) ? ld2(Y, i + col * n) : z2{0.0, 0.0};
   for (int j = m - 1; j >= 1; --j) {
-    if (r == j) xj[c] = y;
-    __syncthreads();
-    if (act && r < j) y = zsub(y, zmul(lij(LT, lda, j0 + j, i), xj[c]));
-    __syncthreads();
+    const z2 xj = {__shfl(y.re, j), __shfl(y.im, j)};
+    if (r < j) y = zsub(y, zmul(lb[r][j], xj));  // L[j0 + j, j0 + r] = lb[r][j]
   }
-  if (act) st2(Y, i + col * n, y);
+  if (r < m) st2(Y, i + col * n, y);
 }
 
 // Blocks above I: Y_J -= L[I, J]^T Y_I for every block J < I: thread (r, c)
-// forms column j0+r's sum over the rows of block I, in row order.
+// forms column j0+r's sum over the rows of block I, in row order; the block of
+// L and Y_I staged in LDS.
 __global__ void __launch_bounds__(kBs* kRc) cupdate_bwd_kernel(int64_t n, int64_t nr, const double* __restrict__ LT,
                                                                int64_t lda, double* __restrict__ Y, int64_t i0) {
+  __shared__ z2 lb[kBs][kBs + 1];  // padded: column reads (lb[r][t]) stay conflict-free
   __shared__ z2 ys[kRc][kBs];
   const int r = threadIdx.x % kBs, c = threadIdx.x / kBs;
   const int64_t j0 = kBs * (int64_t)blockIdx.x, j = j0 + r;
   const int64_t col = (int64_t)blockIdx.y * kRc + c;
   const int m = (int)min((int64_t)kBs, n - i0);
+  stage_block(lb, LT, lda, n, i0, j0);
   ys[c][r] = (r < m && col < nr) ? ld2(Y, i0 + r + col * n) : z2{0.0, 0.0};
   __syncthreads();
   if (col >= nr) return;
   z2 acc = ld2(Y, j + col * n);
-  for (int t = 0; t < m; ++t) acc = zsub(acc, zmul(lij(LT, lda, i0 + t, j), ys[c][t]));
+  for (int t = 0; t < m; ++t) acc = zsub(acc, zmul(lb[r][t], ys[c][t]));  // L[i0 + t, j0 + r]
   st2(Y, j + col * n, acc);
 }
 
-// The tridiagonal's elimination with partial pivoting (one thread): per row i
-// the choice sw[i] (row i+1 taken as pivot row), the multiplier f[i], and the U
-// bands dd, du, du2; status = the first zero pivot (1-based) or 0.
-__global__ void ctri_factor_kernel(int64_t n, const double* __restrict__ T, double* __restrict__ dd,
-                                   double* __restrict__ du, double* __restrict__ du2, double* __restrict__ f,
-                                   int32_t* __restrict__ sw, int* __restrict__ status) {
-  if (threadIdx.x != 0 || blockIdx.x != 0 || *status != 0) return;
-  z2 cd = {0.0, 0.0};                                   // running diagonal of row i
-  z2 cu = (n > 1) ? z2{-T[0], -T[1]} : z2{0.0, 0.0};    // running super entry of row i
-  for (int64_t i = 0; i + 1 < n; ++i) {
-    const z2 dl = ld2(T, i);
-    z2 nd = {0.0, 0.0};
-    z2 nu = (i + 2 < n) ? z2{-T[2 * (i + 1)], -T[2 * (i + 1) + 1]} : z2{0.0, 0.0};
-    if (zn2(cd) >= zn2(dl)) {
-      if (cd.re == 0.0 && cd.im == 0.0) {
-        *status = (int)(i + 1);
-        return;
+// The tridiagonal's elimination with partial pivoting: per row i the choice
+// sw[i] (row i+1 taken as pivot row), the multiplier f[i] and the U bands dd,
+// du, du2; status = the first zero pivot (1-based) if it meets one.  The chain
+// runs on thread 0 over chunks of kCh rows staged in LDS by the whole
+// workgroup (one load round trip and one store round trip per chunk).
+constexpr int kCh = 512;
+
+__global__ void __launch_bounds__(256) ctri_factor_kernel(int64_t n, const double* __restrict__ T,
+                                                          double* __restrict__ dd, double* __restrict__ du,
+                                                          double* __restrict__ du2, double* __restrict__ f,
+                                                          int32_t* __restrict__ sw, int* __restrict__ status) {
+  __shared__ z2 tch[kCh + 1];
+  __shared__ z2 o_dd[kCh], o_du[kCh], o_du2[kCh], o_f[kCh];
+  __shared__ int o_sw[kCh];
+  __shared__ int stop;
+  const int t = threadIdx.x;
+  if (*status != 0) return;  // singular T found before (uniform)
+  if (t == 0) stop = 0;
+  z2 cd = {0.0, 0.0};                                 // running diagonal of row i (thread 0)
+  z2 cu = (n > 1) ? ld2(T, 0) : z2{0.0, 0.0};         // running super entry of row i
+  cu = zsub(z2{0.0, 0.0}, cu);
+  for (int64_t c0 = 0; c0 < n - 1; c0 += kCh) {
+    const int cnt = (int)min((int64_t)kCh, n - 1 - c0);
+    const int nld = (int)min((int64_t)cnt + 1, n - 1 - c0);  // T[c0 .. c0 + cnt] where it exists
+    for (int e = t; e < nld; e += blockDim.x) tch[e] = ld2(T, c0 + e);
+    __syncthreads();
+    if (t == 0) {
+      for (int e = 0; e < cnt; ++e) {
+        const int64_t i = c0 + e;
+        const z2 dl = tch[e];
+        z2 nd = {0.0, 0.0};
+        z2 nu = (i + 2 < n) ? zsub(z2{0.0, 0.0}, tch[e + 1]) : z2{0.0, 0.0};
+        if (zn2(cd) >= zn2(dl)) {
+          if (cd.re == 0.0 && cd.im == 0.0) {
+            *status = (int)(i + 1);
+            stop = 1;
+            break;
+          }
+          const z2 fm = zdiv(dl, cd);
+          nd = zsub(nd, zmul(fm, cu));
+          o_dd[e] = cd;
+          o_du[e] = cu;
+          o_du2[e] = z2{0.0, 0.0};
+          o_f[e] = fm;
+          o_sw[e] = 0;
+        } else {
+          const z2 fm = zdiv(cd, dl);
+          const z2 tt = nd;
+          o_dd[e] = dl;
+          o_du[e] = tt;
+          const z2 nd2 = zsub(cu, zmul(fm, tt));
+          z2 u2 = {0.0, 0.0};
+          if (i + 2 < n) {
+            u2 = nu;
+            nu = zsub(z2{0.0, 0.0}, zmul(fm, u2));
+          }
+          o_du2[e] = u2;
+          o_f[e] = fm;
+          o_sw[e] = 1;
+          nd = nd2;
+        }
+        cd = nd;
+        cu = nu;
       }
-      const z2 fm = zdiv(dl, cd);
-      nd = zsub(nd, zmul(fm, cu));
-      st2(dd, i, cd);
-      st2(du, i, cu);
-      st2(du2, i, z2{0.0, 0.0});
-      st2(f, i, fm);
-      sw[i] = 0;
-    } else {
-      const z2 fm = zdiv(cd, dl);
-      const z2 t = nd;
-      st2(dd, i, dl);
-      st2(du, i, t);
-      const z2 nd2 = zsub(cu, zmul(fm, t));
-      z2 u2 = {0.0, 0.0};
-      if (i + 2 < n) {
-        u2 = nu;
-        nu = zsub(z2{0.0, 0.0}, zmul(fm, u2));
-      }
-      st2(du2, i, u2);
-      st2(f, i, fm);
-      sw[i] = 1;
-      nd = nd2;
     }
-    cd = nd;
-    cu = nu;
+    __syncthreads();
+    if (stop) return;
+    for (int e = t; e < cnt; e += blockDim.x) {
+      st2(dd, c0 + e, o_dd[e]);
+      st2(du, c0 + e, o_du[e]);
+      st2(du2, c0 + e, o_du2[e]);
+      st2(f, c0 + e, o_f[e]);
+      sw[c0 + e] = o_sw[e];
+    }
+    __syncthreads();
   }
-  if (cd.re == 0.0 && cd.im == 0.0) {
-    *status = (int)n;
-    return;
+  if (t == 0) {
+    if (cd.re == 0.0 && cd.im == 0.0) *status = (int)n;
+    else st2(dd, n - 1, cd);
   }
-  st2(dd, n - 1, cd);
 }
 
-// One lane per right-hand side: the recorded elimination, then back substitution.
-__global__ void ctri_apply_kernel(int64_t n, int64_t nr, const double* __restrict__ dd, const double* __restrict__ du,
-                                  const double* __restrict__ du2, const double* __restrict__ f,
-                                  const int32_t* __restrict__ sw, const int* __restrict__ status,
-                                  double* __restrict__ Y) {
-  const int64_t col = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (col >= nr || *status != 0) return;
-  double* y = Y + 2 * col * n;
+// One workgroup per right-hand side: the recorded elimination, then back
+// substitution, each chained on thread 0 over chunks staged in LDS.
+__global__ void __launch_bounds__(256) ctri_apply_kernel(int64_t n, const double* __restrict__ dd,
+                                                         const double* __restrict__ du,
+                                                         const double* __restrict__ du2,
+                                                         const double* __restrict__ f,
+                                                         const int32_t* __restrict__ sw,
+                                                         const int* __restrict__ status, double* __restrict__ Y) {
+  __shared__ z2 a[kCh + 1], b[kCh], c[kCh], d[kCh];
+  __shared__ int w[kCh];
+  const int t = threadIdx.x;
+  if (*status != 0) return;
+  double* __restrict__ y = Y + 2 * (int64_t)blockIdx.x * n;
+  // forward: rows c0 .. c0 + cnt - 1; a = y[c0 + 1 ..] (as yet untouched), b = f, w = choices, c = output
   z2 cb = ld2(y, 0);
-  for (int64_t i = 0; i + 1 < n; ++i) {
-    const z2 nb = ld2(y, i + 1);
-    const z2 fm = ld2(f, i);
-    if (sw[i] == 0) {
-      st2(y, i, cb);
-      cb = zsub(nb, zmul(fm, cb));
-    } else {
-      st2(y, i, nb);
-      cb = zsub(cb, zmul(fm, nb));
+  for (int64_t c0 = 0; c0 < n - 1; c0 += kCh) {
+    const int cnt = (int)min((int64_t)kCh, n - 1 - c0);
+    for (int e = t; e < cnt; e += blockDim.x) {
+      a[e] = ld2(y, c0 + 1 + e);
+      b[e] = ld2(f, c0 + e);
+      w[e] = sw[c0 + e];
     }
+    __syncthreads();
+    if (t == 0)
+      for (int e = 0; e < cnt; ++e) {
+        const z2 nb = a[e];
+        if (w[e] == 0) {
+          c[e] = cb;
+          cb = zsub(nb, zmul(b[e], cb));
+        } else {
+          c[e] = nb;
+          cb = zsub(cb, zmul(b[e], nb));
+        }
+      }
+    __syncthreads();
+    for (int e = t; e < cnt; e += blockDim.x) st2(y, c0 + e, c[e]);
+    __syncthreads();
   }
-  // back substitution with the bands dd, du, du2
-  z2 xb = zdiv(cb, ld2(dd, n - 1));
-  st2(y, n - 1, xb);
-  if (n >= 2) {
-    z2 xa = zdiv(zsub(ld2(y, n - 2), zmul(ld2(du, n - 2), xb)), ld2(dd, n - 2));
-    st2(y, n - 2, xa);
-    for (int64_t i = n - 3; i >= 0; --i) {
-      const z2 xi = zdiv(zsub(zsub(ld2(y, i), zmul(ld2(du, i), xa)), zmul(ld2(du2, i), xb)), ld2(dd, i));
-      st2(y, i, xi);
-      xb = xa;
-      xa = xi;
+  // back substitution from the last row: x[i] = (y[i] - du[i] x[i+1] - du2[i] x[i+2]) / dd[i]
+  z2 xa = {0.0, 0.0}, xb = {0.0, 0.0};  // x[i+1], x[i+2] (thread 0)
+  if (t == 0) {
+    xa = zdiv(cb, ld2(dd, n - 1));
+    st2(y, n - 1, xa);
+  }
+  for (int64_t c1 = n - 1; c1 > 0; c1 -= kCh) {  // rows c1 - cnt .. c1 - 1
+    const int cnt = (int)min((int64_t)kCh, c1);
+    const int64_t r0 = c1 - cnt;
+    for (int e = t; e < cnt; e += blockDim.x) {
+      a[e] = ld2(y, r0 + e);
+      b[e] = ld2(dd, r0 + e);
+      c[e] = ld2(du, r0 + e);
+      d[e] = ld2(du2, r0 + e);
     }
+    __syncthreads();
+    if (t == 0)
+      for (int e = cnt - 1; e >= 0; --e) {
+        const int64_t i = r0 + e;
+        const z2 num = (i == n - 2) ? zsub(a[e], zmul(c[e], xa)) : zsub(zsub(a[e], zmul(c[e], xa)), zmul(d[e], xb));
+        const z2 xi = zdiv(num, b[e]);
+        a[e] = xi;
+        xb = xa;
+        xa = xi;
+      }
+    __syncthreads();
+    for (int e = t; e < cnt; e += blockDim.x) st2(y, r0 + e, a[e]);
+    __syncthreads();
   }
 }
 
 // info: n for odd n; else 1 + the first even k with T[k] = 0; else the
 // elimination's own zero pivot; else 0.
-__global__ void csolve_info_kernel(int64_t n, const double* __restrict__ T, const int* __restrict__ status,
-                                   int* __restrict__ dinfo) {
+__global__ void __launch_bounds__(256) csolve_info_kernel(int64_t n, const double* __restrict__ T,
+                                                          const int* __restrict__ status, int* __restrict__ dinfo) {
+  const int64_t z = first_zero_even_pivot(n, T, true);
   if (threadIdx.x != 0) return;
   int v = 0;
   if (n % 2 == 1) v = (int)n;
-  if (v == 0)
-    for (int64_t k = 0; k + 1 < n; k += 2)
-      if (T[2 * k] == 0.0 && T[2 * k + 1] == 0.0) {
-        v = (int)(k + 1);
-        break;
-      }
+  if (v == 0 && z != INT64_MAX) v = (int)(z + 1);
   if (v == 0 && status) v = *status;
   *dinfo = v;
 }
 
-// First even zero pivot (or odd n) into status before anything else runs, so
-// the tridiagonal and triangular steps are skipped for a singular T.
-__global__ void csolve_precheck_kernel(int64_t n, const double* __restrict__ T, int* __restrict__ status) {
+// Odd n or a zero even pivot into status before anything else runs, so the
+// tridiagonal steps and the scatter are skipped for a singular T.
+__global__ void __launch_bounds__(256) csolve_precheck_kernel(int64_t n, const double* __restrict__ T,
+                                                              int* __restrict__ status) {
+  const int64_t z = first_zero_even_pivot(n, T, true);
   if (threadIdx.x != 0) return;
   int v = (n % 2 == 1) ? (int)n : 0;
-  if (v == 0)
-    for (int64_t k = 0; k + 1 < n; k += 2)
-      if (T[2 * k] == 0.0 && T[2 * k + 1] == 0.0) {
-        v = (int)(k + 1);
-        break;
-      }
+  if (v == 0 && z != INT64_MAX) v = (int)(z + 1);
   *status = v;
 }
 
@@ -301,7 +377,7 @@ int run_solve_c128(int64_t n, int64_t nrhs, const double* LT, int64_t lda, const
   if (n == 0) return dinfo ? launch_fill_i32(dinfo, 1, 0, s) : 0;
   if (nrhs > 65535 * (int64_t)kRc) return SKF_ENOTIMPL;
   int rc;
-  hipLaunchKernelGGL(csolve_precheck_kernel, dim3(1), dim3(64), 0, s, n, T, w.status);
+  hipLaunchKernelGGL(csolve_precheck_kernel, dim3(1), dim3(256), 0, s, n, T, w.status);
   SKF_CHECK_LAUNCH("csolve precheck");
   if (n % 2 == 0 && nrhs > 0) {
     // a singular T (found on the device) leaves B as it is: the tridiagonal
@@ -323,10 +399,10 @@ int run_solve_c128(int64_t n, int64_t nrhs, const double* LT, int64_t lda, const
         SKF_CHECK_LAUNCH("csolve update fwd");
       }
     }
-    hipLaunchKernelGGL(ctri_factor_kernel, dim3(1), dim3(64), 0, s, n, T, w.dd, w.du, w.du2, w.f, w.sw, w.status);
+    hipLaunchKernelGGL(ctri_factor_kernel, dim3(1), dim3(256), 0, s, n, T, w.dd, w.du, w.du2, w.f, w.sw, w.status);
     SKF_CHECK_LAUNCH("csolve tri factor");
-    hipLaunchKernelGGL(ctri_apply_kernel, dim3((unsigned)((nrhs + 63) / 64)), dim3(64), 0, s, n, nrhs, w.dd, w.du,
-                       w.du2, w.f, w.sw, w.status, w.Y);
+    hipLaunchKernelGGL(ctri_apply_kernel, dim3((unsigned)nrhs), dim3(256), 0, s, n, w.dd, w.du, w.du2, w.f, w.sw,
+                       w.status, w.Y);
     SKF_CHECK_LAUNCH("csolve tri apply");
     for (int64_t I = nbk - 1; I >= 0; --I) {
       const int64_t i0 = I * kBs;
@@ -343,7 +419,7 @@ int run_solve_c128(int64_t n, int64_t nrhs, const double* LT, int64_t lda, const
     SKF_CHECK_LAUNCH("csolve scatter");
   }
   if (dinfo) {
-    hipLaunchKernelGGL(csolve_info_kernel, dim3(1), dim3(64), 0, s, n, T, w.status, dinfo);
+    hipLaunchKernelGGL(csolve_info_kernel, dim3(1), dim3(256), 0, s, n, T, w.status, dinfo);
     SKF_CHECK_LAUNCH("csolve info");
   }
   return 0;

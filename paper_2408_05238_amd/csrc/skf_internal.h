@@ -54,6 +54,31 @@ __device__ inline void poll_refresh(int it) {
   if (kEveryRound || (it & 7) == 7) __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
 }
 
+// First even k (k + 1 < n) with T[k] == 0 -- complex interleaved T when cplx --
+// found by the whole workgroup (blockDim.x a multiple of 64, at most 1024);
+// INT64_MAX when there is none.  Every thread gets the result.
+__device__ inline int64_t first_zero_even_pivot(int64_t n, const double* __restrict__ T, bool cplx) {
+  __shared__ int64_t red[16];
+  int64_t b = INT64_MAX;
+  for (int64_t k = 2 * (int64_t)threadIdx.x; k + 1 < n; k += 2 * (int64_t)blockDim.x) {
+    const bool z = cplx ? (T[2 * k] == 0.0 && T[2 * k + 1] == 0.0) : (T[k] == 0.0);
+    if (z) {
+      b = k;
+      break;
+    }
+  }
+  for (int s = 32; s >= 1; s >>= 1) {
+    const int64_t o = __shfl_xor(b, s);
+    b = o < b ? o : b;
+  }
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = b;
+  __syncthreads();
+  int64_t r = INT64_MAX;
+  for (unsigned w = 0; w < (blockDim.x + 63) / 64; ++w) r = red[w] < r ? red[w] : r;
+  __syncthreads();
+  return r;
+}
+
 // Tuning table (tune.hip)
 int tune_lookup(int param, int64_t n);
 int tune_set(int param, int64_t lo, int64_t hi, int value);
