@@ -18,12 +18,12 @@
 namespace skf {
 
 // The panel kernel is one wave per workgroup with 64 row slots; LDS holds the
-// (nb/2) x 64 pair vectors per workgroup (97 KB at nb = 128, 49 KB at 64, 24 KB
-// at 32, 12 KB at 16), so a CU hosts one, three, six or twelve of them (the
-// occupancy query decides, registers and wave slots included).  Every
+// (nb/2) x 64 pair vectors per workgroup (65 KB at nb = 128, 33 KB at 64, 17 KB
+// at 32, 9 KB at 16), so a CU hosts two, four, six or six of them (the LDS
+// bound, the occupancy query and the cap of six per CU decide).  Every
 // workgroup of a panel launch must be resident together, so the narrower
-// widths carry larger orders: up to 256, 768, 1536 and 2048 workgroups of 64
-// rows on 256 CUs.
+// widths carry larger orders: up to 512, 1024 and 1536 workgroups of 64 rows
+// on 256 CUs.
 static constexpr int kMaxPanelG = 2048;
 
 static int slots() { return panel_slots(); }

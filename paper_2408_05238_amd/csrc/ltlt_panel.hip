@@ -48,7 +48,6 @@ namespace {
 template <int NB>
 struct PanelSmem {
   double2 LW[NB / 2][64];  // (l', w) of each pair, per slot
-  double Le[NB / 2][64];   // l of each pair's first step, per slot
   double2 coef[NB / 2];    // the pivot row's (l', w) of the pairs so far
 };
 
@@ -77,9 +76,13 @@ __global__ void __launch_bounds__(kPanelThreads) panel_kernel(PanelParams P) {
 
   for (int q = 0; q < NP; ++q) {
     sm.LW[q][lane] = make_double2(0.0, 0.0);
-    sm.Le[q][lane] = 0.0;
   }
   if (lane < NP) sm.coef[lane] = make_double2(0.0, 0.0);
+  // l of each pair's first step, per slot, kept in global scratch (slot-major,
+  // one coalesced line per pair) rather than LDS, so two workgroups of the
+  // widest panel fit one CU
+  double* const my_le = P.Lscr + (size_t)g * 64 + lane;
+  const size_t le_stride = (size_t)G * 64;
 
   int32_t psi = mine ? (int32_t)(rowbase + lane) : INT32_MAX;
   const int32_t hbm = mine ? (int32_t)(rowbase + lane) : 0;
@@ -88,7 +91,7 @@ __global__ void __launch_bounds__(kPanelThreads) panel_kernel(PanelParams P) {
   // the loop head and, vmcnt counting stores too, made every step wait for the
   // previous step's mirror and record stores
   asm volatile("" : "+v"(cur));
-  double lj = 0.0;  // this slot's l of the current pair (register copy of sm.Le[j][lane])
+  double lj = 0.0;  // this slot's l of the current pair
   int stop = 0;
 
   for (int si = 0; si < P.nsteps; ++si) {
@@ -271,10 +274,7 @@ __global__ void __launch_bounds__(kPanelThreads) panel_kernel(PanelParams P) {
         if (psi >= k + 2) val = (alpha != 0.0) ? cur / alpha : 0.0;
         else if (psi == (int32_t)r) val = alpha;
         else wr = false;
-        if (wr) {
-          if (ph == 0) sm.Le[j][lane] = val;
-          else sm.LW[j][lane].x = val;
-        }
+        if (wr && ph == 1) sm.LW[j][lane].x = val;
         if (ph == 0) lj = wr ? val : 0.0;
       }
       uint64_t t0 = 0;
@@ -351,6 +351,7 @@ __global__ void __launch_bounds__(kPanelThreads) panel_kernel(PanelParams P) {
     // finish the column
     if (ph == 0) {
       if (below) cur = gat + corr;
+      if (mine) my_le[(size_t)j * le_stride] = lj;
     } else {
       const double w = below ? gat + corr : 0.0;
       sm.LW[j][lane].y = w;
@@ -379,7 +380,7 @@ __global__ void __launch_bounds__(kPanelThreads) panel_kernel(PanelParams P) {
   const int npairs = P.nsteps / 2;
   const int64_t lo = k0 + P.nsteps;
   for (int c = 0; c < P.nsteps; ++c)
-    P.Lbuf[psi + (int64_t)c * n] = (c & 1) ? sm.LW[c >> 1][lane].x : sm.Le[c >> 1][lane];
+    P.Lbuf[psi + (int64_t)c * n] = (c & 1) ? sm.LW[c >> 1][lane].x : my_le[(size_t)(c >> 1) * le_stride];
   // the pair vectors are the trailing update's operands; row lo is stored as
   // zero, so the update leaves column lo (the next panel's first column, taken
   // from cnext as it stands) without products
@@ -846,6 +847,6 @@ int panel_wgs_per_cu(int nb, bool pf) {
   return c;
 }
 
-size_t panel_scratch_doubles(int, int) { return 0; }
+size_t panel_scratch_doubles(int G, int nb) { return (size_t)(nb / 2) * G * 64; }
 
 }  // namespace skf

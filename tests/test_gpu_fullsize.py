@@ -1,7 +1,8 @@
 """Parity at the full benchmark sizes: n = 16384 FP64 with seeds 2, 3 and 4, in
 the launch configuration bench.py times (skf.ltlt, default block size), seed 2
 again with the narrow panel (nb = 64), and the n = 32768 matrix of the mixed
-precision workload (seed 5, nb = 64 with 512 panel workgroups).
+precision workload (seed 5) at both widths: nb = 128 (512 panel workgroups, two
+per CU: the tuned choice) and nb = 64 (512 workgroups of the narrow panel).
 
 The reference is the oracle's own result for the same seeded input, stored in
 tests/golden/ltlt_n16384_s{seed}.npz by tests/golden/make_golden.py (which calls
@@ -52,14 +53,14 @@ def _apply_P(x, ipiv, transpose=False):
     return x
 
 
-CASES = [(N, 2, None), (N, 3, None), (N, 4, None), (N, 2, "64"), (32768, 5, None)]
+CASES = [(N, 2, None), (N, 3, None), (N, 4, None), (N, 2, "64"), (32768, 5, None), (32768, 5, "64")]
 
 
 @pytest.mark.parametrize("n,seed,nb", CASES, ids=[f"n{c[0]}-s{c[1]}-nb{c[2] or 'auto'}" for c in CASES])
 def test_ltlt_fullsize_against_stored_oracle(skf, n, seed, nb, monkeypatch):
     """n = 16384 in the launch configuration bench.py times (nb = 128, 256 panel
-    workgroups), the same matrix with the narrow panel (nb = 64: 256 workgroups,
-    two per CU), and n = 32768 (nb = 64, 512 workgroups)."""
+    workgroups), the same matrix with the narrow panel (nb = 64: 256 workgroups),
+    and n = 32768 (512 workgroups) at nb = 128 and nb = 64."""
     import torch
     import oracle
     from paper_2408_05238_amd import inputs

@@ -29,14 +29,15 @@ def _write(tmp_path, entries):
 def test_builtin_rules_without_table(skf):
     assert skf.load_tuning(path="off") == 0
     assert skf.tune_get("ltlt_nb", 16384) == 128      # 256 panel workgroups fit one per CU
-    assert skf.tune_get("ltlt_nb", 32768) == 64       # 512 workgroups: two per CU only at width 64
+    assert skf.tune_get("ltlt_nb", 32768) == 128      # 512 workgroups: two per CU at width 128
     assert skf.tune_get("pfonly_nb", 1000) == 128
     assert skf.tune_get("skr2k_band", 16384) == 8
     # wider orders take the narrower panels (more of their workgroups fit a CU;
-    # here without a device: by LDS alone, 1 / 3 / 6 per CU on 256 CUs, and at
-    # most six per CU for any width)
+    # here without a device: by LDS alone, 2 / 4 / 6 / 6 per CU at widths
+    # 128 / 64 / 32 / 16 on 256 CUs, at most six per CU for any width)
     assert skf.tune_get("ltlt_nb", 40000) == 64
-    assert skf.tune_get("ltlt_nb", 60000) == 32
+    assert skf.tune_get("ltlt_nb", 65537) == 64       # 1024 workgroups
+    assert skf.tune_get("ltlt_nb", 65538) == 32
     assert skf.tune_get("ltlt_nb", 98305) == 32       # 1536 workgroups
     assert skf.tune_get("ltlt_nb", 98306) == 0        # no width fits
     assert skf.tune_get("pfonly_nb", 98305) == 32
@@ -62,7 +63,7 @@ def test_table_entries_and_precedence(skf, tmp_path):
 
 def test_infeasible_entry_is_ignored_and_env_overrides(skf, tmp_path, monkeypatch):
     skf.load_tuning(_write(tmp_path, [{"param": "ltlt_nb", "n_lo": 0, "n_hi": 10 ** 9, "value": 128}]))
-    assert skf.tune_get("ltlt_nb", 30000) == 64       # 469 workgroups of width 128 cannot be resident
+    assert skf.tune_get("ltlt_nb", 40000) == 64       # 625 workgroups of width 128 cannot be resident
     monkeypatch.setenv("SKF_NB", "64")
     assert skf.tune_get("ltlt_nb", 1000) == 64
     assert skf.tune_get("pfonly_nb", 1000) == 64
