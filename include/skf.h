@@ -200,7 +200,7 @@ int skf_solve(skf_int n, skf_int nrhs, const double* LT, skf_int lda, const int3
  * device memory (code under HIP graph capture, tight serving loops, harnesses
  * that forbid allocation).  Same operation, kernels and results as skf_solve
  * (bitwise, for the same inputs); its workspace is a fixed device array of the
- * library (7 946 752 bytes, the skf_solve workspace of order 4096, per device,
+ * library (8 405 504 bytes, the skf_solve workspace of order 4096, per device,
  * held until the process ends), so the call allocates nothing.
  *   n       order, 0 <= n <= SKF_SOLVE_NOALLOC_MAX_N, else SKF_ESCRATCH before
  *           any launch (skf_last_error names the limit)

@@ -10,8 +10,8 @@
 //          64 x 64 diagonal blocks are inverted first (all in parallel), then
 //          block I accumulates -L_IJ Y_J as each Y_J is published (tagged
 //          words, no fences) and finishes with Y_I = inv(L_II) acc;
-//   T^{-1} Gaussian elimination with partial pivoting on the tridiagonal
-//          (sequential over rows, one lane per right-hand side);
+//   T^{-1} the tridiagonal's even and odd rows as two bidiagonal triangular
+//          systems (zero diagonal), one substitution chain each, run together;
 //   L^{-T} the same blocked scheme from the last block upwards with the
 //          transposed blocks;
 //   scatter B[perm[i], :] = Z[i, :].
@@ -407,322 +407,130 @@ __global__ void __launch_bounds__(NT) trsv_kernel(int64_t n, const double* __res
   }
 }
 
-// T^{-1} on Y (n x RC) by Gaussian elimination with partial pivoting on the
-// tridiagonal (sub T[i], super -T[i], zero diagonal), taken two rows at a time.
-// With a zero diagonal the elimination has a fixed shape: entering an even row
-// the running diagonal is exactly 0, so that row is always interchanged with
-// the next (its multiplier is 0) and the running diagonal of the odd row is the
-// previous super entry s; the odd row keeps (|s| >= |T[o]|) or interchanges,
-// and leaves the running diagonal exactly 0 again.  Every row of U therefore
-// has a zero first super entry, only 1/diag and the second super entry are
-// kept, and the back substitution is two interleaved chains x_i <- x_{i+2}.
-// The arithmetic on the nonzero entries is that of the row-by-row elimination,
-// with each division replaced by a product with the reciprocal.
-// The pivot choices depend on T only, so lane c of wave 0 carries column c and
-// all lanes take the same choices.  Inputs are staged through LDS in chunks and
-// results leave through LDS: waves 1..3 fetch chunk k+1 and write chunk k-1 out
-// while wave 0 works on chunk k.  The bands go to `band` (2n doubles).
-constexpr int TR = 128;  // rows per chunk (even)
+// T^{-1} on Y (n x RC columns, n even).  T has a zero diagonal, sub-diagonal
+// T[k] and super-diagonal -T[k], so its even rows hold only odd unknowns and
+// its odd rows only even ones:
+//   row 2i:    T[2i-1] x_{2i-1} - T[2i] x_{2i+1} = y_{2i}     (no first term at i = 0)
+//   row 2i+1:  T[2i] x_{2i}     - T[2i+1] x_{2i+2} = y_{2i+1}   (no second term at 2i+1 = n-1)
+// i.e. two bidiagonal triangular systems whose diagonals are the even entries
+// T[2i] (all nonzero exactly when T is nonsingular).  Each is solved by
+// substitution, which is componentwise backward stable:
+//   odd unknowns, forward:   x_{2i+1} = a_i x_{2i-1} + b_i,  a_i = T[2i-1] r_i,  b_i = -y_{2i} r_i
+//   even unknowns, backward: x_{2i}   = c_i x_{2i+2} + d_i,  c_i = T[2i+1] r_i,  d_i = y_{2i+1} r_i
+// with r_i = 1/T[2i]; the coefficients of a chunk of pairs are formed by all
+// threads at once, so a chain step is one fused multiply-add.  Wave 0 carries
+// the forward chain and wave 1 the backward one (lane = right-hand side), over
+// chunks taken from both ends; the solution goes to Z (not Y), so neither
+// chain can overwrite a right-hand side the other has still to read.  A
+// singular T gives non-finite values here; B is then unspecified and the info
+// word reports it.
+constexpr int TC = 256;       // pairs per chunk (one per thread)
+constexpr int TPAD = 8;       // guard entries on each side of a chunk row
+constexpr int TS = TC + 2 * TPAD + 1;  // row stride: 16 lanes' rows in distinct LDS banks
 
-// 1/x from the hardware estimate refined by two Newton steps (each roughly
-// squares the relative error), a few ulps at most.
-__device__ inline double recip(double x) {
-  double r = __builtin_amdgcn_rcp(x);
-  r = fma(r, fma(-x, r, 1.0), r);
-  r = fma(r, fma(-x, r, 1.0), r);
-  return r;
-}
-
-struct TriBuf {
-  double T[2][TR + 2];        // T[i0 .. i0 + TR + 1] (elimination)
-  double in[2][RC][TR + 2];   // right-hand sides, rows i0 .. i0 + TR + 1 / the chunk (back substitution)
-  double out[2][RC][TR];      // results of the chunk
-  double band[2][2][TR];      // 1/diag and second super entry of U, rows of the chunk
-  double plo[TR / 2], pun[TR / 2];  // per pair of the chunk: T[o] and the super entry of row o+1
-  double pc[TR / 2];          // per pair: -(1/T[o]) * (super entry of o+1)
-  double pf[TR / 2];          // per pair: multiplier of the odd row
-  int pk[TR / 2];             // per pair: 1 if the odd row is kept
-};
-
-__global__ void __launch_bounds__(256) tridiag_kernel(int64_t n, const double* __restrict__ T,
-                                                      double* __restrict__ Y, double* __restrict__ band) {
-  __shared__ TriBuf sb;
-  __shared__ int s_sing;
+__global__ void __launch_bounds__(256) tridiag_kernel(int64_t n, int nr, const double* __restrict__ T,
+                                                      const double* __restrict__ Y, double* __restrict__ Z) {
+  __shared__ double sa[2][TS];
+  __shared__ double sb[2][RC][TS];
   const int tid = threadIdx.x;
-  const int c = tid;                 // column of a working lane (tid < RC)
-  const bool work = tid < RC;
-  const int ht = tid - 64;           // helper thread index (waves 1..3), 192 of them
-  // ---------------- elimination, rows 0 .. n-2 (n even) ----------------
-  const int64_t nchf = (n - 1 + TR - 1) / TR;
-  // Helper copies issue all of a thread's loads before the first LDS write (and
-  // all LDS reads before the first store), so a chunk costs one memory latency.
-  constexpr int kIn = (RC * (TR + 2) + 191) / 192;
-  constexpr int kOut = (RC * TR + 191) / 192;
-  constexpr int kBand = (2 * TR + 191) / 192;
-  auto fwd_load = [&](int b, int64_t i0) {
-    const int64_t ti = min(i0 + ht, n - 2);  // clamped: valid for n >= 2
-    const double tv = (ht < TR + 2) ? T[ti < 0 ? 0 : ti] : 0.0;
-    double v[kIn];
+  const int64_t np = n / 2;
+  const int64_t nch = (np + TC - 1) / TC;
+  const int w = tid >> 6, c = tid & 63;
+  double x = 0.0;  // x_{2i-1} (wave 0) or x_{2i+2} (wave 1) carried across chunks
+  for (int64_t ch = 0; ch < nch; ++ch) {
+    // coefficients of pair p at entry TPAD + tid; pairs past the end are
+    // identity steps (a = 1, b = 0: x passes through unchanged)
 #pragma unroll
-    for (int k = 0; k < kIn; ++k) {
-      const int t = min(ht + 192 * k, RC * (TR + 2) - 1);
-      const int cc = t / (TR + 2), r = t % (TR + 2);
-      v[k] = Y[min(i0 + r, n - 1) + (int64_t)cc * n];
-    }
-    if (ht < TR + 2) sb.T[b][ht] = (i0 + ht <= n - 2) ? tv : 0.0;
+    for (int d = 0; d < 2; ++d) {
+      const int64_t p = (d == 0 ? ch : nch - 1 - ch) * TC + tid;
+      double av = 1.0, bv[RC];
 #pragma unroll
-    for (int k = 0; k < kIn; ++k) {
-      const int t = ht + 192 * k;
-      if (t < RC * (TR + 2)) {
-        const int cc = t / (TR + 2), r = t % (TR + 2);
-        sb.in[b][cc][r] = (i0 + r <= n - 1) ? v[k] : 0.0;
+      for (int k = 0; k < RC; ++k) bv[k] = 0.0;
+      if (p < np) {
+        const double r = 1.0 / T[2 * p];
+        const double t = (d == 0) ? (p > 0 ? T[2 * p - 1] : 0.0) : (2 * p + 2 < n ? T[2 * p + 1] : 0.0);
+#pragma unroll
+        for (int k = 0; k < RC; ++k) bv[k] = (k < nr) ? Y[2 * p + d + (int64_t)k * n] : 0.0;
+        av = t * r;
+#pragma unroll
+        for (int k = 0; k < RC; ++k) bv[k] = (d == 0) ? -(bv[k] * r) : bv[k] * r;
       }
-    }
-  };
-  auto fwd_flush = [&](int b, int64_t i0) {  // rows i0 .. min(i0 + TR, n - 1) - 1
-    const int rows = (int)min((int64_t)TR, n - 1 - i0);
-    double v[kOut], w[kBand];
+      sa[d][TPAD + tid] = av;
 #pragma unroll
-    for (int k = 0; k < kOut; ++k) {
-      const int t = min(ht + 192 * k, RC * TR - 1);
-      v[k] = sb.out[b][t / TR][t % TR];
-    }
-#pragma unroll
-    for (int k = 0; k < kBand; ++k) {
-      const int t = min(ht + 192 * k, 2 * TR - 1);
-      w[k] = sb.band[b][t / TR][t % TR];
-    }
-#pragma unroll
-    for (int k = 0; k < kOut; ++k) {
-      const int t = ht + 192 * k;
-      const int cc = t / TR, r = t % TR;
-      if (t < RC * TR && r < rows) Y[i0 + r + (int64_t)cc * n] = v[k];
-    }
-#pragma unroll
-    for (int k = 0; k < kBand; ++k) {
-      const int t = ht + 192 * k;
-      const int q = t / TR, r = t % TR;
-      if (t < 2 * TR && r < rows) band[(int64_t)q * n + i0 + r] = w[k];
-    }
-  };
-  double u = (n > 1) ? -T[0] : 0.0;   // super entry carried into the next even row
-  double ys = work ? Y[(int64_t)c * n] : 0.0;  // right-hand side carried with the running row
-  double sd = 0.0;                    // running diagonal entering the last row
-  int64_t sing = 0;                   // uniform across the working lanes
-  if (ht >= 0) fwd_load(0, 0);
-  __syncthreads();
-  for (int64_t ch = 0; ch < nchf; ++ch) {
-    const int cur = (int)(ch & 1);
-    const int64_t i0 = ch * TR;
-    if (ht >= 0) {
-      if (ch >= 1) fwd_flush(cur ^ 1, i0 - TR);
-      if (ch + 1 < nchf) fwd_load(cur ^ 1, i0 + TR);
-    }
-    if (tid < 64 && !sing) {
-      // The pivot choices, multipliers and U depend on T only.  Wave 0 takes
-      // (a) each pair's chain-free part, one pair per lane; (b) the chain
-      // through the running diagonal u alone (uniform, every lane, no branch):
-      // the odd row of pair j has diagonal s_j = u and is kept when |s_j| >=
-      // |T[o]|, then u = kept ? -T[o+1] : s_j * (-(1/T[o]) T[o+1]); (c) per pair
-      // again, the reciprocal pivots, multipliers, U and the first zero pivot;
-      // (d) the working lanes carry the right-hand sides through the choices.
-      const int rows = (int)min((int64_t)TR, n - 1 - i0);
-      const int npc = (rows + 1) / 2;            // pairs; with odd rows the last is row n-2 and the last row
-      const int nf = (rows & 1) ? npc - 1 : npc;  // pairs with a full odd row
-      const double* tb = sb.T[cur];
-      const int j = tid, r = 2 * j;
-      const int64_t e = i0 + r;
-      const double le = tb[r], lo_j = tb[r + 1], t2 = tb[r + 2];
-      const double rl_j = recip(lo_j);
-      const double un_j = (e + 3 < n) ? -t2 : 0.0;
-      if (j < npc) {
-        sb.band[cur][0][r] = recip(le);
-        sb.band[cur][1][r] = (e + 2 < n) ? -lo_j : 0.0;
-      }
-      sb.plo[j] = lo_j;
-      sb.pun[j] = un_j;
-      sb.pc[j] = -(rl_j * un_j);
-      double mys = 0.0;
-      {
-        constexpr int G4 = 4;
-        double lo[G4], cf[G4], un[G4];
-#pragma unroll
-        for (int t = 0; t < G4; ++t) {
-          lo[t] = sb.plo[t];
-          cf[t] = sb.pc[t];
-          un[t] = sb.pun[t];
-        }
-        for (int jb = 0; jb < nf; jb += G4) {
-          const int jn = min(jb + G4, TR / 2 - G4);
-          double lon[G4], cfn[G4], unn[G4];
-#pragma unroll
-          for (int t = 0; t < G4; ++t) {
-            lon[t] = sb.plo[jn + t];
-            cfn[t] = sb.pc[jn + t];
-            unn[t] = sb.pun[jn + t];
-          }
-#pragma unroll
-          for (int t = 0; t < G4; ++t) {
-            const double s_ = u;
-            const bool keep = fabs(s_) >= fabs(lo[t]);
-            const double un_next = keep ? un[t] : s_ * cf[t];
-            mys = (tid == jb + t) ? s_ : mys;
-            u = (jb + t < nf) ? un_next : u;
-          }
-#pragma unroll
-          for (int t = 0; t < G4; ++t) {
-            lo[t] = lon[t];
-            cf[t] = cfn[t];
-            un[t] = unn[t];
-          }
-        }
-      }
-      if (rows & 1) sd = u;  // e = n-2: the odd row is the last row, diagonal u
-      // (c) pair j's odd row from s_j; the first zero pivot in row order
-      const bool keep = fabs(mys) >= fabs(lo_j);
-      const double rs = recip(mys);
-      if (j < nf) {
-        sb.band[cur][0][r + 1] = keep ? rs : rl_j;
-        sb.band[cur][1][r + 1] = keep ? 0.0 : un_j;
-        sb.pf[j] = keep ? lo_j * rs : mys * rl_j;
-        sb.pk[j] = (int)keep;
-      }
-      const uint64_t ze = __ballot(j < npc && le == 0.0);
-      const uint64_t zo = __ballot(j < nf && (keep ? mys : lo_j) == 0.0);
-      if (ze | zo) {
-        const int jf = (int)__builtin_ctzll(ze | zo);
-        sing = i0 + 2 * jf + (((ze >> jf) & 1ull) ? 1 : 2);
-      }
-      if (work && !sing) {
-        // even row: always interchanged with the odd row (multiplier 0); odd row:
-        // kept (eliminate the next row with it) or interchanged with the next row
-        const double* yb = sb.in[cur][c];
-        double ye = yb[1], yo = yb[2], f = sb.pf[0];
-        int kp = sb.pk[0];
-        for (int q = 0; q < nf; ++q) {
-          const int qn = min(q + 1, TR / 2 - 1);
-          const double ye_n = yb[2 * qn + 1], yo_n = yb[2 * qn + 2], f_n = sb.pf[qn];
-          const int kp_n = sb.pk[qn];
-          sb.out[cur][c][2 * q] = ye;
-          sb.out[cur][c][2 * q + 1] = kp ? ys : yo;
-          ys = kp ? yo - f * ys : ys - f * yo;
-          ye = ye_n;
-          yo = yo_n;
-          f = f_n;
-          kp = kp_n;
-        }
-        if (rows & 1) sb.out[cur][c][2 * nf] = yb[2 * nf + 1];  // the last row's right-hand side stays in ys
-      }
+      for (int k = 0; k < RC; ++k) sb[d][k][TPAD + tid] = bv[k];
     }
     __syncthreads();
-  }
-  if (ht >= 0 && nchf >= 1) fwd_flush((int)((nchf - 1) & 1), (nchf - 1) * TR);
-  if (work && !sing) {  // last row n-1: diagonal sd
-    if (sd == 0.0) sing = n;
-    else {
-      if (c == 0) {
-        band[n - 1] = recip(sd);
-        band[2 * n - 1] = 0.0;
+    // the chains: eight steps per block, the next block's coefficients read
+    // while this one runs (the guard entries absorb the reads past the row)
+    constexpr int G8 = 8;
+    if (w == 0 && c < nr) {
+      const double* aa = sa[0] + TPAD;
+      double* bb = sb[0][c] + TPAD;
+      double ca[G8], cb[G8];
+#pragma unroll
+      for (int u = 0; u < G8; ++u) {
+        ca[u] = aa[u];
+        cb[u] = bb[u];
       }
-      Y[n - 1 + (int64_t)c * n] = ys;
-    }
-  }
-  if (tid == 0) s_sing = sing ? 1 : 0;
-  __syncthreads();  // also orders the global writes above before the reads below
-  if (s_sing) return;  // singular T: the info word reports it from T
-  // ---------------- back substitution, rows n-1 .. 0 ----------------
-  const int64_t nchb = (n + TR - 1) / TR;
-  auto bwd_load = [&](int b, int64_t i1) {  // rows i1 - TR .. i1 - 1 (negative rows padded)
-    double v[kOut], w[kBand];
+      for (int j0 = 0; j0 < TC; j0 += G8) {
+        double na[G8], nb2[G8];
 #pragma unroll
-    for (int k = 0; k < kOut; ++k) {
-      const int t = min(ht + 192 * k, RC * TR - 1);
-      const int64_t i = i1 - TR + t % TR;
-      v[k] = Y[(i < 0 ? 0 : i) + (int64_t)(t / TR) * n];
-    }
-#pragma unroll
-    for (int k = 0; k < kBand; ++k) {
-      const int t = min(ht + 192 * k, 2 * TR - 1);
-      const int64_t i = i1 - TR + t % TR;
-      w[k] = band[(int64_t)(t / TR) * n + (i < 0 ? 0 : i)];
-    }
-#pragma unroll
-    for (int k = 0; k < kOut; ++k) {
-      const int t = ht + 192 * k;
-      if (t < RC * TR) sb.in[b][t / TR][t % TR] = (i1 - TR + t % TR >= 0) ? v[k] : 0.0;
-    }
-#pragma unroll
-    for (int k = 0; k < kBand; ++k) {
-      const int t = ht + 192 * k;
-      if (t < 2 * TR) sb.band[b][t / TR][t % TR] = (i1 - TR + t % TR >= 0) ? w[k] : 0.0;
-    }
-  };
-  auto bwd_flush = [&](int b, int64_t i1) {
-    double v[kOut];
-#pragma unroll
-    for (int k = 0; k < kOut; ++k) {
-      const int t = min(ht + 192 * k, RC * TR - 1);
-      v[k] = sb.out[b][t / TR][t % TR];
-    }
-#pragma unroll
-    for (int k = 0; k < kOut; ++k) {
-      const int t = ht + 192 * k;
-      const int64_t i = i1 - TR + t % TR;
-      if (t < RC * TR && i >= 0) Y[i + (int64_t)(t / TR) * n] = v[k];
-    }
-  };
-  double x1 = 0.0, x2 = 0.0;  // solution at rows i+1, i+2
-  if (ht >= 0) bwd_load(0, n);
-  __syncthreads();
-  for (int64_t ch = 0; ch < nchb; ++ch) {
-    const int cur = (int)(ch & 1);
-    const int64_t i1 = n - ch * TR;
-    if (ht >= 0) {
-      if (ch >= 1) bwd_flush(cur ^ 1, i1 + TR);
-      if (ch + 1 < nchb) bwd_load(cur ^ 1, i1 - TR);
-    }
-    if (work) {
-      // x_i = (y_i - du2_i x_{i+2}) / d_i  (the first super entry of U is 0),
-      // eight rows at a time with the next eight rows' operands in flight; rows
-      // below 0 are zero padding and give zeros
-      constexpr int G8 = 8;
-      const double* ib = sb.in[cur][c];
-      const double* p0 = sb.band[cur][0];
-      const double* p1 = sb.band[cur][1];
-      double a[G8], b1[G8], b0[G8];
-#pragma unroll
-      for (int t = 0; t < G8; ++t) {
-        a[t] = ib[TR - G8 + t];
-        b1[t] = p1[TR - G8 + t];
-        b0[t] = p0[TR - G8 + t];
-      }
-      for (int rb = TR - G8; rb >= 0; rb -= G8) {
-        const int rn = max(rb - G8, 0);
-        double an[G8], b1n[G8], b0n[G8];
-#pragma unroll
-        for (int t = 0; t < G8; ++t) {
-          an[t] = ib[rn + t];
-          b1n[t] = p1[rn + t];
-          b0n[t] = p0[rn + t];
+        for (int u = 0; u < G8; ++u) {
+          na[u] = aa[j0 + G8 + u];
+          nb2[u] = bb[j0 + G8 + u];
         }
 #pragma unroll
-        for (int t = G8 - 1; t >= 0; --t) {
-          const double v = (a[t] - b1[t] * x2) * b0[t];
-          sb.out[cur][c][rb + t] = v;
-          x2 = x1;
-          x1 = v;
+        for (int u = 0; u < G8; ++u) {
+          x = fma(ca[u], x, cb[u]);
+          bb[j0 + u] = x;
         }
 #pragma unroll
-        for (int t = 0; t < G8; ++t) {
-          a[t] = an[t];
-          b1[t] = b1n[t];
-          b0[t] = b0n[t];
+        for (int u = 0; u < G8; ++u) {
+          ca[u] = na[u];
+          cb[u] = nb2[u];
+        }
+      }
+    } else if (w == 1 && c < nr) {
+      const double* aa = sa[1] + TPAD + TC - 1;
+      double* bb = sb[1][c] + TPAD + TC - 1;
+      double ca[G8], cb[G8];
+#pragma unroll
+      for (int u = 0; u < G8; ++u) {
+        ca[u] = aa[-u];
+        cb[u] = bb[-u];
+      }
+      for (int j0 = 0; j0 < TC; j0 += G8) {
+        double na[G8], nb2[G8];
+#pragma unroll
+        for (int u = 0; u < G8; ++u) {
+          na[u] = aa[-(j0 + G8 + u)];
+          nb2[u] = bb[-(j0 + G8 + u)];
+        }
+#pragma unroll
+        for (int u = 0; u < G8; ++u) {
+          x = fma(ca[u], x, cb[u]);
+          bb[-(j0 + u)] = x;
+        }
+#pragma unroll
+        for (int u = 0; u < G8; ++u) {
+          ca[u] = na[u];
+          cb[u] = nb2[u];
         }
       }
     }
     __syncthreads();
+    // x_{2p+1} (forward chain) and x_{2p} (backward chain) to their rows of Z
+#pragma unroll
+    for (int d = 0; d < 2; ++d) {
+      const int64_t p = (d == 0 ? ch : nch - 1 - ch) * TC + tid;
+      if (p < np) {
+#pragma unroll
+        for (int k = 0; k < RC; ++k)
+          if (k < nr) Z[2 * p + 1 - d + (int64_t)k * n] = sb[d][k][TPAD + tid];
+      }
+    }
+    __syncthreads();  // the chunk buffers are refilled next
   }
-  if (ht >= 0) bwd_flush((int)((nchb - 1) & 1), n - (nchb - 1) * TR);
 }
 
 // info = 1 + first even k with T[k] == 0, or n for odd n, or 0.
@@ -751,7 +559,7 @@ __global__ void solve_info_kernel(int64_t n, const double* __restrict__ T, const
 
 }  // namespace
 
-// Workspace: perm (n int32) | Dinv (nb*BS*BS) | Y (n*RC) | tridiagonal bands (2*n) | published blocks
+// Workspace: perm (n int32) | Dinv (nb*BS*BS) | Y (n*RC) | Z (n*RC) | published blocks
 // (2*nb*BS*RC words) | status
 struct SolveWork {
   int32_t* perm;
@@ -759,7 +567,7 @@ struct SolveWork {
   double* Mf;  // fold blocks, forward (nb*BS*BS)
   double* Mb;  // fold blocks, backward
   double* Y;
-  double* tri;
+  double* Z;  // T^{-1} Y
   uint64_t* pub;
   int* status;
   size_t bytes;
@@ -767,7 +575,7 @@ struct SolveWork {
 
 // Byte sizes of the workspace parts for order n (each part 256-aligned).
 struct SolveSizes {
-  size_t perm, Dinv, Mf, Mb, Y, tri, pub, status;
+  size_t perm, Dinv, Mf, Mb, Y, Z, pub, status;
 };
 
 constexpr int64_t at_least_1(int64_t v) { return v > 1 ? v : 1; }
@@ -780,14 +588,14 @@ constexpr SolveSizes solve_sizes(int64_t n) {
                     round256(sizeof(double) * (size_t)at_least_1(nb) * BS * BS),
                     round256(sizeof(double) * (size_t)at_least_1(nb) * BS * BS),
                     round256(sizeof(double) * (size_t)at_least_1(n) * RC),
-                    round256(sizeof(double) * (size_t)at_least_1(n) * 2),
+                    round256(sizeof(double) * (size_t)at_least_1(n) * RC),
                     round256(sizeof(uint64_t) * (size_t)at_least_1(nb) * BS * RC * 2),
                     round256(256)};
 }
 
 constexpr size_t solve_bytes(int64_t n) {
   const SolveSizes z = solve_sizes(n);
-  return z.perm + z.Dinv + z.Mf + z.Mb + z.Y + z.tri + z.pub + z.status;
+  return z.perm + z.Dinv + z.Mf + z.Mb + z.Y + z.Z + z.pub + z.status;
 }
 
 static SolveWork solve_carve(void* base, int64_t n) {
@@ -804,7 +612,7 @@ static SolveWork solve_carve(void* base, int64_t n) {
   w.Mf = (double*)take(z.Mf);
   w.Mb = (double*)take(z.Mb);
   w.Y = (double*)take(z.Y);
-  w.tri = (double*)take(z.tri);
+  w.Z = (double*)take(z.Z);
   w.pub = (uint64_t*)take(z.pub);
   w.status = (int*)take(z.status);
   w.bytes = off;
@@ -854,13 +662,13 @@ int run_solve(int64_t n, int64_t nrhs, const double* LT, int64_t lda, const int3
       hipLaunchKernelGGL(trsv_kernel<false>, dim3((unsigned)nb), dim3(NT), 0, s, n, LT, lda, w.Dinv, w.Mf, w.Y,
                          w.pub, tag, w.status);
       SKF_CHECK_LAUNCH("trsv fwd");
-      hipLaunchKernelGGL(tridiag_kernel, dim3(1), dim3(256), 0, s, n, T, w.Y, w.tri);
+      hipLaunchKernelGGL(tridiag_kernel, dim3(1), dim3(256), 0, s, n, nr, T, w.Y, w.Z);
       SKF_CHECK_LAUNCH("tridiag");
       ++tag;
-      hipLaunchKernelGGL(trsv_kernel<true>, dim3((unsigned)nb), dim3(NT), 0, s, n, LT, lda, w.Dinv, w.Mb, w.Y,
+      hipLaunchKernelGGL(trsv_kernel<true>, dim3((unsigned)nb), dim3(NT), 0, s, n, LT, lda, w.Dinv, w.Mb, w.Z,
                          w.pub, tag, w.status);
       SKF_CHECK_LAUNCH("trsv bwd");
-      hipLaunchKernelGGL(scatter_kernel, dim3(gx, RC), dim3(256), 0, s, n, nr, w.perm, w.Y, B + c0 * ldb, ldb);
+      hipLaunchKernelGGL(scatter_kernel, dim3(gx, RC), dim3(256), 0, s, n, nr, w.perm, w.Z, B + c0 * ldb, ldb);
       SKF_CHECK_LAUNCH("scatter");
     }
   }
