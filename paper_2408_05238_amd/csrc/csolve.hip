@@ -8,14 +8,13 @@
 //           solved by one workgroup (column sweep in LDS), then every block
 //           below subtracts L[I, J] Y_J (one workgroup per block row and group
 //           of four right-hand sides, the 64 x 64 block of L read once);
-//   T⁻¹     Gaussian elimination with partial pivoting on the tridiagonal
-//           T(k+1, k) = T[k], T(k, k+1) = -T[k]: the pivot choices depend on T
-//           only, so they are recorded once (multipliers and the U bands), then
-//           one workgroup per right-hand side applies them and back-substitutes
-//           (each chain on one thread over chunks staged in LDS);
-//   L⁻ᵀ     by blocks from the last: the transposed diagonal block by one
-//           workgroup, then every block above subtracts L[I, J]ᵀ Y_I;
-//   scatter B[perm[i], :] = Y[i, :].
+//   T⁻¹     the tridiagonal T(k+1, k) = T[k], T(k, k+1) = -T[k] (zero
+//           diagonal) split into its even rows (odd unknowns) and odd rows
+//           (even unknowns): two bidiagonal substitutions, run together by two
+//           waves, into Z;
+//   L⁻ᵀ     by blocks from the last on Z: the transposed diagonal block by one
+//           workgroup, then every block above subtracts L[I, J]ᵀ Z_I;
+//   scatter B[perm[i], :] = Z[i, :].
 // L[i, j] (i > j >= 1) is read from LT[i, j-1]; L[:, 0] = e_0.
 // Each step is a launch; a block's launches wait for the previous block's
 // through the stream, so no workgroup waits on another.
@@ -162,159 +161,112 @@ __global__ void __launch_bounds__(kBs* kRc) cupdate_bwd_kernel(int64_t n, int64_
   st2(Y, j + col * n, acc);
 }
 
-// The tridiagonal's elimination with partial pivoting: per row i the choice
-// sw[i] (row i+1 taken as pivot row), the multiplier f[i] and the U bands dd,
-// du, du2; status = the first zero pivot (1-based) if it meets one.  The chain
-// runs on thread 0 over chunks of kCh rows staged in LDS by the whole
-// workgroup (one load round trip and one store round trip per chunk).
-constexpr int kCh = 512;
+// T^{-1} on Y (n x nrhs, n even).  The complex skew tridiagonal T has a zero
+// diagonal, so its even rows hold only the odd unknowns and its odd rows only
+// the even ones: two bidiagonal triangular systems whose diagonals are the
+// even entries T[2i] (all nonzero here: a zero one stops the solve first),
+// each solved by substitution (componentwise backward stable):
+//   x_{2i+1} = a_i x_{2i-1} + b_i,  a_i = T[2i-1] r_i,  b_i = -y_{2i} r_i
+//   x_{2i}   = c_i x_{2i+2} + d_i,  c_i = T[2i+1] r_i,  d_i = y_{2i+1} r_i
+// with r_i = 1/T[2i] (Smith's division).  Per chunk of kTc pairs, threads
+// 0..kTc-1 form the forward chain's coefficients and the others the backward
+// chain's; then wave 0 runs the forward chain and wave 1 the backward one
+// (lane = right-hand side, kCc per workgroup), one complex multiply-add per
+// step; chunks are padded with identity steps so the loop has no guard.  The
+// solution goes to Z, so neither chain overwrites a right-hand side the other
+// still reads.
+constexpr int kTc = 128;                   // pairs per chunk
+constexpr int kCc = 16;                    // right-hand sides per workgroup
+constexpr int kTpad = 8;                   // guard entries on each side of a row
+constexpr int kTs = kTc + 2 * kTpad + 1;   // row stride: the lanes' rows in distinct LDS banks
 
-__global__ void __launch_bounds__(256) ctri_factor_kernel(int64_t n, const double* __restrict__ T,
-                                                          double* __restrict__ dd, double* __restrict__ du,
-                                                          double* __restrict__ du2, double* __restrict__ f,
-                                                          int32_t* __restrict__ sw, int* __restrict__ status) {
-  __shared__ z2 tch[kCh + 1];
-  __shared__ z2 o_dd[kCh], o_du[kCh], o_du2[kCh], o_f[kCh];
-  __shared__ int o_sw[kCh];
-  __shared__ int stop;
-  const int t = threadIdx.x;
-  if (*status != 0) return;  // singular T found before (uniform)
-  if (t == 0) stop = 0;
-  z2 cd = {0.0, 0.0};                                 // running diagonal of row i (thread 0)
-  z2 cu = (n > 1) ? ld2(T, 0) : z2{0.0, 0.0};         // running super entry of row i
-  cu = zsub(z2{0.0, 0.0}, cu);
-  for (int64_t c0 = 0; c0 < n - 1; c0 += kCh) {
-    const int cnt = (int)min((int64_t)kCh, n - 1 - c0);
-    const int nld = (int)min((int64_t)cnt + 1, n - 1 - c0);  // T[c0 .. c0 + cnt] where it exists
-    for (int e = t; e < nld; e += blockDim.x) tch[e] = ld2(T, c0 + e);
-    __syncthreads();
-    if (t == 0) {
-      for (int e = 0; e < cnt; ++e) {
-        const int64_t i = c0 + e;
-        const z2 dl = tch[e];
-        z2 nd = {0.0, 0.0};
-        z2 nu = (i + 2 < n) ? zsub(z2{0.0, 0.0}, tch[e + 1]) : z2{0.0, 0.0};
-        if (zn2(cd) >= zn2(dl)) {
-          if (cd.re == 0.0 && cd.im == 0.0) {
-            *status = (int)(i + 1);
-            stop = 1;
-            break;
-          }
-          const z2 fm = zdiv(dl, cd);
-          nd = zsub(nd, zmul(fm, cu));
-          o_dd[e] = cd;
-          o_du[e] = cu;
-          o_du2[e] = z2{0.0, 0.0};
-          o_f[e] = fm;
-          o_sw[e] = 0;
-        } else {
-          const z2 fm = zdiv(cd, dl);
-          const z2 tt = nd;
-          o_dd[e] = dl;
-          o_du[e] = tt;
-          const z2 nd2 = zsub(cu, zmul(fm, tt));
-          z2 u2 = {0.0, 0.0};
-          if (i + 2 < n) {
-            u2 = nu;
-            nu = zsub(z2{0.0, 0.0}, zmul(fm, u2));
-          }
-          o_du2[e] = u2;
-          o_f[e] = fm;
-          o_sw[e] = 1;
-          nd = nd2;
-        }
-        cd = nd;
-        cu = nu;
-      }
-    }
-    __syncthreads();
-    if (stop) return;
-    for (int e = t; e < cnt; e += blockDim.x) {
-      st2(dd, c0 + e, o_dd[e]);
-      st2(du, c0 + e, o_du[e]);
-      st2(du2, c0 + e, o_du2[e]);
-      st2(f, c0 + e, o_f[e]);
-      sw[c0 + e] = o_sw[e];
-    }
-    __syncthreads();
+__device__ inline z2 zfma(z2 a, z2 x, z2 b) {  // a x + b
+  return {fma(a.re, x.re, fma(-a.im, x.im, b.re)), fma(a.re, x.im, fma(a.im, x.re, b.im))};
+}
+
+template <int DIR>
+__device__ inline void cchain(const z2* __restrict__ aa, z2* __restrict__ bb, z2& x) {
+  // step j takes entry j (DIR = +1, from the chunk's start) or kTc-1-j (DIR = -1);
+  // eight steps per block, the next block's coefficients read while it runs
+  constexpr int G8 = 8;
+  const int base = (DIR > 0) ? 0 : kTc - 1;
+  z2 ca[G8], cb[G8];
+#pragma unroll
+  for (int u = 0; u < G8; ++u) {
+    ca[u] = aa[base + DIR * u];
+    cb[u] = bb[base + DIR * u];
   }
-  if (t == 0) {
-    if (cd.re == 0.0 && cd.im == 0.0) *status = (int)n;
-    else st2(dd, n - 1, cd);
+  for (int j0 = 0; j0 < kTc; j0 += G8) {
+    z2 na[G8], nb[G8];
+#pragma unroll
+    for (int u = 0; u < G8; ++u) {
+      na[u] = aa[base + DIR * (j0 + G8 + u)];
+      nb[u] = bb[base + DIR * (j0 + G8 + u)];
+    }
+#pragma unroll
+    for (int u = 0; u < G8; ++u) {
+      x = zfma(ca[u], x, cb[u]);
+      bb[base + DIR * (j0 + u)] = x;
+    }
+#pragma unroll
+    for (int u = 0; u < G8; ++u) {
+      ca[u] = na[u];
+      cb[u] = nb[u];
+    }
   }
 }
 
-// One workgroup per right-hand side: the recorded elimination, then back
-// substitution, each chained on thread 0 over chunks staged in LDS.
-__global__ void __launch_bounds__(256) ctri_apply_kernel(int64_t n, const double* __restrict__ dd,
-                                                         const double* __restrict__ du,
-                                                         const double* __restrict__ du2,
-                                                         const double* __restrict__ f,
-                                                         const int32_t* __restrict__ sw,
-                                                         const int* __restrict__ status, double* __restrict__ Y) {
-  __shared__ z2 a[kCh + 1], b[kCh], c[kCh], d[kCh];
-  __shared__ int w[kCh];
-  const int t = threadIdx.x;
-  if (*status != 0) return;
-  double* __restrict__ y = Y + 2 * (int64_t)blockIdx.x * n;
-  // forward: rows c0 .. c0 + cnt - 1; a = y[c0 + 1 ..] (as yet untouched), b = f, w = choices, c = output
-  z2 cb = ld2(y, 0);
-  for (int64_t c0 = 0; c0 < n - 1; c0 += kCh) {
-    const int cnt = (int)min((int64_t)kCh, n - 1 - c0);
-    for (int e = t; e < cnt; e += blockDim.x) {
-      a[e] = ld2(y, c0 + 1 + e);
-      b[e] = ld2(f, c0 + e);
-      w[e] = sw[c0 + e];
-    }
-    __syncthreads();
-    if (t == 0)
-      for (int e = 0; e < cnt; ++e) {
-        const z2 nb = a[e];
-        if (w[e] == 0) {
-          c[e] = cb;
-          cb = zsub(nb, zmul(b[e], cb));
-        } else {
-          c[e] = nb;
-          cb = zsub(cb, zmul(b[e], nb));
+__global__ void __launch_bounds__(256) ctri_kernel(int64_t n, int64_t nr, const double* __restrict__ T,
+                                                   const int* __restrict__ status, const double* __restrict__ Y,
+                                                   double* __restrict__ Z) {
+  __shared__ z2 sa[2][kTs];
+  __shared__ z2 sb[2][kCc][kTs];
+  if (*status != 0) return;  // singular T: B is left as it is
+  const int tid = threadIdx.x;
+  const int64_t c0 = (int64_t)blockIdx.x * kCc;
+  const int ncol = (int)min((int64_t)kCc, nr - c0);
+  const int64_t np = n / 2, nch = (np + kTc - 1) / kTc;
+  const int d = tid / kTc, q = tid % kTc;  // coefficient phase: direction and pair of the chunk
+  const int w = tid >> 6, lane = tid & 63;
+  z2 x = {0.0, 0.0};  // x_{2i-1} (wave 0) or x_{2i+2} (wave 1) carried across chunks
+  for (int64_t ch = 0; ch < nch; ++ch) {
+    const int64_t p = (d == 0 ? ch : nch - 1 - ch) * kTc + q;
+    {
+      z2 av = {1.0, 0.0}, bv[kCc];
+#pragma unroll
+      for (int k = 0; k < kCc; ++k) bv[k] = z2{0.0, 0.0};
+      if (p < np) {
+        const z2 r = zdiv(z2{1.0, 0.0}, ld2(T, 2 * p));
+        const z2 t = (d == 0) ? (p > 0 ? ld2(T, 2 * p - 1) : z2{0.0, 0.0})
+                              : (2 * p + 2 < n ? ld2(T, 2 * p + 1) : z2{0.0, 0.0});
+#pragma unroll
+        for (int k = 0; k < kCc; ++k) bv[k] = (k < ncol) ? ld2(Y, 2 * p + d + (c0 + k) * n) : z2{0.0, 0.0};
+        av = zmul(t, r);
+#pragma unroll
+        for (int k = 0; k < kCc; ++k) {
+          const z2 v = zmul(bv[k], r);
+          bv[k] = (d == 0) ? z2{-v.re, -v.im} : v;
         }
       }
-    __syncthreads();
-    for (int e = t; e < cnt; e += blockDim.x) st2(y, c0 + e, c[e]);
-    __syncthreads();
-  }
-  // back substitution from the last row: x[i] = (y[i] - du[i] x[i+1] - du2[i] x[i+2]) / dd[i]
-  z2 xa = {0.0, 0.0}, xb = {0.0, 0.0};  // x[i+1], x[i+2] (thread 0)
-  if (t == 0) {
-    xa = zdiv(cb, ld2(dd, n - 1));
-    st2(y, n - 1, xa);
-  }
-  for (int64_t c1 = n - 1; c1 > 0; c1 -= kCh) {  // rows c1 - cnt .. c1 - 1
-    const int cnt = (int)min((int64_t)kCh, c1);
-    const int64_t r0 = c1 - cnt;
-    for (int e = t; e < cnt; e += blockDim.x) {
-      a[e] = ld2(y, r0 + e);
-      b[e] = ld2(dd, r0 + e);
-      c[e] = ld2(du, r0 + e);
-      d[e] = ld2(du2, r0 + e);
+      sa[d][kTpad + q] = av;
+#pragma unroll
+      for (int k = 0; k < kCc; ++k) sb[d][k][kTpad + q] = bv[k];
     }
     __syncthreads();
-    if (t == 0)
-      for (int e = cnt - 1; e >= 0; --e) {
-        const int64_t i = r0 + e;
-        const z2 num = (i == n - 2) ? zsub(a[e], zmul(c[e], xa)) : zsub(zsub(a[e], zmul(c[e], xa)), zmul(d[e], xb));
-        const z2 xi = zdiv(num, b[e]);
-        a[e] = xi;
-        xb = xa;
-        xa = xi;
-      }
+    if (w == 0 && lane < ncol) cchain<1>(sa[0] + kTpad, sb[0][lane] + kTpad, x);
+    else if (w == 1 && lane < ncol) cchain<-1>(sa[1] + kTpad, sb[1][lane] + kTpad, x);
     __syncthreads();
-    for (int e = t; e < cnt; e += blockDim.x) st2(y, r0 + e, a[e]);
-    __syncthreads();
+    // x_{2p+1} (forward chain) and x_{2p} (backward chain) to their rows of Z
+    if (p < np) {
+#pragma unroll
+      for (int k = 0; k < kCc; ++k)
+        if (k < ncol) st2(Z, 2 * p + 1 - d + (c0 + k) * n, sb[d][k][kTpad + q]);
+    }
+    __syncthreads();  // the chunk buffers are refilled next
   }
 }
 
-// info: n for odd n; else 1 + the first even k with T[k] = 0; else the
-// elimination's own zero pivot; else 0.
+// info: n for odd n; else 1 + the first even k with T[k] = 0; else 0.
 __global__ void __launch_bounds__(256) csolve_info_kernel(int64_t n, const double* __restrict__ T,
                                                           const int* __restrict__ status, int* __restrict__ dinfo) {
   const int64_t z = first_zero_even_pivot(n, T, true);
@@ -339,8 +291,7 @@ __global__ void __launch_bounds__(256) csolve_precheck_kernel(int64_t n, const d
 
 struct CSolveWork {
   int32_t* perm;
-  double *Y, *dd, *du, *du2, *f;
-  int32_t* sw;
+  double *Y, *Z;  // P B, then L^{-1} P B; T^{-1} of it, then the solution before P^T
   int* status;
   size_t bytes;
 };
@@ -356,11 +307,7 @@ CSolveWork cs_carve(void* base, int64_t n, int64_t nrhs) {
   const size_t m = (size_t)std::max<int64_t>(n, 1), r = (size_t)std::max<int64_t>(nrhs, 1);
   w.perm = (int32_t*)take(sizeof(int32_t) * m);
   w.Y = (double*)take(2 * sizeof(double) * m * r);
-  w.dd = (double*)take(2 * sizeof(double) * m);
-  w.du = (double*)take(2 * sizeof(double) * m);
-  w.du2 = (double*)take(2 * sizeof(double) * m);
-  w.f = (double*)take(2 * sizeof(double) * m);
-  w.sw = (int32_t*)take(sizeof(int32_t) * m);
+  w.Z = (double*)take(2 * sizeof(double) * m * r);
   w.status = (int*)take(256);
   w.bytes = off;
   return w;
@@ -399,22 +346,20 @@ int run_solve_c128(int64_t n, int64_t nrhs, const double* LT, int64_t lda, const
         SKF_CHECK_LAUNCH("csolve update fwd");
       }
     }
-    hipLaunchKernelGGL(ctri_factor_kernel, dim3(1), dim3(256), 0, s, n, T, w.dd, w.du, w.du2, w.f, w.sw, w.status);
-    SKF_CHECK_LAUNCH("csolve tri factor");
-    hipLaunchKernelGGL(ctri_apply_kernel, dim3((unsigned)nrhs), dim3(256), 0, s, n, w.dd, w.du, w.du2, w.f, w.sw,
-                       w.status, w.Y);
-    SKF_CHECK_LAUNCH("csolve tri apply");
+    hipLaunchKernelGGL(ctri_kernel, dim3((unsigned)((nrhs + kCc - 1) / kCc)), dim3(256), 0, s, n, nrhs, T, w.status,
+                       w.Y, w.Z);
+    SKF_CHECK_LAUNCH("csolve tri");
     for (int64_t I = nbk - 1; I >= 0; --I) {
       const int64_t i0 = I * kBs;
-      hipLaunchKernelGGL(cdiag_bwd_kernel, dim3(gr), dim3(kBs * kRc), 0, s, n, nrhs, LT, lda, w.Y, i0);
+      hipLaunchKernelGGL(cdiag_bwd_kernel, dim3(gr), dim3(kBs * kRc), 0, s, n, nrhs, LT, lda, w.Z, i0);
       SKF_CHECK_LAUNCH("csolve diag bwd");
       if (I > 0) {
-        hipLaunchKernelGGL(cupdate_bwd_kernel, dim3((unsigned)I, gr), dim3(kBs * kRc), 0, s, n, nrhs, LT, lda, w.Y,
+        hipLaunchKernelGGL(cupdate_bwd_kernel, dim3((unsigned)I, gr), dim3(kBs * kRc), 0, s, n, nrhs, LT, lda, w.Z,
                            i0);
         SKF_CHECK_LAUNCH("csolve update bwd");
       }
     }
-    hipLaunchKernelGGL(cscatter_kernel, dim3(gx, (unsigned)nrhs), dim3(256), 0, s, n, nrhs, w.perm, w.Y, B, ldb,
+    hipLaunchKernelGGL(cscatter_kernel, dim3(gx, (unsigned)nrhs), dim3(256), 0, s, n, nrhs, w.perm, w.Z, B, ldb,
                        w.status);
     SKF_CHECK_LAUNCH("csolve scatter");
   }
