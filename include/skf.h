@@ -71,14 +71,15 @@ typedef int64_t skf_int;
  * used.  Each entry covers the orders n_lo <= n <= n_hi; a later entry covering
  * the same order wins over an earlier one.  Without an entry the built-in rule
  * applies (the widest panel of 128, 64, 32, 16 whose workgroups fit on the
- * device; band of 8 block rows).  The environment variable SKF_NB=16|32|64|128
- * overrides both panel widths.  A table value that is infeasible for a given n
+ * device; band of 8 block rows; width 256, one panel workgroup per CU, only
+ * from a table entry or the override).  The environment variable
+ * SKF_NB=16|32|64|128|256 overrides both panel widths.  A table value that is infeasible for a given n
  * (too many panel workgroups to be resident) is ignored for that n.  Host-only;
  * thread-safe; takes effect for calls made afterwards (workspace sizes cover
  * every feasible width).
  */
-#define SKF_TUNE_LTLT_NB 0    /* panel width of skf_ltlt and skf_ltlt-based calls: 16, 32, 64 or 128 */
-#define SKF_TUNE_PFONLY_NB 1  /* panel width (twice the steps per panel) of skf_pfonly / skf_logpf: 16, 32, 64 or 128 */
+#define SKF_TUNE_LTLT_NB 0    /* panel width of skf_ltlt and skf_ltlt-based calls: 16, 32, 64, 128 or 256 */
+#define SKF_TUNE_PFONLY_NB 1  /* panel width (twice the steps per panel) of skf_pfonly / skf_logpf: 16, 32, 64, 128 or 256 */
 #define SKF_TUNE_SKR2K_BAND 2 /* block rows per band of the trailing update's tile walk, by trailing order: 1..64 */
 #define SKF_TUNE_NPARAMS 3
 /* Add an entry; returns 0, or -1 (param), -2 (n_lo < 0), -3 (n_hi < n_lo), -4 (value not allowed). */
@@ -115,9 +116,9 @@ size_t skf_ltlt_workspace(skf_int n, int prec);
  *   work   device workspace of at least skf_ltlt_workspace(n, prec) bytes
  *   dinfo  device int or NULL (see status codes)
  * Orders: a panel runs one workgroup per 64 rows, all resident at once (at most
- * six per CU), so the panel width is the widest that fits (on 256 CUs: 128 up
- * to n = 16385, 64 up to 49153, 32 or 16 up to 98305); beyond, SKF_ENOTIMPL.
- * skf_pfonly: 128 up to 32769, 64 up to 65537, 32 or 16 up to 98305.
+ * six per CU), so the panel width is the widest that fits (on 256 CUs: 256 up
+ * to n = 16385 when chosen, 128 up to 32769, 64 up to 65537, 32 or 16 up to
+ * 98305); beyond, SKF_ENOTIMPL.  skf_pfonly: the same.
  */
 int skf_ltlt(skf_int n, double* A, skf_int lda, int32_t* ipiv, double* T, int prec,
              void* work, size_t lwork, int* dinfo, void* stream);

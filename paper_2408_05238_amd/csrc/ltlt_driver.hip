@@ -18,12 +18,12 @@
 namespace skf {
 
 // The panel kernel is one wave per workgroup with 64 row slots; LDS holds the
-// (nb/2) x 64 pair vectors per workgroup (65 KB at nb = 128, 33 KB at 64, 17 KB
-// at 32, 9 KB at 16), so a CU hosts two, four, six or six of them (the LDS
-// bound, the occupancy query and the cap of six per CU decide).  Every
-// workgroup of a panel launch must be resident together, so the narrower
-// widths carry larger orders: up to 512, 1024 and 1536 workgroups of 64 rows
-// on 256 CUs.
+// (nb/2) x 64 pair vectors per workgroup (130 KB at nb = 256, 65 KB at 128,
+// 33 KB at 64, 17 KB at 32, 9 KB at 16), so a CU hosts one, two, four, six or
+// six of them (the LDS bound, the occupancy query and the cap of six per CU
+// decide).  Every workgroup of a panel launch must be resident together, so the
+// narrower widths carry larger orders: up to 256, 512, 1024 and 1536
+// workgroups of 64 rows on 256 CUs.
 static constexpr int kMaxPanelG = 2048;
 
 static int slots() { return panel_slots(); }
@@ -32,13 +32,16 @@ static int64_t max_panel_groups(int nb, bool pf = false) {
   return std::min<int64_t>(kMaxPanelG, (int64_t)panel_wgs_per_cu(nb, pf) * device_info().num_cus);
 }
 
-// Panel width for order n: SKF_NB override, else the tuning table's entry,
-// else the widest of 128, 64, 32, 16 whose workgroups fit on the device; an
-// infeasible choice falls through to the next rule.  -1: no width fits.
+// Panel width for order n: SKF_NB override, else the tuning table's entry
+// (256 only from there: its one-per-CU panel is not always the faster), else the
+// widest of 128, 64, 32, 16 whose workgroups fit on the device; an infeasible
+// choice falls through to the next rule.  -1: no width fits.
 static int plan_nb(int64_t n, int param) {
   const int64_t g0 = std::max<int64_t>(1, (n - 1 + slots() - 1) / slots());
   const bool pf = param == SKF_TUNE_PFONLY_NB;
-  auto fits = [&](int nb) { return (nb == 128 || nb == 64 || nb == 32 || nb == 16) && g0 <= max_panel_groups(nb, pf); };
+  auto fits = [&](int nb) {
+    return (nb == 256 || nb == 128 || nb == 64 || nb == 32 || nb == 16) && g0 <= max_panel_groups(nb, pf);
+  };
   if (const char* e = getenv("SKF_NB")) {
     const int want = atoi(e);
     if (fits(want)) return want;
@@ -97,7 +100,7 @@ size_t ltlt_workspace_bytes(int64_t n, int prec) {
   if (ltlt_plan_nb(n) < 0 && pfonly_plan_nb(n) < 0) return 0;
   const int64_t g0 = std::max<int64_t>(1, (n - 1 + slots() - 1) / slots());
   size_t b = 0;
-  for (int nb : {16, 32, 64, 128}) {
+  for (int nb : {16, 32, 64, 128, 256}) {
     if (g0 > max_panel_groups(nb, false) && g0 > max_panel_groups(nb, true)) continue;
     LtltWork w;
     b = std::max(b, carve(&w, nullptr, n, nb));

@@ -77,7 +77,7 @@ __global__ void __launch_bounds__(kPanelThreads) panel_kernel(PanelParams P) {
   for (int q = 0; q < NP; ++q) {
     sm.LW[q][lane] = make_double2(0.0, 0.0);
   }
-  if (lane < NP) sm.coef[lane] = make_double2(0.0, 0.0);
+  for (int q = lane; q < NP; q += 64) sm.coef[q] = make_double2(0.0, 0.0);
   // l of each pair's first step, per slot, kept in global scratch (slot-major,
   // one coalesced line per pair) rather than LDS, so two workgroups of the
   // widest panel fit one CU
@@ -241,26 +241,29 @@ __global__ void __launch_bounds__(kPanelThreads) panel_kernel(PanelParams P) {
     // row's coefficients and l0
     const bool lowr = (int64_t)hbm > hx;
     const double graw = src[lowr ? (int64_t)hbm + hx * ld : hx + (int64_t)hbm * ld];
-    // lane t holds coefficient d = t (and d = t + 64): d = 2q -> l'[q], d = 2q+1 -> w[q]
+    // lane t holds coefficients d = t + 64 c (c < CPL): d = 2q -> l'[q], d = 2q+1 -> w[q]
     double l0 = 0.0;
     {
-      constexpr bool kTwo = 2 * NP > 64;  // coefficients 64.. exist (nb = 128)
+      constexpr int CPL = (2 * NP + 63) / 64;  // coefficients per lane
       const uint64_t* wm = P.mirror + ((size_t)gs * 64 + wslot) * NP * 4;
       const int nd = 2 * j;
-      const uint32_t tA = P.tag_base + 2u * (uint32_t)(lane >> 1) + 2u;
-      const uint32_t tB = P.tag_base + 2u * (uint32_t)((lane + 64) >> 1) + 2u;
-      const bool hasA = lane < nd, hasB = kTwo && lane + 64 < nd;
-      const int ia = 2 * lane, ib = kTwo ? 2 * (lane + 64) : 2 * lane;
+      uint32_t tc[CPL];
+      bool has[CPL];
+      int ic[CPL];
+#pragma unroll
+      for (int c = 0; c < CPL; ++c) {
+        const int d = lane + 64 * c;
+        tc[c] = P.tag_base + 2u * (uint32_t)(d >> 1) + 2u;
+        has[c] = d < nd;
+        ic[c] = (d < 2 * NP) ? 2 * d : 0;  // a valid address for every lane
+      }
       const uint64_t* lwp = lzs + 2 * ((size_t)(g % kRecCopies) * G + gs);
-      uint64_t a0, a1, b0, b1, z0, z1;
+      uint64_t cw[CPL][2], z0, z1;
       auto load_all = [&]() {
-        a0 = ld_word(wm + ia);
-        a1 = ld_word(wm + ia + 1);
-        if constexpr (kTwo) {
-          b0 = ld_word(wm + ib);
-          b1 = ld_word(wm + ib + 1);
-        } else {
-          b0 = b1 = 0;
+#pragma unroll
+        for (int c = 0; c < CPL; ++c) {
+          cw[c][0] = ld_word(wm + ic[c]);
+          cw[c][1] = ld_word(wm + ic[c] + 1);
         }
         z0 = ld_word(lwp);
         z1 = ld_word(lwp + 1);
@@ -279,9 +282,9 @@ __global__ void __launch_bounds__(kPanelThreads) panel_kernel(PanelParams P) {
       }
       uint64_t t0 = 0;
       for (int it = 0;; ++it) {
-        const bool ok = (!hasA | ((tag_of(a0) == tA) & (tag_of(a1) == tA))) &
-                        (!hasB | ((tag_of(b0) == tB) & (tag_of(b1) == tB))) & (tag_of(z0) == tag) &
-                        (tag_of(z1) == tag);
+        bool ok = (tag_of(z0) == tag) & (tag_of(z1) == tag);
+#pragma unroll
+        for (int c = 0; c < CPL; ++c) ok &= !has[c] | ((tag_of(cw[c][0]) == tc[c]) & (tag_of(cw[c][1]) == tc[c]));
         if (__all(ok)) break;
         poll_refresh<(NQ > 16)>(it);
         if ((it & 31) == 0) {
@@ -294,15 +297,18 @@ __global__ void __launch_bounds__(kPanelThreads) panel_kernel(PanelParams P) {
         }
         load_all();
       }
-      landed(a0);
-      landed(a1);
-      landed(b0);
-      landed(b1);
+#pragma unroll
+      for (int c = 0; c < CPL; ++c) {
+        landed(cw[c][0]);
+        landed(cw[c][1]);
+      }
       landed(z0);
       landed(z1);
       // coefficient d sits in component d % 2 of pair d / 2
-      if (hasA) reinterpret_cast<double*>(&sm.coef[0])[lane] = from32((uint32_t)a0, (uint32_t)a1);
-      if (hasB) reinterpret_cast<double*>(&sm.coef[0])[lane + 64] = from32((uint32_t)b0, (uint32_t)b1);
+#pragma unroll
+      for (int c = 0; c < CPL; ++c)
+        if (has[c])
+          reinterpret_cast<double*>(&sm.coef[0])[lane + 64 * c] = from32((uint32_t)cw[c][0], (uint32_t)cw[c][1]);
       l0 = from32((uint32_t)z0, (uint32_t)z1);
       // form l0 in its own registers here, while the coefficient loads are
       // known to have landed: formed lazily at its use after this step's
@@ -442,9 +448,9 @@ __global__ void __launch_bounds__(kPanelThreads) panel_pf_kernel(PanelParams P) 
   uint64_t* const my_mirror = P.mirror + ((size_t)g * 64 + lane) * NP * 4;
 
   for (int q = 0; q < NP; ++q) sm.LW[q][lane] = make_double2(0.0, 0.0);
-  if (lane < NP) {
-    sm.cx[lane] = make_double2(0.0, 0.0);
-    sm.cy[lane] = make_double2(0.0, 0.0);
+  for (int q = lane; q < NP; q += 64) {
+    sm.cx[q] = make_double2(0.0, 0.0);
+    sm.cy[q] = make_double2(0.0, 0.0);
   }
 
   int32_t psi = mine ? (int32_t)(rowbase + lane) : INT32_MAX;
@@ -625,36 +631,38 @@ __global__ void __launch_bounds__(kPanelThreads) panel_pf_kernel(PanelParams P) 
     const double gry = src[lowy ? (int64_t)hbm + hy * ld : hy + (int64_t)hbm * ld];
     const double gyx = src[lowyx ? hy + hx * ld : hx + hy * ld];
     {
-      constexpr bool kTwo = 2 * NP > 64;
+      constexpr int CPL = (2 * NP + 63) / 64;  // coefficients per lane: d = lane + 64 c
       const uint64_t* wx = P.mirror + ((size_t)gs * 64 + wslot) * NP * 4;
       const uint64_t* wy = P.mirror + ((size_t)ygs * 64 + yslot) * NP * 4;
       const int nd = 2 * si;
-      const uint32_t tA = P.tag_base + (uint32_t)(lane >> 1) + 1u;
-      const uint32_t tB = P.tag_base + (uint32_t)((lane + 64) >> 1) + 1u;
-      const bool hasA = lane < nd, hasB = kTwo && lane + 64 < nd;
-      const int ia = 2 * lane, ib = kTwo ? 2 * (lane + 64) : 2 * lane;
-      uint64_t xa0, xa1, xb0, xb1, ya0, ya1, yb0, yb1;
+      uint32_t tc[CPL];
+      bool has[CPL];
+      int ic[CPL];
+#pragma unroll
+      for (int c = 0; c < CPL; ++c) {
+        const int d = lane + 64 * c;
+        tc[c] = P.tag_base + (uint32_t)(d >> 1) + 1u;
+        has[c] = d < nd;
+        ic[c] = (d < 2 * NP) ? 2 * d : 0;  // a valid address for every lane
+      }
+      uint64_t xw[CPL][2], yw[CPL][2];
       auto load_coef = [&]() {
-        xa0 = ld_word(wx + ia);
-        xa1 = ld_word(wx + ia + 1);
-        ya0 = ld_word(wy + ia);
-        ya1 = ld_word(wy + ia + 1);
-        if constexpr (kTwo) {
-          xb0 = ld_word(wx + ib);
-          xb1 = ld_word(wx + ib + 1);
-          yb0 = ld_word(wy + ib);
-          yb1 = ld_word(wy + ib + 1);
-        } else {
-          xb0 = xb1 = yb0 = yb1 = 0;
+#pragma unroll
+        for (int c = 0; c < CPL; ++c) {
+          xw[c][0] = ld_word(wx + ic[c]);
+          xw[c][1] = ld_word(wx + ic[c] + 1);
+          yw[c][0] = ld_word(wy + ic[c]);
+          yw[c][1] = ld_word(wy + ic[c] + 1);
         }
       };
       load_coef();
       uint64_t t0 = 0;
       for (int it = 0;; ++it) {
-        const bool ok = (!hasA | ((tag_of(xa0) == tA) & (tag_of(xa1) == tA) & (tag_of(ya0) == tA) &
-                                  (tag_of(ya1) == tA))) &
-                        (!hasB | ((tag_of(xb0) == tB) & (tag_of(xb1) == tB) & (tag_of(yb0) == tB) &
-                                  (tag_of(yb1) == tB)));
+        bool ok = true;
+#pragma unroll
+        for (int c = 0; c < CPL; ++c)
+          ok &= !has[c] | ((tag_of(xw[c][0]) == tc[c]) & (tag_of(xw[c][1]) == tc[c]) & (tag_of(yw[c][0]) == tc[c]) &
+                           (tag_of(yw[c][1]) == tc[c]));
         if (__all(ok)) break;
         poll_refresh<(NQ > 16)>(it);
         if ((it & 31) == 0) {
@@ -667,23 +675,20 @@ __global__ void __launch_bounds__(kPanelThreads) panel_pf_kernel(PanelParams P) 
         }
         load_coef();
       }
-      landed(xa0);
-      landed(xa1);
-      landed(xb0);
-      landed(xb1);
-      landed(ya0);
-      landed(ya1);
-      landed(yb0);
-      landed(yb1);
+#pragma unroll
+      for (int c = 0; c < CPL; ++c) {
+        landed(xw[c][0]);
+        landed(xw[c][1]);
+        landed(yw[c][0]);
+        landed(yw[c][1]);
+      }
       // coefficient d sits in component d % 2 of step d / 2
-      if (hasA) {
-        reinterpret_cast<double*>(&sm.cx[0])[lane] = from32((uint32_t)xa0, (uint32_t)xa1);
-        reinterpret_cast<double*>(&sm.cy[0])[lane] = from32((uint32_t)ya0, (uint32_t)ya1);
-      }
-      if (hasB) {
-        reinterpret_cast<double*>(&sm.cx[0])[lane + 64] = from32((uint32_t)xb0, (uint32_t)xb1);
-        reinterpret_cast<double*>(&sm.cy[0])[lane + 64] = from32((uint32_t)yb0, (uint32_t)yb1);
-      }
+#pragma unroll
+      for (int c = 0; c < CPL; ++c)
+        if (has[c]) {
+          reinterpret_cast<double*>(&sm.cx[0])[lane + 64 * c] = from32((uint32_t)xw[c][0], (uint32_t)xw[c][1]);
+          reinterpret_cast<double*>(&sm.cy[0])[lane + 64 * c] = from32((uint32_t)yw[c][0], (uint32_t)yw[c][1]);
+        }
       if (__any(tout)) {
         stop = 4;
         break;
@@ -770,6 +775,8 @@ int launch_panel(const PanelParams& p, hipStream_t s) {
   if (p.G > kMaxG || p.S > 64 || p.n >= (1 << 24)) return SKF_ENOTIMPL;
   const int nq = (p.G + 63) / 64;
   switch (p.nb) {
+    case 256: return nq <= 1 ? launch_panel_t<256, 1>(p, s) : nq <= 2 ? launch_panel_t<256, 2>(p, s)
+                     : nq <= 4 ? launch_panel_t<256, 4>(p, s) : SKF_ENOTIMPL;
     case 128: return nq <= 1 ? launch_panel_t<128, 1>(p, s) : nq <= 2 ? launch_panel_t<128, 2>(p, s)
                      : nq <= 4 ? launch_panel_t<128, 4>(p, s) : launch_panel_t<128, 8>(p, s);
     case 64: return nq <= 1 ? launch_panel_t<64, 1>(p, s) : nq <= 2 ? launch_panel_t<64, 2>(p, s)
@@ -786,6 +793,8 @@ int launch_panel_pf(const PanelParams& p, hipStream_t s) {
   if (p.G > kMaxG || p.S > 64 || p.n >= (1 << 24) || !p.front) return SKF_ENOTIMPL;
   const int nq = (p.G + 63) / 64;
   switch (p.nb) {
+    case 256: return nq <= 1 ? launch_panel_pf_t<256, 1>(p, s) : nq <= 2 ? launch_panel_pf_t<256, 2>(p, s)
+                     : nq <= 4 ? launch_panel_pf_t<256, 4>(p, s) : SKF_ENOTIMPL;
     case 128: return nq <= 1 ? launch_panel_pf_t<128, 1>(p, s) : nq <= 2 ? launch_panel_pf_t<128, 2>(p, s)
                      : nq <= 4 ? launch_panel_pf_t<128, 4>(p, s) : launch_panel_pf_t<128, 8>(p, s);
     case 64: return nq <= 1 ? launch_panel_pf_t<64, 1>(p, s) : nq <= 2 ? launch_panel_pf_t<64, 2>(p, s)
@@ -817,9 +826,9 @@ int panel_slots() { return 64; }
 // more than the rounded bound, 13 of 12416 bytes on a 160 KB CU, was measured
 // not to fit), and by kMaxPanelPerCu.  Cached per width.
 int panel_wgs_per_cu(int nb, bool pf) {
-  static int cache[2][5] = {{0}};
-  const int w = nb == 128 ? 0 : nb == 64 ? 1 : nb == 32 ? 2 : nb == 16 ? 3 : 4;
-  if (w == 4) return 0;
+  static int cache[2][6] = {{0}};
+  const int w = nb == 128 ? 0 : nb == 64 ? 1 : nb == 32 ? 2 : nb == 16 ? 3 : nb == 256 ? 4 : 5;
+  if (w == 5) return 0;
   int& c = cache[pf ? 1 : 0][w];
   if (c) return c;
   const void* k = nullptr;
@@ -827,7 +836,8 @@ int panel_wgs_per_cu(int nb, bool pf) {
     case 0: k = pf ? (const void*)panel_pf_kernel<128, 8> : (const void*)panel_kernel<128, 8>; break;
     case 1: k = pf ? (const void*)panel_pf_kernel<64, 16> : (const void*)panel_kernel<64, 16>; break;
     case 2: k = pf ? (const void*)panel_pf_kernel<32, 32> : (const void*)panel_kernel<32, 32>; break;
-    default: k = pf ? (const void*)panel_pf_kernel<16, 32> : (const void*)panel_kernel<16, 32>; break;
+    case 3: k = pf ? (const void*)panel_pf_kernel<16, 32> : (const void*)panel_kernel<16, 32>; break;
+    default: k = pf ? (const void*)panel_pf_kernel<256, 4> : (const void*)panel_kernel<256, 4>; break;
   }
   const size_t lds = pf ? sizeof(PanelPfSmem<128>) * nb / 128 : sizeof(PanelSmem<128>) * nb / 128;
   size_t lds_cu = 163840;

@@ -34,7 +34,7 @@ bool tune_value_ok(int param, int value) {
   switch (param) {
     case SKF_TUNE_LTLT_NB:
     case SKF_TUNE_PFONLY_NB:
-      return value == 16 || value == 32 || value == 64 || value == 128;
+      return value == 16 || value == 32 || value == 64 || value == 128 || value == 256;
     case SKF_TUNE_SKR2K_BAND:
       return value >= 1 && value <= 64;
 

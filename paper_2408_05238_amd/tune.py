@@ -85,7 +85,7 @@ def sweep(sizes=DEFAULT_SIZES, reps=3, band_n=16384, log=print):
         for param, call in (("ltlt_nb", skf.ltlt), ("pfonly_nb", skf.pfonly)):
             pid = skf.TUNE_PARAMS[param]
             res = {}
-            for nb in (64, 128):
+            for nb in (64, 128, 256):
                 lib.skf_tune_clear()
                 lib.skf_tune_set(pid, 0, N_MAX, nb)
                 if lib.skf_tune_get(pid, n) != nb:

@@ -1,6 +1,7 @@
 """Parity at the full benchmark sizes: n = 16384 FP64 with seeds 2, 3 and 4, in
 the launch configuration bench.py times (skf.ltlt, default block size), seed 2
-again with the narrow panel (nb = 64), and the n = 32768 matrix of the mixed
+again with the narrow panel (nb = 64) and the widest one (nb = 256, one panel
+workgroup per CU), and the n = 32768 matrix of the mixed
 precision workload (seed 5) at both widths: nb = 128 (512 panel workgroups, two
 per CU: the tuned choice) and nb = 64 (512 workgroups of the narrow panel).
 
@@ -53,7 +54,7 @@ def _apply_P(x, ipiv, transpose=False):
     return x
 
 
-CASES = [(N, 2, None), (N, 3, None), (N, 4, None), (N, 2, "64"), (32768, 5, None), (32768, 5, "64")]
+CASES = [(N, 2, None), (N, 3, None), (N, 4, None), (N, 2, "64"), (N, 2, "256"), (32768, 5, None), (32768, 5, "64")]
 
 
 @pytest.mark.parametrize("n,seed,nb", CASES, ids=[f"n{c[0]}-s{c[1]}-nb{c[2] or 'auto'}" for c in CASES])

@@ -233,7 +233,8 @@ def test_ltlt_repeatable(skf, gen):
 
 @pytest.mark.parametrize("n,nb", [(300, "64"), (777, "64"), (2048, "64"), (4500, "64"), (300, "128"),
                                   (2048, "128"), (4096, "128"), (300, "32"), (1000, "32"), (2048, "32"),
-                                  (777, "16"), (2048, "16")])
+                                  (777, "16"), (2048, "16"), (300, "256"), (777, "256"), (4096, "256"),
+                                  (6000, "256")])
 def test_ltlt_parity_nb(skf, oracle_mod, gen, n, nb, monkeypatch):
     """Each panel width forced, whatever the tuning table picks for n (the narrow
     panel is also the only one that fits beyond one CU's worth of slots per CU)."""

@@ -66,7 +66,7 @@ def test_pfonly_parity(skf, oracle_mod, gen, n):
 
 @pytest.mark.parametrize("n,nb", [(300, "64"), (778, "64"), (2048, "64"), (4500, "64"), (300, "128"),
                                   (2048, "128"), (4096, "128"), (300, "32"), (2048, "32"), (778, "16"),
-                                  (2048, "16")])
+                                  (2048, "16"), (300, "256"), (2048, "256"), (6000, "256")])
 def test_pfonly_parity_nb(skf, oracle_mod, gen, n, nb, monkeypatch):
     """Each panel width forced, whatever the tuning table picks for n."""
     monkeypatch.setenv("SKF_NB", nb)
@@ -164,14 +164,19 @@ def test_pfonly_n16384_against_stored_oracle(skf, seed):
     assert abs(la - float(g["logabs"])) <= LOGPF_TOL * max(1.0, abs(float(g["logabs"])))
 
 
-def test_pfonly_n16384_against_stored_pfonly_oracle(skf):
+@pytest.mark.parametrize("nb", [None, "256"])
+def test_pfonly_n16384_against_stored_pfonly_oracle(skf, nb, monkeypatch):
     """The launch configuration of skf_logpf at n = 16384 (panel_pf_kernel with
-    256 workgroups): interchanges bit for bit against the oracle's Pfaffian-only
-    mode (tests/golden/pfonly_n16384_s2.npz), every even pivot within its
-    per-entry bound, log|Pf| and sign."""
+    256 workgroups), and the same with the widest panel (nb = 256, one
+    workgroup per CU): interchanges bit for bit against the oracle's
+    Pfaffian-only mode (tests/golden/pfonly_n16384_s2.npz), every even pivot
+    within its per-entry bound, log|Pf| and sign."""
     import torch
     from paper_2408_05238_amd import inputs
     import oracle
+    if nb:
+        monkeypatch.setenv("SKF_NB", nb)
+    print(f"pfonly n=16384 nb={nb or 'auto'}", flush=True)
     N = 16384
     g = np.load(os.path.join(HERE, "golden", f"pfonly_n{N}_s2.npz"))
     A = inputs.skew_gaussian(N, 2, inputs.STREAM_A)

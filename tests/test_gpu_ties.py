@@ -25,7 +25,7 @@ def skf():
 
 
 CASES = [(300, 11, "128"), (1000, 12, "128"), (4096, 13, "128"), (1000, 14, "64"), (4500, 15, "64"),
-         (2000, 16, None), (1000, 17, "32"), (2000, 18, "16")]
+         (2000, 16, None), (1000, 17, "32"), (2000, 18, "16"), (4096, 19, "256")]
 
 
 @pytest.mark.parametrize("n,seed,nb", CASES, ids=[f"n{c[0]}-nb{c[2] or 'auto'}" for c in CASES])

@@ -61,6 +61,17 @@ def test_table_entries_and_precedence(skf, tmp_path):
     assert skf.tune_get("skr2k_band", 500) == 16
 
 
+def test_width_256_only_where_one_workgroup_per_cu_suffices(skf, tmp_path):
+    # 130 KB of LDS per panel workgroup: one per CU, 256 workgroups of 64 rows
+    skf.load_tuning(_write(tmp_path, [{"param": "ltlt_nb", "n_lo": 0, "n_hi": 10 ** 9, "value": 256},
+                                      {"param": "pfonly_nb", "n_lo": 0, "n_hi": 10 ** 9, "value": 256}]))
+    assert skf.tune_get("ltlt_nb", 16384) == 256
+    assert skf.tune_get("ltlt_nb", 16385) == 256
+    assert skf.tune_get("ltlt_nb", 16386) == 128      # 257 workgroups: the built-in rule
+    assert skf.tune_get("pfonly_nb", 16385) == 256
+    assert skf.tune_get("pfonly_nb", 20000) == 128
+
+
 def test_infeasible_entry_is_ignored_and_env_overrides(skf, tmp_path, monkeypatch):
     skf.load_tuning(_write(tmp_path, [{"param": "ltlt_nb", "n_lo": 0, "n_hi": 10 ** 9, "value": 128}]))
     assert skf.tune_get("ltlt_nb", 40000) == 64       # 625 workgroups of width 128 cannot be resident
@@ -74,7 +85,8 @@ def test_bad_entries_are_rejected(skf, tmp_path):
     assert lib.skf_tune_set(7, 0, 10, 64) == -1
     assert lib.skf_tune_set(0, -1, 10, 64) == -2
     assert lib.skf_tune_set(0, 10, 9, 64) == -3
-    assert lib.skf_tune_set(0, 0, 10, 256) == -4      # width 256 does not fit a CU's LDS
+    assert lib.skf_tune_set(0, 0, 10, 512) == -4      # no panel of width 512
+    assert lib.skf_tune_set(0, 0, 10, 256) == 0
     assert lib.skf_tune_set(2, 0, 10, 0) == -4
     assert lib.skf_tune_get(9, 100) == -1
     with pytest.raises(ValueError):
