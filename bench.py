@@ -117,6 +117,11 @@ def _device():
     return dev
 
 
+def _sig(v):
+    """Floats to 4 significant digits (error figures such as 1e-15 stay visible)."""
+    return float(f"{v:.4g}") if isinstance(v, float) else v
+
+
 def _line(metric, value, unit, ms_per_step, args, dtype, workload, higher=True, **extra):
     out = {"metric": metric, "value": value, "unit": unit, "n_gpus": 1, "steps": args.steps,
            "warmup": args.warmup, "ms_per_step": ms_per_step, "higher_is_better": higher, "scaling": "weak",
@@ -447,9 +452,9 @@ def bench_serve(args):
           round(st["mean_ms"], 3), args, "f64 / f32-trailing+refine",
           f"{count} Poisson requests, n log-uniform on [64,4096] (seed 8), 70% FP64 / 30% FP32+refine, "
           f"Pf:solve 50:50, 16 RHS, 64 GB budget", higher=False,
-          saturation={k: (round(v, 3) if isinstance(v, float) else v) for k, v in sat.items()},
+          saturation={k: _sig(v) for k, v in sat.items()},
           at_rate_hz=round(rate, 2),
-          serving={k: (round(v, 3) if isinstance(v, float) else v) for k, v in st.items()})
+          serving={k: _sig(v) for k, v in st.items()})
 
 
 def main():

@@ -18,12 +18,14 @@
 namespace skf {
 
 // The panel kernel is one wave per workgroup with 64 row slots; LDS holds the
-// (nb/2) x 64 pair vectors per workgroup (130 KB at nb = 256, 65 KB at 128,
-// 33 KB at 64, 17 KB at 32, 9 KB at 16), so a CU hosts one, two, four, six or
-// six of them (the LDS bound, the occupancy query and the cap of six per CU
-// decide).  Every workgroup of a panel launch must be resident together, so the
-// narrower widths carry larger orders: up to 256, 512, 1024 and 1536
-// workgroups of 64 rows on 256 CUs.
+// (nb/2) x 64 pair vectors per workgroup and, in the faster form, the
+// first-step multipliers (97 KB at nb = 128, 49 KB at 64, 24 KB at 32, 12 KB at
+// 16: one, three, six, six per CU); the other form keeps the multipliers in
+// global scratch (131 KB at 256, 66 KB at 128, 33 KB at 64: one, two, four per
+// CU), and a launch takes it only when its grid needs that residency (the
+// occupancy query and the cap of six per CU also apply).  Every workgroup of a
+// panel launch must be resident together, so the narrower widths carry larger
+// orders: up to 256, 512, 1024 and 1536 workgroups of 64 rows on 256 CUs.
 static constexpr int kMaxPanelG = 2048;
 
 static int slots() { return panel_slots(); }

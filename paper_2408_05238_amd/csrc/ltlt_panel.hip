@@ -45,16 +45,21 @@ using namespace panel;
 namespace {
 
 
-template <int NB>
+// LE: each slot's first-step multipliers l kept in LDS (the faster form) or,
+// when the grid needs more workgroups per CU than that footprint allows, in a
+// slot-major global scratch (one coalesced line per pair, stored with the
+// pair's mirror entries and read back by the same lane at the panel's end).
+template <int NB, bool LE>
 struct PanelSmem {
-  double2 LW[NB / 2][64];  // (l', w) of each pair, per slot
-  double2 coef[NB / 2];    // the pivot row's (l', w) of the pairs so far
+  double2 LW[NB / 2][64];        // (l', w) of each pair, per slot
+  double Le[LE ? NB / 2 : 1][64];  // l of each pair's first step, per slot (LE)
+  double2 coef[NB / 2];          // the pivot row's (l', w) of the pairs so far
 };
 
-template <int NB, int NQ>
+template <int NB, int NQ, bool LE>
 __global__ void __launch_bounds__(kPanelThreads) panel_kernel(PanelParams P) {
   constexpr int NP = NB / 2;
-  __shared__ PanelSmem<NB> sm;
+  __shared__ PanelSmem<NB, LE> sm;
 
   const int lane = threadIdx.x;
   const int g = blockIdx.x;
@@ -76,12 +81,10 @@ __global__ void __launch_bounds__(kPanelThreads) panel_kernel(PanelParams P) {
 
   for (int q = 0; q < NP; ++q) {
     sm.LW[q][lane] = make_double2(0.0, 0.0);
+    if constexpr (LE) sm.Le[q][lane] = 0.0;
   }
   for (int q = lane; q < NP; q += 64) sm.coef[q] = make_double2(0.0, 0.0);
-  // l of each pair's first step, per slot, kept in global scratch (slot-major,
-  // one coalesced line per pair) rather than LDS, so two workgroups of the
-  // widest panel fit one CU
-  double* const my_le = P.Lscr + (size_t)g * 64 + lane;
+  double* const my_le = P.Lscr + (size_t)g * 64 + lane;  // !LE: slot-major scratch
   const size_t le_stride = (size_t)G * 64;
 
   int32_t psi = mine ? (int32_t)(rowbase + lane) : INT32_MAX;
@@ -277,7 +280,10 @@ __global__ void __launch_bounds__(kPanelThreads) panel_kernel(PanelParams P) {
         if (psi >= k + 2) val = (alpha != 0.0) ? cur / alpha : 0.0;
         else if (psi == (int32_t)r) val = alpha;
         else wr = false;
-        if (wr && ph == 1) sm.LW[j][lane].x = val;
+        if (wr) {
+          if (ph == 1) sm.LW[j][lane].x = val;
+          else if constexpr (LE) sm.Le[j][lane] = val;
+        }
         if (ph == 0) lj = wr ? val : 0.0;
       }
       uint64_t t0 = 0;
@@ -357,7 +363,6 @@ __global__ void __launch_bounds__(kPanelThreads) panel_kernel(PanelParams P) {
     // finish the column
     if (ph == 0) {
       if (below) cur = gat + corr;
-      if (mine) my_le[(size_t)j * le_stride] = lj;
     } else {
       const double w = below ? gat + corr : 0.0;
       sm.LW[j][lane].y = w;
@@ -371,6 +376,7 @@ __global__ void __launch_bounds__(kPanelThreads) panel_kernel(PanelParams P) {
         st_word(m + 1, mk(mt, lo32(lp)));
         st_word(m + 2, mk(mt, hi32(w)));
         st_word(m + 3, mk(mt, lo32(w)));
+        if constexpr (!LE) my_le[(size_t)j * le_stride] = lj;  // beside the mirror stores
       }
     }
   }
@@ -385,8 +391,13 @@ __global__ void __launch_bounds__(kPanelThreads) panel_kernel(PanelParams P) {
   if (!mine) return;
   const int npairs = P.nsteps / 2;
   const int64_t lo = k0 + P.nsteps;
-  for (int c = 0; c < P.nsteps; ++c)
-    P.Lbuf[psi + (int64_t)c * n] = (c & 1) ? sm.LW[c >> 1][lane].x : my_le[(size_t)(c >> 1) * le_stride];
+  // !LE: an unpaired last step's l is still in lj (pairs store theirs at the pair's end)
+  for (int c = 0; c < P.nsteps; ++c) {
+    double le;
+    if constexpr (LE) le = sm.Le[c >> 1][lane];
+    else le = (c + 1 == P.nsteps) ? lj : my_le[(size_t)(c >> 1) * le_stride];
+    P.Lbuf[psi + (int64_t)c * n] = (c & 1) ? sm.LW[c >> 1][lane].x : le;
+  }
   // the pair vectors are the trailing update's operands; row lo is stored as
   // zero, so the update leaves column lo (the next panel's first column, taken
   // from cnext as it stands) without products
@@ -762,9 +773,9 @@ int launch_panel_pf_t(const PanelParams& p, hipStream_t s) {
   return 0;
 }
 
-template <int NB, int NQ>
+template <int NB, int NQ, bool LE>
 int launch_panel_t(const PanelParams& p, hipStream_t s) {
-  hipLaunchKernelGGL((panel_kernel<NB, NQ>), dim3(p.G), dim3(kPanelThreads), 0, s, p);
+  hipLaunchKernelGGL((panel_kernel<NB, NQ, LE>), dim3(p.G), dim3(kPanelThreads), 0, s, p);
   SKF_CHECK_LAUNCH("panel");
   return 0;
 }
@@ -774,17 +785,26 @@ int launch_panel_t(const PanelParams& p, hipStream_t s) {
 int launch_panel(const PanelParams& p, hipStream_t s) {
   if (p.G > kMaxG || p.S > 64 || p.n >= (1 << 24)) return SKF_ENOTIMPL;
   const int nq = (p.G + 63) / 64;
+  // multipliers in LDS whenever the grid fits at that footprint
+  const bool le = p.G <= panel_wgs_per_cu_form(p.nb, true) * device_info().num_cus;
   switch (p.nb) {
-    case 256: return nq <= 1 ? launch_panel_t<256, 1>(p, s) : nq <= 2 ? launch_panel_t<256, 2>(p, s)
-                     : nq <= 4 ? launch_panel_t<256, 4>(p, s) : SKF_ENOTIMPL;
-    case 128: return nq <= 1 ? launch_panel_t<128, 1>(p, s) : nq <= 2 ? launch_panel_t<128, 2>(p, s)
-                     : nq <= 4 ? launch_panel_t<128, 4>(p, s) : launch_panel_t<128, 8>(p, s);
-    case 64: return nq <= 1 ? launch_panel_t<64, 1>(p, s) : nq <= 2 ? launch_panel_t<64, 2>(p, s)
-                    : nq <= 4 ? launch_panel_t<64, 4>(p, s) : nq <= 8 ? launch_panel_t<64, 8>(p, s) : launch_panel_t<64, 16>(p, s);
-    case 32: return nq <= 2 ? launch_panel_t<32, 2>(p, s) : nq <= 8 ? launch_panel_t<32, 8>(p, s)
-                    : nq <= 16 ? launch_panel_t<32, 16>(p, s) : launch_panel_t<32, 32>(p, s);
-    case 16: return nq <= 2 ? launch_panel_t<16, 2>(p, s) : nq <= 8 ? launch_panel_t<16, 8>(p, s)
-                    : nq <= 16 ? launch_panel_t<16, 16>(p, s) : launch_panel_t<16, 32>(p, s);
+    case 256: return nq <= 1 ? launch_panel_t<256, 1, false>(p, s) : nq <= 2 ? launch_panel_t<256, 2, false>(p, s)
+                     : nq <= 4 ? launch_panel_t<256, 4, false>(p, s) : SKF_ENOTIMPL;
+    case 128:
+      if (le)
+        return nq <= 1 ? launch_panel_t<128, 1, true>(p, s) : nq <= 2 ? launch_panel_t<128, 2, true>(p, s)
+               : nq <= 4 ? launch_panel_t<128, 4, true>(p, s) : launch_panel_t<128, 8, true>(p, s);
+      return nq <= 4 ? launch_panel_t<128, 4, false>(p, s) : launch_panel_t<128, 8, false>(p, s);
+    case 64:
+      if (le)
+        return nq <= 1 ? launch_panel_t<64, 1, true>(p, s) : nq <= 2 ? launch_panel_t<64, 2, true>(p, s)
+               : nq <= 4 ? launch_panel_t<64, 4, true>(p, s) : nq <= 8 ? launch_panel_t<64, 8, true>(p, s)
+               : launch_panel_t<64, 16, true>(p, s);
+      return nq <= 8 ? launch_panel_t<64, 8, false>(p, s) : launch_panel_t<64, 16, false>(p, s);
+    case 32: return nq <= 2 ? launch_panel_t<32, 2, true>(p, s) : nq <= 8 ? launch_panel_t<32, 8, true>(p, s)
+                    : nq <= 16 ? launch_panel_t<32, 16, true>(p, s) : launch_panel_t<32, 32, true>(p, s);
+    case 16: return nq <= 2 ? launch_panel_t<16, 2, true>(p, s) : nq <= 8 ? launch_panel_t<16, 8, true>(p, s)
+                    : nq <= 16 ? launch_panel_t<16, 16, true>(p, s) : launch_panel_t<16, 32, true>(p, s);
     default: return SKF_ENOTIMPL;
   }
 }
@@ -819,34 +839,44 @@ size_t panel_mirror_words(int G, int nb) { return (size_t)G * 64 * (nb / 2) * 4;
 
 int panel_slots() { return 64; }
 
-// Panel workgroups that may share one CU for width nb (the full or the
-// Pfaffian-only panel): the occupancy of its largest record-pass instantiation
-// (registers and wave slots), capped by the LDS it holds rounded up to 1 KB per
-// workgroup (the occupancy query counts the exact byte size, and one workgroup
-// more than the rounded bound, 13 of 12416 bytes on a 160 KB CU, was measured
-// not to fit), and by kMaxPanelPerCu.  Cached per width.
-int panel_wgs_per_cu(int nb, bool pf) {
-  static int cache[2][6] = {{0}};
+// Panel workgroups that may share one CU for width nb, per kernel form (the
+// full panel with its multipliers in LDS or in scratch, or the Pfaffian-only
+// panel): the occupancy of its largest record-pass instantiation (registers
+// and wave slots), capped by the LDS it holds rounded up to 1 KB per workgroup
+// (the occupancy query counts the exact byte size, and one workgroup more than
+// the rounded bound, 13 of 12416 bytes on a 160 KB CU, was measured not to
+// fit), and by kMaxPanelPerCu; 0 for a form that is not built.  Cached.
+static int wgs_per_cu(int nb, int form) {  // form 0: full, LE; 1: full, scratch; 2: Pfaffian-only
+  static int cache[3][6] = {{0}};
   const int w = nb == 128 ? 0 : nb == 64 ? 1 : nb == 32 ? 2 : nb == 16 ? 3 : nb == 256 ? 4 : 5;
   if (w == 5) return 0;
-  int& c = cache[pf ? 1 : 0][w];
+  if (form == 0 && w == 4) return 0;       // 256 with l in LDS: beyond a CU's LDS
+  if (form == 1 && (w == 2 || w == 3)) return 0;  // 32, 16: the LDS form already reaches the cap
+  int& c = cache[form][w];
   if (c) return c;
   const void* k = nullptr;
-  switch (w) {
-    case 0: k = pf ? (const void*)panel_pf_kernel<128, 8> : (const void*)panel_kernel<128, 8>; break;
-    case 1: k = pf ? (const void*)panel_pf_kernel<64, 16> : (const void*)panel_kernel<64, 16>; break;
-    case 2: k = pf ? (const void*)panel_pf_kernel<32, 32> : (const void*)panel_kernel<32, 32>; break;
-    case 3: k = pf ? (const void*)panel_pf_kernel<16, 32> : (const void*)panel_kernel<16, 32>; break;
-    default: k = pf ? (const void*)panel_pf_kernel<256, 4> : (const void*)panel_kernel<256, 4>; break;
+  size_t lds = 0;
+  switch (form * 8 + w) {
+    case 0: k = (const void*)panel_kernel<128, 8, true>; lds = sizeof(PanelSmem<128, true>); break;
+    case 1: k = (const void*)panel_kernel<64, 16, true>; lds = sizeof(PanelSmem<64, true>); break;
+    case 2: k = (const void*)panel_kernel<32, 32, true>; lds = sizeof(PanelSmem<32, true>); break;
+    case 3: k = (const void*)panel_kernel<16, 32, true>; lds = sizeof(PanelSmem<16, true>); break;
+    case 8: k = (const void*)panel_kernel<128, 8, false>; lds = sizeof(PanelSmem<128, false>); break;
+    case 9: k = (const void*)panel_kernel<64, 16, false>; lds = sizeof(PanelSmem<64, false>); break;
+    case 12: k = (const void*)panel_kernel<256, 4, false>; lds = sizeof(PanelSmem<256, false>); break;
+    case 16: k = (const void*)panel_pf_kernel<128, 8>; lds = sizeof(PanelPfSmem<128>); break;
+    case 17: k = (const void*)panel_pf_kernel<64, 16>; lds = sizeof(PanelPfSmem<64>); break;
+    case 18: k = (const void*)panel_pf_kernel<32, 32>; lds = sizeof(PanelPfSmem<32>); break;
+    case 19: k = (const void*)panel_pf_kernel<16, 32>; lds = sizeof(PanelPfSmem<16>); break;
+    default: k = (const void*)panel_pf_kernel<256, 4>; lds = sizeof(PanelPfSmem<256>); break;
   }
-  const size_t lds = pf ? sizeof(PanelPfSmem<128>) * nb / 128 : sizeof(PanelSmem<128>) * nb / 128;
   size_t lds_cu = 163840;
   int dev = 0, v = 0;
   if (hipGetDevice(&dev) == hipSuccess &&
       hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerMultiprocessor, dev) == hipSuccess && v > 0)
     lds_cu = (size_t)v;
   (void)hipGetLastError();
-  const int by_lds = (int)std::max<size_t>(1, lds_cu / align_up(lds, 1024));
+  const int by_lds = (int)(lds_cu / align_up(lds, 1024));
   int b = 0;
   if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&b, k, kPanelThreads, 0) != hipSuccess || b < 1) {
     // no device to ask (host-only use of the planner): the LDS bound alone
@@ -855,6 +885,14 @@ int panel_wgs_per_cu(int nb, bool pf) {
   }
   c = std::min(std::min(b, by_lds), kMaxPanelPerCu);
   return c;
+}
+
+int panel_wgs_per_cu_form(int nb, bool le) { return wgs_per_cu(nb, le ? 0 : 1); }
+
+// The most panel workgroups per CU any form of the panel reaches at width nb.
+int panel_wgs_per_cu(int nb, bool pf) {
+  if (pf) return wgs_per_cu(nb, 2);
+  return std::max(wgs_per_cu(nb, 0), wgs_per_cu(nb, 1));
 }
 
 size_t panel_scratch_doubles(int G, int nb) { return (size_t)(nb / 2) * G * 64; }

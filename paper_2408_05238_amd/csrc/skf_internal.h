@@ -170,6 +170,7 @@ int launch_panel(const PanelParams& p, hipStream_t s);
 int launch_panel_pf(const PanelParams& p, hipStream_t s);
 int panel_slots();
 int panel_wgs_per_cu(int nb, bool pf);
+int panel_wgs_per_cu_form(int nb, bool le);  // the full panel with its multipliers in LDS (le) or scratch
 size_t panel_record_words(int G);
 size_t panel_mirror_words(int G, int nb);
 size_t panel_scratch_doubles(int G, int nb);
