@@ -254,9 +254,10 @@ size_t skf_ltlt_c128_workspace(skf_int n);
  * The elimination step of skf_ltlt at every k with the pivot the largest
  * |z|^2 = re^2 + im^2 below the diagonal of column k (lowest index on ties).
  * Blocked: panels of 64 steps (n up to 64 x 256 panel workgroups on 256 CUs,
- * i.e. 16385) or 32 steps (up to 32769), each a persistent kernel on the real
- * and imaginary planes, its pairs (l, v) applied as one real skew rank-2k update
- * per plane on the matrix cores; beyond, SKF_ENOTIMPL.
+ * i.e. 16385), 32 steps (up to 32769) or 16 steps (up to 65537), each a
+ * persistent kernel on the real and imaginary planes, its pairs (l, v) applied
+ * as one real skew rank-2k update per plane on the matrix cores; beyond,
+ * SKF_ENOTIMPL.
  *   A      device, lda x n complex128 (interleaved re, im), strict lower triangle
  *          read; on exit as skf_ltlt's A: L[i,j] (i > j >= 1) at A[i, j-1], the
  *          subdiagonal A[k+1,k] = T[k]

@@ -792,6 +792,10 @@ int launch_cltlt(const CLtltParams& p, int nb, hipStream_t s) {
     if (nq <= 2) return launch_cltlt_t<32, 2>(p, s);
     if (nq <= 4) return launch_cltlt_t<32, 4>(p, s);
     if (nq <= 8) return launch_cltlt_t<32, 8>(p, s);
+  } else if (nb == 16) {
+    if (nq <= 2) return launch_cltlt_t<16, 2>(p, s);
+    if (nq <= 8) return launch_cltlt_t<16, 8>(p, s);
+    if (nq <= 16) return launch_cltlt_t<16, 16>(p, s);
   }
   return SKF_ENOTIMPL;
 }
@@ -889,14 +893,16 @@ CBWork cb_carve(void* base, int64_t n, int nb) {
 
 // Panel width (steps per panel) of the complex LTL^T for order n: 64 (134 KB
 // of LDS per workgroup, one per CU) when its workgroups fit on the device, else
-// 32 (two per CU), else 0.  SKF_NB=32 selects the narrow panel wherever it fits.
+// 32 (67 KB, two per CU), else 16 (34 KB, four per CU), else 0.  SKF_NB=32 or 16
+// selects that narrower panel wherever it fits.
 int clplan_nb(int64_t n) {
   const int64_t g0 = std::max<int64_t>(1, (n - 1 + kCSlots - 1) / kCSlots);
   const int64_t cus = device_info().num_cus;
   const char* e = getenv("SKF_NB");
-  const bool narrow = e && atoi(e) == 32;
-  if (!narrow && g0 <= std::min<int64_t>(256, cus)) return 64;
-  if (g0 <= std::min<int64_t>(512, 2 * cus)) return 32;
+  const int want = e ? atoi(e) : 0;
+  if (want != 32 && want != 16 && g0 <= std::min<int64_t>(256, cus)) return 64;
+  if (want != 16 && g0 <= std::min<int64_t>(512, 2 * cus)) return 32;
+  if (g0 <= std::min<int64_t>(1024, 4 * cus)) return 16;
   return 0;
 }
 

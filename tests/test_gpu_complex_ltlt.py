@@ -4,11 +4,13 @@ numpy factorization and solve: interchanges bit for bit, T and every L entry
 within the summation-error bound of its magnitude sum, the subdiagonal of the
 output equal to T, log|Pf| and the phase against the oracle; real input gives
 the real factorization's interchanges; the solve against the oracle's solve
-with the same (GPU) factors and by its backward error with A.  Both panel widths
-(64 and, with SKF_NB=32, 32 steps per panel) are covered; at n = 4096 and 16384
-(no stored oracle result) the checks are properties: log|Pf| against the
-Pfaffian-only reduction (a different elimination order) and the solve's
-backward error."""
+with the same (GPU) factors and by its backward error with A.  Every panel
+width (64 and, with SKF_NB=32 or 16, 32 or 16 steps per panel) is covered; at
+n = 4096 and 16384 (no stored oracle result) the checks are properties: log|Pf|
+against the Pfaffian-only reduction (a different elimination order) and the
+solve's backward error; at n = 33000 (the width-16 panel's range, 516
+workgroups) real input against the real factorization's interchanges and the
+solve's backward error on complex input."""
 from __future__ import annotations
 
 import math
@@ -29,11 +31,11 @@ def skf():
     return s
 
 
-@pytest.fixture(params=["nb64", "nb32"])
+@pytest.fixture(params=["nb64", "nb32", "nb16"])
 def width(request, monkeypatch):
     monkeypatch.delenv("SKF_NB", raising=False)
-    if request.param == "nb32":
-        monkeypatch.setenv("SKF_NB", "32")
+    if request.param != "nb64":
+        monkeypatch.setenv("SKF_NB", request.param[2:])
     return request.param
 
 
@@ -171,3 +173,47 @@ def test_complex_ltlt_full_size_properties(skf, n, nb, monkeypatch):
     anorm = float((S.abs().sum(1) + S.abs().sum(0)).max())
     eta = (R.abs().amax(0) / (anorm * Xd.abs().amax(0) + torch.from_numpy(np.abs(B).max(0)).to(Xd.device))).max()
     assert float(eta) <= 1e-13, float(eta)
+
+
+def test_complex_ltlt_width16_range(skf, monkeypatch):
+    """n = 33000: beyond the 32-step panel's reach (516 panel workgroups, four
+    per CU with 16 steps per panel).  A real matrix as complex input gives the
+    real factorization's interchanges (T real, equal to the real T within the
+    two evaluations' rounding); complex input gives a solve with backward error
+    at most 1e-13."""
+    import torch
+    from paper_2408_05238_amd import inputs
+    monkeypatch.delenv("SKF_NB", raising=False)
+    n = 33000
+    assert skf.lib().skf_ltlt_c128_workspace(n) > 0
+    R = skf.to_device_colmajor(inputs.skew_gaussian(n, 3, inputs.STREAM_A))
+    C = R.to(torch.complex128)
+    print(f"complex ltlt n={n} real input", flush=True)
+    ipc, Tc, infc = skf.ltlt_c128(C)
+    del C
+    ipr, Tr, infr = skf.ltlt(R)
+    del R
+    assert infc == infr == 0
+    assert torch.equal(ipc, ipr)
+    assert float(Tc.imag.abs().max()) == 0.0
+    assert float(((Tc.real - Tr).abs() / Tr.abs().clamp_min(1e-300)).max()) <= 1e-9
+    del ipc, Tc, ipr, Tr
+    torch.cuda.empty_cache()
+    print(f"complex ltlt n={n} complex input", flush=True)
+    g = torch.Generator(device="cuda").manual_seed(11)
+    X = torch.randn(n, n, dtype=torch.complex128, device="cuda", generator=g)
+    S = torch.tril(X, -1)
+    del X
+    A = S.t().contiguous().t()   # column-major; only the strict lower triangle is read
+    ipiv, T, info = skf.ltlt_c128(A)
+    assert info == 0
+    B = torch.randn(n, 2, dtype=torch.complex128, device="cuda", generator=g)
+    Bc = B.t().contiguous().t()
+    Xs = Bc.clone().t().contiguous().t()
+    assert skf.solve_c128(A, ipiv, T, Xs) == 0
+    del A
+    R2 = (S @ Xs - S.t() @ Xs) - Bc
+    anorm = float((S.abs().sum(1) + S.abs().sum(0)).max())
+    eta = (R2.abs().amax(0) / (anorm * Xs.abs().amax(0) + Bc.abs().amax(0))).max()
+    print(f"complex ltlt n={n}: solve backward error {float(eta):.2e}", flush=True)
+    assert float(eta) <= 1e-13
