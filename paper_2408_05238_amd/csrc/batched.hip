@@ -60,12 +60,13 @@ struct Smem {
   int piv;
   double alpha, l0;
   double akk;  // Pfaffian-only form: A[k+2, k+1] before the step's interchange
-  int flag;
 };
 
 __device__ inline bool better(double a, int pa, double b, int pb) { return (a > b) || (a == b && pa < pb); }
 
-// block arg-max of (v, p) (larger v, then lower p); result broadcast
+// block arg-max of (v, p) (larger v, then lower p); result broadcast.  The
+// callers pass other barriers before the next call, so the per-wave slots need
+// no barrier of their own after they are read.
 __device__ inline void block_argmax(Smem& sm, double v, int p, double* ov, int* op) {
   for (int off = 32; off >= 1; off >>= 1) {
     const double v2 = __shfl_xor(v, off);
@@ -90,7 +91,6 @@ __device__ inline void block_argmax(Smem& sm, double v, int p, double* ov, int* 
     }
   *ov = bv;
   *op = bp;
-  __syncthreads();
 }
 
 // Delayed trailing update of a panel: A[i,jj] += sum_q (P_q[i] Q_q[jj] - Q_q[i] P_q[jj])
@@ -219,13 +219,12 @@ __global__ void __launch_bounds__(BT, kWgPerCu) batched_kernel(BatchArgs a) {
             }
           }
         }
-        if (tid == 0) sm.flag = 0;
-        __syncthreads();
-        if (nf) sm.flag = 1;
+        // a non-finite entry enters the arg-max as +inf (finite |c| never is)
+        if (nf) bv = INFINITY;
         double gv;
         int p;
         block_argmax(sm, bv, bp, &gv, &p);
-        if (sm.flag) {
+        if (gv == INFINITY) {
           status = SKF_ENONFINITE;
           break;
         }
@@ -464,13 +463,12 @@ __global__ void __launch_bounds__(BT, kWgPerCu) pfonly_kernel(BatchArgs a) {
               }
             }
           }
-          if (tid == 0) sm.flag = 0;
-          __syncthreads();
-          if (nf) sm.flag = 1;
+          // a non-finite entry enters the arg-max as +inf (finite |c| never is)
+          if (nf) bv = INFINITY;
           double gv;
           int p;
           block_argmax(sm, bv, bp, &gv, &p);
-          if (sm.flag) {
+          if (gv == INFINITY) {
             status = SKF_ENONFINITE;
             break;
           }

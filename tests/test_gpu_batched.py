@@ -68,6 +68,13 @@ def test_batched_logpf_only_and_nonfinite(skf, oracle_mod, gen):
     assert sg[0] == s_r and oracle_mod.isclose_log(la[0], la_r) <= 1e-12
     assert info[1] == skf.ENONFINITE
     assert sg[2] == 0 and la[2] == -np.inf
+    # the full factorization reports it too, for a NaN and for an infinity
+    for bad in (np.nan, np.inf):
+        mats_h[1][50, 3] = bad
+        mats = [skf.to_device_colmajor(A) for A in mats_h]
+        _, _, info_f, _, _ = skf.ltlt_batched(mats)
+        info_f = _host(info_f)
+        assert info_f[1] == skf.ENONFINITE and info_f[0] == 0, (bad, info_f)
 
 
 SOLVE_NS = [0, 1, 2, 3, 4, 6, 64, 65, 66, 100, 130, 257, 300, 511, 512]
