@@ -368,6 +368,9 @@ class Scheduler:
             "solve_berr_max": max(berr) if berr else float("nan"),
             "pf_logabs_rel_bound": PF_REL_BOUND,
             "errors_stated": sum(1 for r in res if r.err_kind),
+            # numerical outcomes other than 0 (a singular or odd-order input's
+            # info, SKF_ENONFINITE, SKF_ETIMEOUT), by code
+            "outcomes": {str(k): v for k, v in sorted(collections.Counter(r.info for r in res if r.info).items())},
         }
 
 
