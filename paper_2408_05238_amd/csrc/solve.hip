@@ -146,22 +146,39 @@ __global__ void inv_diag_kernel(int64_t n, const double* __restrict__ LT, int64_
 // multiplied, and lands in the other half of a double-buffered LDS tile.
 constexpr int kLdPerThread = BS * BS / NT;  // 16
 
-// acc[i][c] -= sum_j Lb[i][j] y[j][c] over the 64 x 16 block: thread (row i =
-// tid % 64, column group g = tid / 64) keeps four sums in registers; the y
-// reads are the same address across a wave (LDS broadcast).
+// Block products out = M y (M a 64 x 64 LDS block, y 64 x 16) on the FP64
+// matrix cores: wave w forms the 16 x 16 tile of rows 16w .. 16w+15 in sixteen
+// 16x16x4 steps (two accumulators, even and odd steps).  Lane l supplies
+// M[16w + l % 16][4s + l / 16] and y[4s + l / 16][l % 16] at step s and holds
+// out[16w + l / 16 + 4r][l % 16] in element r: two LDS reads per step and wave,
+// where one row and four columns per lane took twenty per eight inner terms —
+// the chain-critical product went from 2.2 us (LDS-bound) to a fraction.
+typedef double mf4 __attribute__((ext_vector_type(4)));
+
+__device__ inline mf4 tile_mm(const double (&M)[BS][BS + 1], const double (&y)[BS][RC + 1], int tid) {
+  static_assert(NT == 4 * 64 && BS == 64 && RC == 16, "four waves, one 16 x 16 tile each");
+  const int w = tid >> 6, l = tid & 63;
+  const int ra = 16 * w + (l & 15), kq = l >> 4, cb = l & 15;
+  mf4 e = {0.0, 0.0, 0.0, 0.0}, o = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+  for (int s2 = 0; s2 < BS / 4; s2 += 2) {
+    e = __builtin_amdgcn_mfma_f64_16x16x4f64(M[ra][4 * s2 + kq], y[4 * s2 + kq][cb], e, 0, 0, 0);
+    o = __builtin_amdgcn_mfma_f64_16x16x4f64(M[ra][4 * s2 + 4 + kq], y[4 * s2 + 4 + kq][cb], o, 0, 0, 0);
+  }
+  return e + o;
+}
+
+// The output (row, column) of element r of thread tid in tile_mm's layout.
+__device__ inline int tile_row(int tid, int r) { return 16 * (tid >> 6) + ((tid & 63) >> 4) + 4 * r; }
+__device__ inline int tile_col(int tid) { return tid & 15; }
+
+// acc -= Lb y over the 64 x 16 block (each thread its four outputs).
 __device__ inline void block_mv(const double (&Lb)[BS][BS + 1], const double (&y)[BS][RC + 1],
                                 double (&acc)[BS][RC + 1], int tid) {
-  static_assert(NT == BS * (RC / 4), "one thread per row and group of four columns");
-  const int i = tid % BS, g = tid / BS;
-  double s4[4] = {0.0, 0.0, 0.0, 0.0};
-#pragma unroll 8
-  for (int j = 0; j < BS; ++j) {
-    const double l = Lb[i][j];
+  const mf4 d = tile_mm(Lb, y, tid);
+  const int c = tile_col(tid);
 #pragma unroll
-    for (int q = 0; q < 4; ++q) s4[q] += l * y[j][4 * g + q];
-  }
-#pragma unroll
-  for (int q = 0; q < 4; ++q) acc[i][4 * g + q] -= s4[q];
+  for (int r = 0; r < 4; ++r) acc[tile_row(tid, r)][c] -= d[r];
 }
 
 // Fold blocks for the last term of each block's substitution: with Db and Lb
@@ -321,13 +338,9 @@ __global__ void __launch_bounds__(NT) trsv_kernel(int64_t n, const double* __res
     }
     if (!more) {
       __syncthreads();  // acc complete; Lb[buf] holds M_I
-      const int i = tid % BS, g = tid / BS;
-#pragma unroll 8
-      for (int j = 0; j < BS; ++j) {
-        const double l = Db[i][j];
+      const mf4 d = tile_mm(Db, acc, tid);
 #pragma unroll
-        for (int q = 0; q < 4; ++q) s4[q] += l * acc[j][4 * g + q];
-      }
+      for (int r = 0; r < 4; ++r) s4[r] = d[r];
     }
     {
       auto load_all = [&]() { load_y(J); };
@@ -358,13 +371,9 @@ __global__ void __launch_bounds__(NT) trsv_kernel(int64_t n, const double* __res
     __syncthreads();
     if (stop) break;
     if (!more) {
-      const int i = tid % BS, g = tid / BS;
-#pragma unroll 8
-      for (int j = 0; j < BS; ++j) {
-        const double l = Lb[buf][i][j];
+      const mf4 m = tile_mm(Lb[buf], yJ[buf], tid);
 #pragma unroll
-        for (int q = 0; q < 4; ++q) s4[q] -= l * yJ[buf][j][4 * g + q];
-      }
+      for (int r = 0; r < 4; ++r) s4[r] -= m[r];
       folded = true;
       break;
     }
@@ -385,24 +394,21 @@ __global__ void __launch_bounds__(NT) trsv_kernel(int64_t n, const double* __res
   }
   // Y_I = inv(L_II) acc  (forward)  or  inv(L_II)^T acc  (backward), unless folded above
   {
-    // thread (row i, column group g) forms four results; acc is read-only here
-    const int i = tid % BS, g = tid / BS;
+    // each thread its four results in tile_mm's layout; acc is read-only here
     if (!folded) {
-#pragma unroll 8
-      for (int j = 0; j < BS; ++j) {
-        const double l = Db[i][j];
+      const mf4 d = tile_mm(Db, acc, tid);
 #pragma unroll
-        for (int q = 0; q < 4; ++q) s4[q] += l * acc[j][4 * g + q];
-      }
+      for (int r = 0; r < 4; ++r) s4[r] = d[r];
     }
+    const int c = tile_col(tid);
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      const int c = 4 * g + q;
-      const uint64_t b = (uint64_t)__double_as_longlong(s4[q]);
+    for (int r = 0; r < 4; ++r) {
+      const int i = tile_row(tid, r);
+      const uint64_t b = (uint64_t)__double_as_longlong(s4[r]);
       uint64_t* pw = pub + 2 * (((size_t)I * RC + c) * BS + i);
       st_word(pw, tagged(tag, (uint32_t)(b >> 32)));
       st_word(pw + 1, tagged(tag, (uint32_t)b));
-      if (i < bs) Y[r0 + i + (int64_t)c * n] = s4[q];
+      if (i < bs) Y[r0 + i + (int64_t)c * n] = s4[r];
     }
   }
 }
