@@ -351,6 +351,11 @@ __global__ void __launch_bounds__(NT) trsv_kernel(int64_t n, const double* __res
         for (int q = 0; q < 4; ++q) ok &= ((uint32_t)(w[q][0] >> 32) == tag) & ((uint32_t)(w[q][1] >> 32) == tag);
         if (ok) break;
         poll_refresh(it);
+        // only the last blocks before a workgroup's own link are urgent: one
+        // waiting for a block two or more ahead of its chain neighbour's backs
+        // off between rounds (about 0.4 us), leaving the newest block's lines
+        // to the readers that need them first
+        if (idx + 2 < count) __builtin_amdgcn_s_sleep(16);
         if ((it & 31) == 0) {
           const uint64_t now = wall_clock64();
           if (it == 0) t0 = now;
