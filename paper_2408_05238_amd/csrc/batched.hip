@@ -1,7 +1,7 @@
 // Batched skew LTL^T + Pfaffian: many independent matrices (n <= 512) in ONE
 // persistent launch.
 //
-// Each 256-thread workgroup takes matrix indices from a device work queue
+// Each 512-thread workgroup takes matrix indices from a device work queue
 // (largest n first, so the long factorizations start early) and factors one
 // matrix at a time in its own storage, with no inter-workgroup communication:
 //   * interchanges are applied eagerly to the matrix (the O(n) row/column
@@ -27,10 +27,13 @@ namespace skf {
 namespace {
 
 constexpr int BR = 512;   // largest order handled per workgroup
-constexpr int BNP = 8;    // pairs per panel (nb = 16): LDS and registers fit two workgroups per CU
+constexpr int BNP = 8;    // pairs per panel (nb = 16): the LDS fits two workgroups per CU
 constexpr int kWgPerCu = 2;
-constexpr int BT = 256;   // threads
+constexpr int BT = 512;   // threads: one row per thread, two workgroups (16 waves) per CU
 constexpr int RPT = BR / BT;
+// two 512-thread workgroups per CU are four waves per SIMD: registers capped at
+// 128 per lane (the launch-bounds form alone let them grow to 161)
+constexpr int kWavesPerSimd = kWgPerCu * BT / 256;
 
 struct BatchArgs {
   int64_t batch;
@@ -171,7 +174,7 @@ __device__ inline void trailing_update(double* __restrict__ A, int64_t ld, int64
 // kFactors: also leave L in place (the Pfaffian-only form needs neither the
 // finished columns of L nor their row interchanges).
 template <bool kFactors>
-__global__ void __launch_bounds__(BT, kWgPerCu) batched_kernel(BatchArgs a) {
+__global__ void __launch_bounds__(BT) __attribute__((amdgpu_waves_per_eu(kWavesPerSimd, kWavesPerSimd))) batched_kernel(BatchArgs a) {
   __shared__ Smem sm;
   const int tid = threadIdx.x;
   for (;;) {
@@ -406,7 +409,7 @@ __global__ void __launch_bounds__(BT, kWgPerCu) batched_kernel(BatchArgs a) {
 // k+2 at one known place (row p), or replaces it by the old column k+1 (p =
 // k+2), which is patched in registers.  ipiv (if given) receives the
 // interchanges (even positions stay j), T the pivots at even k.
-__global__ void __launch_bounds__(BT, kWgPerCu) pfonly_kernel(BatchArgs a) {
+__global__ void __launch_bounds__(BT) __attribute__((amdgpu_waves_per_eu(kWavesPerSimd, kWavesPerSimd))) pfonly_kernel(BatchArgs a) {
   __shared__ Smem sm;
   const int tid = threadIdx.x;
   for (;;) {
