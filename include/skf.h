@@ -17,7 +17,9 @@
  * Storage conventions shared by all entry points (column-major, 0-based):
  *   - A is n x n with leading dimension lda >= max(1,n); ONLY the strict lower
  *     triangle is read.  The diagonal and the strict upper triangle are never
- *     read or written.
+ *     written and their values never used (the residual and solve kernels may
+ *     issue a discarded load of A[0,0] as a clamped address; NaN or Inf there
+ *     changes nothing).
  *   - On exit from a factorization, L[i,j] (i > j >= 1) is stored at A[i, j-1],
  *     the subdiagonal A[k+1,k] holds T[k], and T[k] is also written to T[].
  *   - ipiv[0] = 0; ipiv[j] = p >= j means rows/columns j and p were interchanged

@@ -130,7 +130,7 @@ __device__ inline void trailing_update(double* __restrict__ A, int64_t ld, int64
 #pragma unroll
     for (int t = 0; t < SW; ++t) {
       const int64_t jj = j0 + t;
-      v[t] = A[(row < n && jj < row) ? row + jj * ld : 0];
+      v[t] = A[(row < n && jj < row) ? row + jj * ld : 1];  // unused ones read A[1, 0], strictly lower
     }
   };
   int64_t x = tid;
@@ -443,13 +443,17 @@ __global__ void __launch_bounds__(BT) __attribute__((amdgpu_waves_per_eu(kWavesP
         for (int q = 0; q < np; ++q) {
           const int64_t k = k0 + 2 * q, rr = k + 1, x = k + 2;
           const bool last = x >= n;  // k = n-2: pivot only
-          // stored columns k+1 (rows > k+1) and k+2 (rows > k+2), before the pivot is known
+          // stored columns k+1 (rows > k+1) and k+2 (rows > k+2), before the pivot
+          // is known.  Every load here and below is issued unconditionally (an
+          // unused one reads A[1, 0]) and its value selected where it is used,
+          // so no wait for one load is placed before the next is issued.
           double oldr[RPT], colx[RPT];
           for (int r = 0; r < RPT; ++r) {
             const int i = tid + BT * r;
-            oldr[r] = (!last && i > rr && i < n) ? A[i + rr * ld] : 0.0;
-            colx[r] = (!last && i > x && i < n) ? A[i + x * ld] : 0.0;
-            if (!last && i == x) sm.akk = oldr[r];
+            const bool vr = !last && i > rr && i < n, vx = !last && i > x && i < n;
+            const double a0 = A[vr ? i + rr * ld : 1], a1 = A[vx ? i + x * ld : 1];
+            oldr[r] = vr ? a0 : 0.0;
+            colx[r] = vx ? a1 : 0.0;
           }
           // pivot over rows >= k+1
           double bv = -1.0;
@@ -476,27 +480,15 @@ __global__ void __launch_bounds__(BT) __attribute__((amdgpu_waves_per_eu(kWavesP
             break;
           }
           const double alpha = sm.cur[p];
-          // column k+1 after the interchange (rows > k+1), and the interchange in memory
-          double newc[RPT];
+          // column k+1 after the interchange (rows > k+1): row p left of the
+          // diagonal (negated), A[p, k+1] (negated) and column p below it; the
+          // sign and the p == k+1 case are applied where the value is used
+          double praw[RPT];
           for (int r = 0; r < RPT; ++r) {
             const int i = tid + BT * r;
-            double v = 0.0;
-            if (!last && i > rr && i < n) {
-              if (p != rr) v = (i < p) ? -A[p + (int64_t)i * ld] : (i == p ? -A[p + rr * ld] : A[i + (int64_t)p * ld]);
-              else v = oldr[r];
-            }
-            newc[r] = v;
-          }
-          if (!last && p != rr) {
-            for (int r = 0; r < RPT; ++r) {
-              const int i = tid + BT * r;
-              if (i > rr && i < n) {
-                const double old = oldr[r];
-                if (i < p) A[p + (int64_t)i * ld] = -old;
-                else if (i == p) A[p + rr * ld] = -old;
-                else A[i + (int64_t)p * ld] = old;
-              }
-            }
+            const bool vp = !last && p != rr && i > rr && i < n;
+            const int64_t at = (i < p) ? p + (int64_t)i * ld : (i == p ? p + rr * ld : i + (int64_t)p * ld);
+            praw[r] = A[vp ? at : 1];
           }
           // every thread has read alpha = cur[p] before rows r and p of the LDS
           // arrays are swapped: an LDS-only barrier (global stores stay in flight)
@@ -520,17 +512,38 @@ __global__ void __launch_bounds__(BT) __attribute__((amdgpu_waves_per_eu(kWavesP
           }
           __syncthreads();
           if (last) break;
-          // (l, v) of this step below row k+1: v = stored column k+1 + corrections
+          // (l, v) of this step below row k+1: v = stored column k+1 + corrections.
+          // The owner of row k+2 also leaves its stored A[k+2, k+1] for the next
+          // column here, not where it is loaded: that LDS write waits for the
+          // load, and before the arg-max barrier it would hold the whole
+          // workgroup for a second memory round trip per step.
           for (int r = 0; r < RPT; ++r) {
             const int i = tid + BT * r;
+            if (i == x) sm.akk = oldr[r];
             if (i > rr && i < n) {
               const double l = (alpha != 0.0) ? sm.cur[i] / alpha : 0.0;
+              const double newc = (p == rr) ? oldr[r] : (i <= p ? -praw[r] : praw[r]);
               double corr = 0.0;
               for (int qq = 0; qq < q; ++qq) {
                 const double2 u = sm.LW[qq][i], c = sm.LW[qq][rr];
                 corr += u.x * c.y - u.y * c.x;
               }
-              sm.LW[q][i] = make_double2(l, newc[r] + corr);
+              sm.LW[q][i] = make_double2(l, newc + corr);
+            }
+          }
+          // the interchange in memory: old column k+1 moves to row p / column p.
+          // Issued after the products above so that their wait (for the pivot
+          // row's loads) does not also wait for these stores; the next step's
+          // loads of these places come after two more barriers.
+          if (p != rr) {
+            for (int r = 0; r < RPT; ++r) {
+              const int i = tid + BT * r;
+              if (i > rr && i < n) {
+                const double old = oldr[r];
+                if (i < p) A[p + (int64_t)i * ld] = -old;
+                else if (i == p) A[p + rr * ld] = -old;
+                else A[i + (int64_t)p * ld] = old;
+              }
             }
           }
           __syncthreads();

@@ -206,3 +206,27 @@ def test_pfonly_batched_alone_equals_mixed_and_edges(skf, oracle_mod, gen):
         assert np.array_equal(_host(ip_1[0]), _host(ip_m[b]))
     assert sg_m[-2] == 0 and la_m[-2] == -np.inf and info_m[-2] > 0
     assert sg_m[-1] == int(np.sign(np.prod(d))) and abs(la_m[-1] - np.log(np.abs(d)).sum()) <= 1e-13 * 40
+
+
+def test_batched_uses_only_the_strict_lower_triangle(skf, gen):
+    """Both batched kernels give the same bits when the diagonal and the strict
+    upper triangle hold NaN, and leave those places unwritten."""
+    sizes = [2, 3, 34, 130, 300, 512]
+    clean = [gen.batch_matrix(n, 31, b) for b, n in enumerate(sizes)]
+    dirty = []
+    for A in clean:
+        D = A.copy()
+        D[np.triu_indices(A.shape[0])] = np.nan
+        dirty.append(D)
+    for run in (skf.pfonly_batched, skf.ltlt_batched):
+        mc = [skf.to_device_colmajor(A) for A in clean]
+        md = [skf.to_device_colmajor(A) for A in dirty]
+        rc, rd = run(mc), run(md)
+        for k in range(3):  # log|Pf|, sign, outcome
+            assert np.array_equal(_host(rc[k]), _host(rd[k]), equal_nan=True), (run.__name__, k)
+        for b, n in enumerate(sizes):
+            assert np.array_equal(_host(rc[3][b]), _host(rd[3][b])), (run.__name__, n)
+            assert np.array_equal(_host(rc[4][b]), _host(rd[4][b])), (run.__name__, n)
+            got = _host(md[b])
+            assert np.all(np.isnan(got[np.triu_indices(n)])), (run.__name__, n)
+            assert np.array_equal(np.tril(_host(mc[b]), -1), np.tril(got, -1)), (run.__name__, n)
