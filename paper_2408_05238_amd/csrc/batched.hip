@@ -207,6 +207,21 @@ __global__ void __launch_bounds__(BT) __attribute__((amdgpu_waves_per_eu(kWavesP
       for (int si = 0; si < nsteps; ++si) {
         const int64_t k = k0 + si, rr = k + 1;
         const int j = si >> 1, ph = si & 1;
+        // loads whose addresses do not depend on the pivot, issued before its
+        // search: the stored column r below r and row r of the finished columns
+        // of L.  Every load of the step is issued unconditionally (an unused one
+        // reads A[1, 0]) and selected where its value is used, so the step waits
+        // for memory once.
+        static_assert(BT >= BR, "one finished column per thread in the row swap");
+        double colr[RPT];
+        for (int r = 0; r < RPT; ++r) {
+          const int i = tid + BT * r;
+          const bool vr = i > rr && i < n;
+          const double a0 = A[vr ? i + rr * ld : 1];
+          colr[r] = vr ? a0 : 0.0;
+        }
+        const bool vc = kFactors && tid < k;
+        const double xr = A[vc ? rr + (int64_t)tid * ld : 1];
         // pivot over rows >= k+1
         double bv = -1.0;
         int bp = INT32_MAX;
@@ -234,29 +249,31 @@ __global__ void __launch_bounds__(BT) __attribute__((amdgpu_waves_per_eu(kWavesP
         const double alpha = sm.cur[p];
         // symmetric interchange r <-> p (lower storage) and the new column r below r:
         //   A[i,r] (i > r) := i < p ? -A[p,i] : (i == p ? -A[p,r] : A[i,p])
+        double praw[RPT];
+        for (int r = 0; r < RPT; ++r) {
+          const int i = tid + BT * r;
+          const bool vp = p != rr && i > rr && i < n;
+          const int64_t at = (i < p) ? p + (int64_t)i * ld : (i == p ? p + rr * ld : i + (int64_t)p * ld);
+          praw[r] = A[vp ? at : 1];
+        }
+        const bool vs = vc && p != rr;
+        const double yp = A[vs ? p + (int64_t)tid * ld : 1];
         double newc[RPT];
         for (int r = 0; r < RPT; ++r) {
           const int i = tid + BT * r;
-          double v = 0.0;
-          if (i > rr && i < n) {
-            if (p != rr) v = (i < p) ? -A[p + (int64_t)i * ld] : (i == p ? -A[p + rr * ld] : A[i + (int64_t)p * ld]);
-            else v = A[i + rr * ld];
-          }
-          newc[r] = v;
+          newc[r] = (i > rr && i < n) ? (p == rr ? colr[r] : (i <= p ? -praw[r] : praw[r])) : 0.0;
         }
         if (p != rr) {
           // row segments left of r (finished columns of L; column k is carried in cur)
-          if (kFactors)
-          for (int64_t c = tid; c < k; c += BT) {
-            const double x = A[rr + c * ld], y = A[p + c * ld];
-            A[rr + c * ld] = y;
-            A[p + c * ld] = x;
+          if (vs) {
+            A[rr + (int64_t)tid * ld] = yp;
+            A[p + (int64_t)tid * ld] = xr;
           }
           // column r below r vs row p / column p (old column r moves there)
           for (int r = 0; r < RPT; ++r) {
             const int i = tid + BT * r;
             if (i > rr && i < n) {
-              const double old = A[i + rr * ld];
+              const double old = colr[r];
               if (i < p) A[p + (int64_t)i * ld] = -old;
               else if (i == p) A[p + rr * ld] = -old;  // A[p,r] := -A[p,r]
               else A[i + (int64_t)p * ld] = old;
