@@ -102,8 +102,10 @@ __device__ inline void block_argmax(Smem& sm, double v, int p, double* ov, int* 
 // has the rows j0+1 .. n-1.  Items are numbered strip by strip and dealt to the
 // threads round-robin, so every thread gets the same number of items whatever
 // the triangle's shape, and consecutive threads take consecutive rows of a strip
-// (coalesced).  Each item's 4 elements are loaded (clamped addresses) before the
-// previous item is multiplied and stored.
+// (coalesced).  A thread locates its first item from its index (a quadratic
+// root) and each next one, BT items further, by walking on through the strips.
+// Each item's 4 elements are loaded (clamped addresses) before the previous item
+// is multiplied and stored.
 constexpr int kStrip = 4;
 
 __device__ inline void trailing_update(double* __restrict__ A, int64_t ld, int64_t n, int64_t c1, int npairs,
@@ -126,6 +128,22 @@ __device__ inline void trailing_update(double* __restrict__ A, int64_t ld, int64
     *j0 = c1 + SW * st;
     *row = *j0 + 1 + (x - P(st));
   };
+  // the item BT further on: the rest of this strip, then whole strips (the
+  // caller guarantees that it exists, so the walk ends inside the triangle)
+  auto advance = [&](int64_t* j0, int64_t* row) {
+    int64_t m = BT;
+    while (*j0 < n) {
+      const int64_t left = n - 1 - *row;  // items after this one in its strip
+      if (m <= left) {
+        *row += m;
+        return;
+      }
+      m -= left + 1;
+      *j0 += SW;
+      *row = *j0 + 1;
+    }
+    *j0 = *row = n - 1;  // not reached
+  };
   auto load = [&](int64_t j0, int64_t row, double (&v)[SW]) {
 #pragma unroll
     for (int t = 0; t < SW; ++t) {
@@ -143,7 +161,9 @@ __device__ inline void trailing_update(double* __restrict__ A, int64_t ld, int64
     const int64_t xn = x + BT;
     int64_t j0n = 0, rown = n;
     if (xn < total) {
-      locate(xn, &j0n, &rown);
+      j0n = j0;
+      rown = row;
+      advance(&j0n, &rown);
       load(j0n, rown, nxt);
     }
     double acc[SW];
