@@ -169,13 +169,15 @@ __device__ inline void trailing_update(double* __restrict__ A, int64_t ld, int64
     double acc[SW];
 #pragma unroll
     for (int t = 0; t < SW; ++t) acc[t] = 0.0;
+    // all of a pair's LDS operands are read before any is used (one LDS wait
+    // per pair, not one per column), two fused multiply-adds per product
     for (int q = 0; q < npairs; ++q) {
       const double2 u = LW[q][row];
+      double2 v[SW];
 #pragma unroll
-      for (int t = 0; t < SW; ++t) {
-        const double2 v = LW[q][min(j0 + t, (int64_t)BR - 1)];
-        acc[t] += u.x * v.y - u.y * v.x;
-      }
+      for (int t = 0; t < SW; ++t) v[t] = LW[q][min(j0 + t, (int64_t)BR - 1)];
+#pragma unroll
+      for (int t = 0; t < SW; ++t) acc[t] = fma(-u.y, v[t].x, fma(u.x, v[t].y, acc[t]));
     }
 #pragma unroll
     for (int t = 0; t < SW; ++t) {
