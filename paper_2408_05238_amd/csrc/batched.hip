@@ -65,6 +65,26 @@ struct Smem {
   double akk;  // Pfaffian-only form: A[k+2, k+1] before the step's interchange
 };
 
+// sum over the panel's pairs q < np of l'_q[i] w_q[c] - w_q[i] l'_q[c] (the
+// correction of entry (i, c) by the pairs so far).  Pairs are read four at a
+// time, all eight LDS operands issued before any is used; pairs np .. 4*ceil(np/4)-1
+// are the zero rows the panel start left, adding exactly nothing.
+__device__ inline double skew_dot(const double2 (&LW)[BNP][BR], int i, int64_t c, int np) {
+  static_assert(BNP % 4 == 0, "pairs are read in groups of four");
+  double s = 0.0;
+  for (int q0 = 0; q0 < np; q0 += 4) {
+    double2 u[4], w[4];
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+      u[t] = LW[q0 + t][i];
+      w[t] = LW[q0 + t][c];
+    }
+#pragma unroll
+    for (int t = 0; t < 4; ++t) s = fma(-u[t].y, w[t].x, fma(u[t].x, w[t].y, s));
+  }
+  return s;
+}
+
 __device__ inline bool better(double a, int pa, double b, int pb) { return (a > b) || (a == b && pa < pb); }
 
 // block arg-max of (v, p) (larger v, then lower p); result broadcast.  The
@@ -562,12 +582,7 @@ __global__ void __launch_bounds__(BT) __attribute__((amdgpu_waves_per_eu(kWavesP
             if (i > rr && i < n) {
               const double l = (alpha != 0.0) ? sm.cur[i] / alpha : 0.0;
               const double newc = (p == rr) ? oldr[r] : (i <= p ? -praw[r] : praw[r]);
-              double corr = 0.0;
-              for (int qq = 0; qq < q; ++qq) {
-                const double2 u = sm.LW[qq][i], c = sm.LW[qq][rr];
-                corr += u.x * c.y - u.y * c.x;
-              }
-              sm.LW[q][i] = make_double2(l, newc + corr);
+              sm.LW[q][i] = make_double2(l, newc + skew_dot(sm.LW, i, rr, q));
             }
           }
           // the interchange in memory: old column k+1 moves to row p / column p.
@@ -593,12 +608,7 @@ __global__ void __launch_bounds__(BT) __attribute__((amdgpu_waves_per_eu(kWavesP
             const int i = tid + BT * r;
             if (i > x && i < n) {
               const double st = (p == x) ? oldr[r] : (i == p ? -akk : colx[r]);
-              double corr = 0.0;
-              for (int qq = 0; qq <= q; ++qq) {
-                const double2 u = sm.LW[qq][i], c = sm.LW[qq][x];
-                corr += u.x * c.y - u.y * c.x;
-              }
-              sm.cur[i] = st + corr;
+              sm.cur[i] = st + skew_dot(sm.LW, i, x, q + 1);
             }
           }
           ++done;
