@@ -252,8 +252,8 @@ __global__ void __launch_bounds__(BT) __attribute__((amdgpu_waves_per_eu(kWavesP
         // loads whose addresses do not depend on the pivot, issued before its
         // search: the stored column r below r and row r of the finished columns
         // of L.  Every load of the step is issued unconditionally (an unused one
-        // reads A[1, 0]) and selected where its value is used, so the step waits
-        // for memory once.
+        // reads A[1, 0]) and selected where its value is used, so the loads that
+        // do not depend on the pivot overlap its search.
         static_assert(BT >= BR, "one finished column per thread in the row swap");
         double colr[RPT];
         for (int r = 0; r < RPT; ++r) {
